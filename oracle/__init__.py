@@ -1,0 +1,169 @@
+"""Python access to the CPU oracle of the fractional ABM scheme.
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the CPU-baseline leg
+of the benchmark load this; the GPU library never does.  The arithmetic lives
+in ``abm_oracle.c`` (plain C, FP64, weights from the literal formulas of
+Section 2 evaluated in __float128); this module only builds it with gcc and
+marshals arguments through ctypes.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "abm_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+
+# right-hand side ids used by the oracle (its own numbering)
+RHS_LINEAR, RHS_DUFFING, RHS_LORENZ, RHS_POLY, RHS_LCR = 0, 1, 2, 3, 4
+RHS_DIM = {RHS_LINEAR: 1, RHS_DUFFING: 2, RHS_LORENZ: 3, RHS_POLY: 1, RHS_LCR: 2}
+
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle into oracle/liboracle.so with gcc (-O2, OpenMP,
+    libquadmath, no FP contraction)."""
+    if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=gnu11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
+           _SRC, "-o", tmp, "-lquadmath", "-lm"]
+    subprocess.check_call(cmd)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build()
+    lib = ctypes.CDLL(_LIB)
+    c_dp = ctypes.POINTER(ctypes.c_double)
+    lib.oracle_weights.argtypes = [ctypes.c_double, ctypes.c_int64, c_dp, c_dp, c_dp]
+    lib.oracle_weights.restype = ctypes.c_int
+    lib.oracle_weights_at.argtypes = [ctypes.c_double, ctypes.c_int64, ctypes.c_int64, c_dp, c_dp,
+                                      c_dp]
+    lib.oracle_weights_at.restype = ctypes.c_int
+    lib.oracle_solve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_int64, c_dp, c_dp, ctypes.c_int64, c_dp, ctypes.c_int]
+    lib.oracle_solve.restype = ctypes.c_int
+    lib.oracle_steps_from_states.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                             ctypes.c_double, c_dp, c_dp, c_dp,
+                                             ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, c_dp]
+    lib.oracle_steps_from_states.restype = ctypes.c_int
+    lib.oracle_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ctypes.c_int32), c_dp, c_dp,
+                                       ctypes.POINTER(ctypes.c_int64), c_dp, c_dp, ctypes.c_int64,
+                                       ctypes.POINTER(c_dp), ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.c_int]
+    lib.oracle_solve_batch.restype = ctypes.c_int
+    lib.oracle_num_threads.argtypes = []
+    lib.oracle_num_threads.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def n_out(N: int, out_stride: int) -> int:
+    """Number of states written for a run of N steps at the given stride."""
+    if out_stride == 0:
+        return 1
+    return N // out_stride + 1 + (1 if N % out_stride else 0)
+
+
+def weights(alpha: float, n: int, k0: int = 0):
+    """b_k, a_k, c_k for k = k0..k0+n-1 (Section 2), as three float64 arrays."""
+    lib = _load()
+    b = np.zeros(n, np.float64)
+    a = np.zeros(n, np.float64)
+    c = np.zeros(n, np.float64)
+    rc = lib.oracle_weights_at(float(alpha), int(k0), int(n), _dp(b), _dp(a), _dp(c))
+    if rc != 0:
+        raise ValueError("oracle_weights failed: %d" % rc)
+    return b, a, c
+
+
+def _params(rhs, d, x0, p):
+    x = np.zeros(4, np.float64)
+    pp = np.zeros(8, np.float64)
+    x0 = np.asarray(x0, np.float64).ravel()
+    p = np.asarray(p, np.float64).ravel()
+    if x0.size != d or p.size > 8:
+        raise ValueError("bad x0/p size")
+    x[:d] = x0
+    pp[:p.size] = p
+    return x, pp
+
+
+def solve(rhs: int, alpha: float, h: float, N: int, x0, p, out_stride: int = 1,
+          compensated: bool = False) -> np.ndarray:
+    """One trajectory; returns the written states as an (n_out, d) array."""
+    lib = _load()
+    d = RHS_DIM[rhs]
+    x, pp = _params(rhs, d, x0, p)
+    y = np.zeros((n_out(N, out_stride), d), np.float64)
+    rc = lib.oracle_solve(rhs, d, float(alpha), float(h), int(N), _dp(x), _dp(pp),
+                          int(out_stride), _dp(y), 1 if compensated else 0)
+    if rc != 0:
+        raise ValueError("oracle_solve failed: %d" % rc)
+    return y
+
+
+def steps_from_states(rhs: int, alpha: float, h: float, x0, p, y_hist: np.ndarray,
+                      s_list) -> np.ndarray:
+    """y_s recomputed for each s in s_list from the given states y_0..y_{s-1}."""
+    lib = _load()
+    d = RHS_DIM[rhs]
+    x, pp = _params(rhs, d, x0, p)
+    s_arr = np.ascontiguousarray(np.asarray(s_list, np.int64))
+    yh = np.ascontiguousarray(np.asarray(y_hist, np.float64).reshape(-1, d))
+    if s_arr.size and (s_arr.min() < 1 or s_arr.max() > yh.shape[0]):
+        raise ValueError("s out of range of the given history")
+    out = np.zeros((s_arr.size, d), np.float64)
+    rc = lib.oracle_steps_from_states(rhs, d, float(alpha), float(h), _dp(x), _dp(pp), _dp(yh),
+                                      s_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                      int(s_arr.size), _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_steps_from_states failed: %d" % rc)
+    return out
+
+
+def solve_batch(rhs, alpha, h, N, x0, p, out_stride: int = 0, compensated: bool = False):
+    """Many independent trajectories (OpenMP over trajectories).  Every argument
+    is per trajectory (sequence of length B); returns a list of (n_out, d) arrays."""
+    lib = _load()
+    B = len(rhs)
+    rhs_a = np.asarray(rhs, np.int32)
+    d_a = np.asarray([RHS_DIM[int(r)] for r in rhs_a], np.int32)
+    al = np.asarray(alpha, np.float64)
+    hh = np.asarray(h, np.float64)
+    NN = np.asarray(N, np.int64)
+    xs = np.zeros((B, 4), np.float64)
+    ps = np.zeros((B, 8), np.float64)
+    for i in range(B):
+        xs[i], ps[i] = _params(int(rhs_a[i]), int(d_a[i]), x0[i], p[i])
+    outs = [np.zeros((n_out(int(NN[i]), out_stride), int(d_a[i])), np.float64) for i in range(B)]
+    ptrs = (ctypes.POINTER(ctypes.c_double) * max(B, 1))(*[_dp(o) for o in outs])
+    st = np.zeros(B, np.int32)
+    i32 = ctypes.POINTER(ctypes.c_int32)
+    rc = lib.oracle_solve_batch(B, rhs_a.ctypes.data_as(i32), d_a.ctypes.data_as(i32), _dp(al),
+                                _dp(hh), NN.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                _dp(xs), _dp(ps), int(out_stride), ptrs, st.ctypes.data_as(i32),
+                                1 if compensated else 0)
+    if rc != 0:
+        raise ValueError("oracle_solve_batch failed: %s" % st)
+    return outs
+
+
+def num_threads() -> int:
+    return int(_load().oracle_num_threads())

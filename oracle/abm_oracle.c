@@ -1,0 +1,308 @@
+/*
+ * Reference CPU oracle for the fractional Adams-Bashforth-Moulton (ABM)
+ * predictor-corrector (Bonchis, Kaslik, Rosu, "HPC optimal parallel
+ * communication algorithm for the simulation of fractional-order systems",
+ * arXiv 1710.01133).
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the slow, obviously-correct
+ * definition that the GPU library is checked against.  Only the test suite,
+ * the smoke check and the CPU-baseline leg of the benchmark may load it.  It
+ * shares no code, header, table or constant with the GPU library.
+ *
+ * What it computes (Section 2, "Preliminaries"):
+ *   problem      D^alpha y = f(t, y), y(0) = x0, 0 < alpha <= 1   (eq. fde)
+ *   grid         t_n = n h, f_n = f(t_n, y_n) with the corrected y_n
+ *   predictor    yP_{n+1} = x0 + h^alpha * sum_{k=0..n} b_{n-k} f_k      (eq. abm)
+ *   corrector    y_{n+1}  = x0 + h^alpha * ( c_n f_0 + sum_{k=1..n} a_{n-k} f_k
+ *                                            + f(t_{n+1}, yP_{n+1}) / Gamma(alpha+2) )
+ *   weights      b_n = ((n+1)^alpha - n^alpha) / Gamma(alpha+1)
+ *                a_n = ((n+2)^(alpha+1) - 2 (n+1)^(alpha+1) + n^(alpha+1)) / Gamma(alpha+2)
+ *                c_n = (n^(alpha+1) - (n-alpha)(n+1)^alpha) / Gamma(alpha+2)
+ * Readings taken where the text is garbled:
+ *   - b_n is printed with "+" between the two powers; the product-rectangle
+ *     rule it comes from needs "-" (the tests pin this by quadrature and by
+ *     the telescoping sum of b).
+ *   - exactly one corrector evaluation per step (PECE), f_n uses corrected y_n.
+ *   - systems are treated component-wise with one alpha for all components.
+ *
+ * Arithmetic: the weights are evaluated from the literal formulas in
+ * __float128 (113-bit significand), so the cancellation inside the
+ * differences of powers costs nothing visible, then rounded once to double.
+ * Gamma(alpha+1), Gamma(alpha+2) and h^alpha are taken in double (tgamma,
+ * pow).  History sums run in double, ascending k, plain or (optionally)
+ * Neumaier-compensated.
+ *
+ * Right-hand sides (a fixed set, numbered here on their own):
+ *   0 LINEAR   f = -lambda * y                          p = {lambda}
+ *   1 DUFFING  f = (y2, -delta y2 - y1 - y1^3 + A cos(omega t))   p = {delta, A, omega}
+ *   2 LORENZ   f = (s(y2-y1), y1(r-y3)-y2, y1 y2 - b y3)          p = {s, r, b}
+ *   3 POLY     f = c0 + c1 t (each component)            p = {c0, c1}
+ *   4 LCR      f = (y2 - g(y1), -sigma y2 - y1 + F sin(omega t))  (eq. sys.LRC,
+ *              one common order)   p = {sigma, omega, a, b, F}
+ *              g(x) = b x - a + b (x <= -1), a x (|x| < 1), b x + a - b (x >= 1)
+ */
+#include <math.h>
+#include <quadmath.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_OK 0
+#define ORC_EINVAL -1
+#define ORC_ENOMEM -2
+
+static int rhs_dim(int rhs)
+{
+    switch (rhs) {
+    case 0: return 1;
+    case 1: return 2;
+    case 2: return 3;
+    case 3: return 1;
+    case 4: return 2;
+    default: return -1;
+    }
+}
+
+/* Right-hand side f(t, y) for the fixed set above. */
+static void rhs_eval(int rhs, const double *p, double t, const double *y, double *f)
+{
+    switch (rhs) {
+    case 0:
+        f[0] = -p[0] * y[0];
+        break;
+    case 1:
+        f[0] = y[1];
+        f[1] = -p[0] * y[1] - y[0] - y[0] * y[0] * y[0] + p[1] * cos(p[2] * t);
+        break;
+    case 2:
+        f[0] = p[0] * (y[1] - y[0]);
+        f[1] = y[0] * (p[1] - y[2]) - y[1];
+        f[2] = y[0] * y[1] - p[2] * y[2];
+        break;
+    case 3:
+        f[0] = p[0] + p[1] * t;
+        break;
+    case 4: {
+        double x = y[0], g;
+        if (x <= -1.0)
+            g = p[3] * x - p[2] + p[3];
+        else if (x >= 1.0)
+            g = p[3] * x + p[2] - p[3];
+        else
+            g = p[2] * x;
+        f[0] = y[1] - g;
+        f[1] = -p[0] * y[1] - y[0] + p[4] * sin(p[1] * t);
+        break;
+    }
+    }
+}
+
+/*
+ * Weights b_k, a_k, c_k for k = k0..k0+n-1 (Section 2, eq. abm and the
+ * corrector weights below it), each from its literal formula in __float128,
+ * rounded once to double and stored at index k-k0.  The Gamma factors are
+ * taken in double and applied in quad.
+ */
+int oracle_weights_at(double alpha, int64_t k0, int64_t n, double *b, double *a, double *c)
+{
+    if (!(alpha > 0.0 && alpha <= 1.0) || n < 0 || k0 < 0)
+        return ORC_EINVAL;
+    const __float128 al = (__float128)alpha;
+    const __float128 g1 = (__float128)tgamma(alpha + 1.0);
+    const __float128 g2 = (__float128)tgamma(alpha + 2.0);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t k = k0 + i;
+        const __float128 kq = (__float128)k;
+        const __float128 k1 = kq + 1, k2 = kq + 2;
+        const __float128 pk0 = (k == 0) ? 0 : powq(kq, al);   /* k^alpha */
+        const __float128 pk1 = powq(k1, al);                  /* (k+1)^alpha */
+        const __float128 qk0 = (k == 0) ? 0 : powq(kq, al + 1);
+        const __float128 qk1 = powq(k1, al + 1);
+        const __float128 qk2 = powq(k2, al + 1);
+        if (b) b[i] = (double)((pk1 - pk0) / g1);
+        if (a) a[i] = (double)((qk2 - 2 * qk1 + qk0) / g2);
+        if (c) c[i] = (double)((qk0 - (kq - al) * pk1) / g2);
+    }
+    return ORC_OK;
+}
+
+/* Weights for k = 0..n-1. */
+int oracle_weights(double alpha, int64_t n, double *b, double *a, double *c)
+{
+    return oracle_weights_at(alpha, 0, n, b, a, c);
+}
+
+/* One ABM history sum for one component: plain ascending order, or
+ * Neumaier-compensated when comp != 0. */
+static double hist_sum(const double *w, const double *F, int d, int comp_idx,
+                       int64_t k_lo, int64_t n, int comp)
+{
+    double s = 0.0, e = 0.0;
+    for (int64_t k = k_lo; k <= n; ++k) {
+        const double term = w[n - k] * F[k * d + comp_idx];
+        if (comp) {
+            const double t = s + term;
+            if (fabs(s) >= fabs(term))
+                e += (s - t) + term;
+            else
+                e += (term - t) + s;
+            s = t;
+        } else {
+            s += term;
+        }
+    }
+    return s + e;
+}
+
+/*
+ * One trajectory of the fractional ABM scheme.
+ *   rhs, p      right-hand side and its parameters (table above)
+ *   d           state dimension (must equal the dimension of rhs)
+ *   alpha, h, N order, step size, number of steps
+ *   x0          initial state, d doubles
+ *   out_stride  0: write only y_N;  k>0: write y_s for s = 0, k, 2k, ... and y_N
+ *   y_out       d doubles per written state, in that order
+ *   comp        0: plain ascending sums; 1: Neumaier-compensated sums
+ * Returns 0, or a negative code for invalid arguments / allocation failure.
+ */
+int oracle_solve(int rhs, int d, double alpha, double h, int64_t N,
+                 const double *x0, const double *p, int64_t out_stride,
+                 double *y_out, int comp)
+{
+    if (rhs_dim(rhs) != d || !(alpha > 0.0 && alpha <= 1.0) || !(h > 0.0) ||
+        !isfinite(h) || N < 1 || out_stride < 0 || !x0 || !p || !y_out)
+        return ORC_EINVAL;
+    double *b = malloc(sizeof(double) * (size_t)N);
+    double *a = malloc(sizeof(double) * (size_t)N);
+    double *c = malloc(sizeof(double) * (size_t)N);
+    double *F = malloc(sizeof(double) * (size_t)(N + 1) * (size_t)d);
+    if (!b || !a || !c || !F) {
+        free(b); free(a); free(c); free(F);
+        return ORC_ENOMEM;
+    }
+    int rc = oracle_weights(alpha, N, b, a, c);
+    if (rc != ORC_OK) {
+        free(b); free(a); free(c); free(F);
+        return rc;
+    }
+    const double ha = pow(h, alpha);
+    const double g2 = tgamma(alpha + 2.0);
+    double y[8], yp[8], fp[8], P[8], C[8];
+
+    rhs_eval(rhs, p, 0.0, x0, F);   /* F_0 = f(t_0, y_0) */
+    int64_t w = 0;
+    if (out_stride > 0) {
+        memcpy(y_out, x0, sizeof(double) * (size_t)d);
+        w = 1;
+    }
+    for (int64_t s = 1; s <= N; ++s) {
+        const int64_t n = s - 1;
+        const double t = (double)s * h;
+        for (int i = 0; i < d; ++i)
+            P[i] = hist_sum(b, F, d, i, 0, n, comp);
+        for (int i = 0; i < d; ++i)
+            yp[i] = x0[i] + ha * P[i];
+        rhs_eval(rhs, p, t, yp, fp);
+        for (int i = 0; i < d; ++i) {
+            /* c_n f_0 first, then the a-weighted sum over k = 1..n */
+            double hs = hist_sum(a, F, d, i, 1, n, comp);
+            C[i] = c[n] * F[i] + hs;
+            y[i] = x0[i] + ha * (C[i] + fp[i] / g2);
+        }
+        rhs_eval(rhs, p, t, y, F + s * d);
+        if (out_stride > 0 && (s % out_stride == 0 || s == N)) {
+            memcpy(y_out + w * d, y, sizeof(double) * (size_t)d);
+            ++w;
+        }
+    }
+    if (out_stride == 0)
+        memcpy(y_out, y, sizeof(double) * (size_t)d);
+    free(b); free(a); free(c); free(F);
+    return ORC_OK;
+}
+
+/*
+ * Single steps recomputed from a given state history, for checking outputs of
+ * a long run one by one.  y_hist holds y_0 .. y_{smax-1} (d doubles each,
+ * smax = max over s_list); for every s in s_list the oracle forms
+ * F_k = f(t_k, y_hist_k) for k < s and applies one predictor-corrector step
+ * (the same formulas as oracle_solve), writing y_s to y_out + i*d.
+ */
+int oracle_steps_from_states(int rhs, int d, double alpha, double h, const double *x0,
+                             const double *p, const double *y_hist, const int64_t *s_list,
+                             int32_t ns, double *y_out)
+{
+    if (rhs_dim(rhs) != d || !(alpha > 0.0 && alpha <= 1.0) || !(h > 0.0) || ns < 0)
+        return ORC_EINVAL;
+    int64_t smax = 0;
+    for (int32_t i = 0; i < ns; ++i) {
+        if (s_list[i] < 1)
+            return ORC_EINVAL;
+        if (s_list[i] > smax)
+            smax = s_list[i];
+    }
+    if (smax == 0)
+        return ORC_OK;
+    double *b = malloc(sizeof(double) * (size_t)smax);
+    double *a = malloc(sizeof(double) * (size_t)smax);
+    double *c = malloc(sizeof(double) * (size_t)smax);
+    double *F = malloc(sizeof(double) * (size_t)smax * (size_t)d);
+    if (!b || !a || !c || !F) {
+        free(b); free(a); free(c); free(F);
+        return ORC_ENOMEM;
+    }
+    oracle_weights(alpha, smax, b, a, c);
+    for (int64_t k = 0; k < smax; ++k)
+        rhs_eval(rhs, p, (double)k * h, y_hist + k * d, F + k * d);
+    const double ha = pow(h, alpha);
+    const double g2 = tgamma(alpha + 2.0);
+    double yp[8], fp[8];
+    for (int32_t j = 0; j < ns; ++j) {
+        const int64_t s = s_list[j], n = s - 1;
+        const double t = (double)s * h;
+        for (int i = 0; i < d; ++i)
+            yp[i] = x0[i] + ha * hist_sum(b, F, d, i, 0, n, 0);
+        rhs_eval(rhs, p, t, yp, fp);
+        for (int i = 0; i < d; ++i) {
+            double hs = hist_sum(a, F, d, i, 1, n, 0);
+            y_out[j * d + i] = x0[i] + ha * ((c[n] * F[i] + hs) + fp[i] / g2);
+        }
+    }
+    free(b); free(a); free(c); free(F);
+    return ORC_OK;
+}
+
+/*
+ * A batch of independent trajectories, one per entry, run in parallel over
+ * trajectories with OpenMP (each trajectory is the single-trajectory scheme
+ * above, unchanged).  Arrays are per trajectory: rhs[i], d[i], alpha[i], h[i],
+ * N[i], x0[i*4 ...], p[i*8 ...]; y_out[i] points at that trajectory's output.
+ * status[i] receives each trajectory's return code.
+ */
+int oracle_solve_batch(int32_t B, const int32_t *rhs, const int32_t *d,
+                       const double *alpha, const double *h, const int64_t *N,
+                       const double *x0, const double *p, int64_t out_stride,
+                       double *const *y_out, int32_t *status, int comp)
+{
+    if (B < 0)
+        return ORC_EINVAL;
+    int bad = 0;
+#pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
+    for (int32_t i = 0; i < B; ++i) {
+        status[i] = oracle_solve(rhs[i], d[i], alpha[i], h[i], N[i], x0 + 4 * (size_t)i,
+                                 p + 8 * (size_t)i, out_stride, y_out[i], comp);
+        bad |= (status[i] != ORC_OK);
+    }
+    return bad ? ORC_EINVAL : ORC_OK;
+}
+
+/* Number of OpenMP threads the batch entry point would use. */
+int oracle_num_threads(void)
+{
+#ifdef _OPENMP
+    extern int omp_get_max_threads(void);
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}

@@ -1,0 +1,375 @@
+"""Pins for the CPU oracle, taken from mathematics rather than from the oracle
+itself (Section 2: the fractional ABM predictor-corrector and its weights).
+
+Each test would fail under a plausible slip in the oracle:
+  * weights vs quadrature of the product-integration rules   (sign of b, Gamma factors, indices)
+  * telescoping sums of the weights                           (every weight at once)
+  * exactness for forcing linear in t                         (corrector indexing, c_n f_0 term)
+  * Mittag-Leffler convergence order                          (whole scheme)
+  * alpha = 1 two-term recurrence                             (predictor/corrector coupling)
+  * 50-digit brute force on tiny N, weights by quadrature     (every step, every rhs)
+  * equilibrium invariance                                     (rhs formulas, spurious history terms)
+"""
+import math
+
+import mpmath as mp
+import numpy as np
+import pytest
+
+import oracle as O
+
+pytestmark = pytest.mark.filterwarnings("ignore")
+
+
+# ---------------------------------------------------------------- weights
+def _quad_weights(alpha, n, dps=30):
+    """Product-integration weights of step n+1 by numerical quadrature.
+
+    Predictor (product rectangle rule): weight of f_j is
+        (1/Gamma(alpha)) * int_j^{j+1} (n+1-u)^(alpha-1) du       -> b_{n-j}
+    Corrector (product trapezoid rule): weight of f_j is
+        (1/Gamma(alpha)) * int_0^{n+1} (n+1-u)^(alpha-1) phi_j(u) du
+    with phi_j the piecewise-linear hat at node j:  j=0 -> c_n,
+    1<=j<=n -> a_{n-j}, j=n+1 -> 1/Gamma(alpha+2).
+    The integrals are taken in v = n+1-u, the distance to the singular end
+    point, and then in w = v^alpha, which turns v^(alpha-1) dv into dw/alpha
+    and leaves a smooth integrand for the quadrature.
+    """
+    with mp.workdps(dps):
+        al = mp.mpf(alpha)
+        ga = mp.gamma(al)
+        pred = [_kq(al, lambda v: 1, n - j, n + 1 - j) / ga for j in range(n + 1)]
+        corr = []
+        for j in range(n + 2):
+            vj = n + 1 - j     # node j sits at v = n+1-j
+            tot = mp.mpf(0)
+            if j >= 1:      # u in [j-1, j]  <->  v in [vj, vj+1]
+                tot += _kq(al, lambda v: vj + 1 - v, vj, vj + 1)
+            if j <= n:      # u in [j, j+1]  <->  v in [vj-1, vj]
+                tot += _kq(al, lambda v: v - (vj - 1), vj - 1, vj)
+            corr.append(tot / ga)
+        return [float(x) for x in pred], [float(x) for x in corr]
+
+
+def _kq(al, g, v0, v1):
+    """int_{v0}^{v1} v^(al-1) g(v) dv by quadrature in w = v^al."""
+    inv = 1 / al
+    return mp.quad(lambda w: g(w ** inv), [mp.mpf(v0) ** al, mp.mpf(v1) ** al]) / al
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.8, 0.95, 1.0])
+def test_weights_match_quadrature(alpha):
+    nmax = 4
+    b, a, c = O.weights(alpha, nmax + 1)
+    for n in range(nmax + 1):
+        pred, corr = _quad_weights(alpha, n)
+        for j in range(n + 1):
+            assert b[n - j] == pytest.approx(pred[j], rel=2e-15, abs=0)
+        assert c[n] == pytest.approx(corr[0], rel=2e-15, abs=0)
+        for j in range(1, n + 1):
+            assert a[n - j] == pytest.approx(corr[j], rel=2e-15, abs=0)
+        assert corr[n + 1] == pytest.approx(1.0 / math.gamma(alpha + 2.0), rel=2e-15)
+
+
+def test_printed_plus_sign_of_b_is_not_the_rule():
+    # The predictor weight is printed with a "+" between the powers; the
+    # product-rectangle rule gives the difference.  At alpha=0.8, n=1 the
+    # quadrature value is 0.79570; the "+" form would give 2.943.
+    pred, _ = _quad_weights(0.8, 1)
+    plus = (2 ** 0.8 + 1 ** 0.8) / math.gamma(1.8)
+    minus = (2 ** 0.8 - 1 ** 0.8) / math.gamma(1.8)
+    assert pred[0] == pytest.approx(minus, rel=1e-14)
+    assert abs(pred[0] - plus) > 1.0
+    b, _, _ = O.weights(0.8, 2)
+    assert b[1] == pytest.approx(pred[0], rel=1e-15)
+
+
+@pytest.mark.parametrize("alpha,k0", [(0.8, 65536), (0.9, 262144), (0.95, 3_000_000),
+                                      (0.5, 1_000_000)])
+def test_weights_large_index_50_digits(alpha, k0):
+    """Cancellation in the differences of powers grows like k^2; the oracle's
+    quad evaluation must still be within a few ulp of a 50-digit value."""
+    n = 4
+    b, a, c = O.weights(alpha, n, k0=k0)
+    with mp.workdps(50):
+        al = mp.mpf(alpha)
+        g1, g2 = mp.gamma(al + 1), mp.gamma(al + 2)
+        for i in range(n):
+            k = mp.mpf(k0 + i)
+            bb = ((k + 1) ** al - k ** al) / g1
+            aa = ((k + 2) ** (al + 1) - 2 * (k + 1) ** (al + 1) + k ** (al + 1)) / g2
+            cc = (k ** (al + 1) - (k - al) * (k + 1) ** al) / g2
+            # Gamma is taken in double on the oracle side: allow its 1-2 ulp.
+            assert b[i] == pytest.approx(float(bb), rel=8e-16)
+            assert a[i] == pytest.approx(float(aa), rel=8e-16)
+            assert c[i] == pytest.approx(float(cc), rel=8e-16)
+
+
+@pytest.mark.parametrize("alpha", [0.2, 0.55, 0.8, 0.9, 0.99, 1.0])
+def test_weight_sums_telescope(alpha):
+    """Both quadrature rules integrate f == 1 exactly:
+       sum_{k=0..n} b_k                        = (n+1)^alpha / Gamma(alpha+1)
+       c_n + sum_{k=0..n-1} a_k + 1/Gamma(alpha+2) = (n+1)^alpha / Gamma(alpha+1)"""
+    nmax = 5000
+    b, a, c = O.weights(alpha, nmax + 1)
+    g1 = math.gamma(alpha + 1.0)
+    g2 = math.gamma(alpha + 2.0)
+    for n in [0, 1, 2, 7, 100, 1234, nmax]:
+        exact = (n + 1) ** alpha / g1
+        sb = math.fsum(b[: n + 1])
+        sc = math.fsum(list(a[:n]) + [c[n], 1.0 / g2])
+        assert sb == pytest.approx(exact, rel=4e-15)
+        assert sc == pytest.approx(exact, rel=4e-15)
+
+
+def test_alpha_one_weights_exact():
+    b, a, c = O.weights(1.0, 1000)
+    assert np.all(b == 1.0)
+    assert np.all(a == 1.0)
+    assert np.all(c[1:] == 0.5)
+    assert c[0] == 0.5  # c_0 = alpha / Gamma(alpha+2) = 1/2
+
+
+# ---------------------------------------------------------------- whole scheme
+@pytest.mark.parametrize("alpha", [0.35, 0.8, 1.0])
+def test_linear_in_t_forcing_is_integrated_exactly(alpha):
+    """f = c0 + c1 t does not depend on y, so the corrector (product
+    trapezoid rule, exact for piecewise-linear integrands) reproduces
+    y(t) = y0 + c0 t^a/Gamma(a+1) + c1 t^(a+1)/Gamma(a+2) at every node."""
+    c0, c1, y0, h, N = 0.7, -0.3, 0.25, 1.0 / 64, 300
+    y = O.solve(O.RHS_POLY, alpha, h, N, [y0], [c0, c1], out_stride=1)[:, 0]
+    t = np.arange(N + 1) * h
+    exact = y0 + c0 * t ** alpha / math.gamma(alpha + 1) + c1 * t ** (alpha + 1) / math.gamma(alpha + 2)
+    assert np.max(np.abs(y - exact)) <= 2e-14 * np.max(np.abs(exact))
+
+
+def _mittag_leffler(alpha, z, dps=60):
+    with mp.workdps(dps):
+        z = mp.mpf(z)
+        return float(mp.nsum(lambda k: z ** k / mp.gamma(alpha * k + 1), [0, mp.inf]))
+
+
+@pytest.mark.parametrize("alpha", [0.5, 0.8])
+def test_mittag_leffler_convergence_order(alpha):
+    """D^a y = -y, y(0)=1 has y = E_a(-t^a).  The ABM error at fixed T decays
+    like h^(1+a) for a < 1 (the observed order of the product-trapezoid
+    corrector on this smooth-in-t^a solution)."""
+    T = 8.0
+    exact = _mittag_leffler(alpha, -T ** alpha)
+    errs = []
+    hs = [2.0 ** -k for k in (5, 6, 7, 8, 9)]
+    for h in hs:
+        N = int(round(T / h))
+        y = O.solve(O.RHS_LINEAR, alpha, h, N, [1.0], [1.0], out_stride=0)[0, 0]
+        errs.append(abs(y - exact))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert abs(orders[-1] - (1 + alpha)) < 0.08, orders
+
+
+def test_mittag_leffler_at_the_linear_workload():
+    """alpha=0.8, h=2^-10, N=8192: the ABM value sits within 2e-8 of
+    E_0.8(-8^0.8) (error of order h^1.8)."""
+    exact = _mittag_leffler(0.8, -8.0 ** 0.8)
+    y = O.solve(O.RHS_LINEAR, 0.8, 2.0 ** -10, 8192, [1.0], [1.0], out_stride=0)[0, 0]
+    assert 1e-9 < abs(y - exact) < 2e-8
+
+
+def _volterra_alpha1(rhs_fn, x0, h, N):
+    """At alpha = 1 the scheme collapses to a two-term recurrence:
+       yP_{n+1} = yP_n + h f_n                      (yP_0 = x0)
+       y_{n+1}  = y_n + h (f_n + (fP_{n+1} - fP_n)/2)  with fP_0 = f_0."""
+    x0 = np.asarray(x0, float)
+    y = [x0.copy()]
+    f = [rhs_fn(0.0, x0)]
+    yP = x0.copy()
+    fP_prev = f[0]
+    for n in range(N):
+        t1 = (n + 1) * h
+        yP = yP + h * f[n]
+        fP = rhs_fn(t1, yP)
+        ynew = y[n] + h * (f[n] + (fP - fP_prev) / 2.0)
+        y.append(ynew)
+        f.append(rhs_fn(t1, ynew))
+        fP_prev = fP
+    return np.array(y)
+
+
+def _duffing(p):
+    d_, A, w = p
+    return lambda t, y: np.array([y[1], -d_ * y[1] - y[0] - y[0] ** 3 + A * math.cos(w * t)])
+
+
+def test_alpha_one_is_the_volterra_recurrence():
+    p = (0.1, 0.3, 1.2)
+    h, N = 1.0 / 128, 1024
+    y = O.solve(O.RHS_DUFFING, 1.0, h, N, [0.1, 0.0], p, out_stride=1)
+    ref = _volterra_alpha1(_duffing(p), [0.1, 0.0], h, N)
+    assert np.max(np.abs(y - ref)) <= 3e-14 * np.max(np.abs(ref))
+
+
+def test_alpha_one_vs_classical_trapezoid_pece():
+    """Classical trapezoidal PECE (y_{n+1} = y_n + h/2 (f_n + f(t_{n+1}, y_n + h f_n)))
+    coincides with the alpha=1 scheme only when f ignores y; otherwise the two
+    differ by O(h^2)."""
+    # f independent of y: identical up to rounding
+    h, N = 1.0 / 64, 256
+    y = O.solve(O.RHS_POLY, 1.0, h, N, [0.5], [0.7, -0.3], out_stride=1)[:, 0]
+    t = np.arange(N + 1) * h
+    z = 0.5 + 0.7 * t - 0.15 * t * t
+    assert np.max(np.abs(y - z)) < 1e-13
+    # y-dependent f: the gap shrinks about 4x per halving of h
+    p = (0.1, 0.3, 1.2)
+    fn = _duffing(p)
+    gaps = []
+    for h in (2.0 ** -5, 2.0 ** -6, 2.0 ** -7):
+        N = int(4 / h)
+        ya = O.solve(O.RHS_DUFFING, 1.0, h, N, [0.1, 0.0], p, out_stride=0)[0]
+        yc = np.array([0.1, 0.0])
+        for n in range(N):
+            f0 = fn(n * h, yc)
+            yc = yc + h / 2 * (f0 + fn((n + 1) * h, yc + h * f0))
+        gaps.append(np.max(np.abs(ya - yc)))
+    assert gaps[0] > 1e-6
+    r1, r2 = gaps[0] / gaps[1], gaps[1] / gaps[2]
+    assert 3.0 < r1 < 5.0 and 3.0 < r2 < 5.0, gaps
+
+
+# ---------------------------------------------------------------- brute force
+def _rhs_mp(name, p):
+    if name == "LINEAR":
+        return lambda t, y: [-p[0] * y[0]]
+    if name == "DUFFING":
+        return lambda t, y: [y[1], -p[0] * y[1] - y[0] - y[0] ** 3 + p[1] * mp.cos(p[2] * t)]
+    if name == "LORENZ":
+        return lambda t, y: [p[0] * (y[1] - y[0]), y[0] * (p[1] - y[2]) - y[1],
+                             y[0] * y[1] - p[2] * y[2]]
+    if name == "LCR":
+        def g(x):
+            if x <= -1:
+                return p[3] * x - p[2] + p[3]
+            if x >= 1:
+                return p[3] * x + p[2] - p[3]
+            return p[2] * x
+        return lambda t, y: [y[1] - g(y[0]), -p[0] * y[1] - y[0] + p[4] * mp.sin(p[1] * t)]
+    raise KeyError(name)
+
+
+def _brute_force(name, alpha, h, N, x0, p):
+    """50-digit ABM for tiny N with weights from quadrature of the
+    product-integration rules (no closed-form weight is used)."""
+    with mp.workdps(50):
+        al = mp.mpf(alpha)
+        hh = mp.mpf(h)
+        fn = _rhs_mp(name, [mp.mpf(v) for v in p])
+        x0m = [mp.mpf(v) for v in x0]
+        d = len(x0)
+        ha = hh ** al
+        ga = mp.gamma(al)
+        F = [fn(mp.mpf(0), x0m)]
+        ys = [x0m]
+        for n in range(N):
+            # v = t_{n+1}/h - u, kernel v^(alpha-1), node j at v = n+1-j
+            pw = [_kq(al, lambda v: 1, n - j, n + 1 - j) / ga for j in range(n + 1)]
+            cw = []
+            for j in range(n + 2):
+                vj = n + 1 - j
+                tot = mp.mpf(0)
+                if j >= 1:
+                    tot += _kq(al, lambda v: vj + 1 - v, vj, vj + 1)
+                if j <= n:
+                    tot += _kq(al, lambda v: v - (vj - 1), vj - 1, vj)
+                cw.append(tot / ga)
+            t1 = (n + 1) * hh
+            yP = [x0m[i] + ha * mp.fsum(pw[j] * F[j][i] for j in range(n + 1)) for i in range(d)]
+            fP = fn(t1, yP)
+            y1 = [x0m[i] + ha * (mp.fsum(cw[j] * F[j][i] for j in range(n + 1)) + cw[n + 1] * fP[i])
+                  for i in range(d)]
+            ys.append(y1)
+            F.append(fn(t1, y1))
+        return np.array([[float(v) for v in y] for y in ys])
+
+
+@pytest.mark.parametrize("name,alpha,h,x0,p", [
+    ("LINEAR", 0.7, 0.125, [1.0], [1.3]),
+    ("DUFFING", 0.9, 0.05, [0.1, 0.0], [0.1, 0.3, 1.2]),
+    ("LORENZ", 0.95, 0.01, [1.0, 1.0, 1.0], [10.0, 28.0, 8.0 / 3.0]),
+    ("LCR", 0.9, 0.25, [1.2, -0.4], [1.015, 0.55, -1.02, -0.58, 0.117]),
+])
+def test_tiny_n_brute_force(name, alpha, h, x0, p):
+    N = 10
+    rid = {"LINEAR": O.RHS_LINEAR, "DUFFING": O.RHS_DUFFING, "LORENZ": O.RHS_LORENZ,
+           "LCR": O.RHS_LCR}[name]
+    y = O.solve(rid, alpha, h, N, x0, p, out_stride=1)
+    ref = _brute_force(name, alpha, h, N, x0, p)
+    assert np.max(np.abs(y - ref)) <= 2e-15 * max(1.0, np.max(np.abs(ref)))
+
+
+# ---------------------------------------------------------------- invariants
+def _lcr_equilibria(sigma, a, b):
+    """Equilibria of the unforced LCR system (f = 0), as given in the
+    "Numerical experiment" section: E0 = (0,0) and
+    E+- = (+-sigma(a-b)/(1+sigma b), +-(b-a)/(1+sigma b))."""
+    den = 1 + sigma * b
+    return [(0.0, 0.0), (sigma * (a - b) / den, (b - a) / den),
+            (-sigma * (a - b) / den, -(b - a) / den)]
+
+
+@pytest.mark.parametrize("case", ["lorenz0", "lorenz+", "lorenz-", "duffing0", "lcr0", "lcr+",
+                                  "lcr-"])
+def test_equilibrium_is_invariant(case):
+    alpha, h, N = 0.9, 1.0 / 256, 512
+    if case.startswith("lorenz"):
+        s, r, bb = 10.0, 28.0, 8.0 / 3.0
+        q = math.sqrt(bb * (r - 1))
+        x0 = {"lorenz0": (0, 0, 0), "lorenz+": (q, q, r - 1), "lorenz-": (-q, -q, r - 1)}[case]
+        y = O.solve(O.RHS_LORENZ, alpha, h, N, x0, (s, r, bb), out_stride=1)
+    elif case == "duffing0":
+        x0 = (0.0, 0.0)
+        y = O.solve(O.RHS_DUFFING, alpha, h, N, x0, (0.1, 0.0, 1.2), out_stride=1)
+    else:
+        E = _lcr_equilibria(1.015, -1.02, -0.58)
+        x0 = E[{"lcr0": 0, "lcr+": 1, "lcr-": 2}[case]]
+        y = O.solve(O.RHS_LCR, alpha, h, N, x0, (1.015, 0.55, -1.02, -0.58, 0.0), out_stride=1)
+    dev = np.max(np.abs(y - np.asarray(x0)[None, :]))
+    assert dev <= 1e-12 * max(1.0, np.max(np.abs(x0))), dev
+
+
+def test_steps_from_states_reproduce_a_run():
+    pr = dict(rhs=O.RHS_DUFFING, alpha=0.9, h=1e-2, x0=[0.1, 0.0], p=[0.1, 0.3, 1.2])
+    N = 700
+    y = O.solve(pr["rhs"], pr["alpha"], pr["h"], N, pr["x0"], pr["p"], out_stride=1)
+    s_list = [1, 2, 63, 64, 65, 699, 700]
+    ys = O.steps_from_states(pr["rhs"], pr["alpha"], pr["h"], pr["x0"], pr["p"], y, s_list)
+    assert np.array_equal(ys, y[s_list])
+
+
+def test_rounding_noise_floor_is_far_below_parity_tolerance():
+    """Whether 1e-12 agreement is well posed: perturbing x0 by 1e-14 or
+    switching to compensated summation moves the trajectory by far less."""
+    base = dict(alpha=0.95, h=2.0 ** -8, N=4096, p=[0.1, 0.45, 1.2])
+    y0 = O.solve(O.RHS_DUFFING, base["alpha"], base["h"], base["N"], [0.1, 0.0], base["p"])
+    y1 = O.solve(O.RHS_DUFFING, base["alpha"], base["h"], base["N"], [0.1 + 1e-14, 0.0], base["p"])
+    y2 = O.solve(O.RHS_DUFFING, base["alpha"], base["h"], base["N"], [0.1, 0.0], base["p"],
+                 compensated=True)
+    scale = np.max(np.abs(y0))
+    assert np.max(np.abs(y1 - y0)) / scale < 1e-13
+    assert np.max(np.abs(y2 - y0)) / scale < 1e-13
+
+
+def test_batch_equals_single(orc):
+    probs = [(O.RHS_DUFFING, 0.95, 2 ** -6, 300, [0.1, 0.0], [0.1, A, 1.2]) for A in (0.1, 0.35, 0.6)]
+    probs.append((O.RHS_LORENZ, 0.93, 2 ** -8, 257, [1.0, 1.0, 1.0], [10.0, 28.0, 8 / 3]))
+    outs = O.solve_batch([q[0] for q in probs], [q[1] for q in probs], [q[2] for q in probs],
+                         [q[3] for q in probs], [q[4] for q in probs], [q[5] for q in probs],
+                         out_stride=7)
+    for q, o in zip(probs, outs):
+        assert np.array_equal(o, O.solve(*q, out_stride=7))
+
+
+def test_invalid_arguments_rejected():
+    with pytest.raises(ValueError):
+        O.solve(O.RHS_LINEAR, 1.5, 0.1, 10, [1.0], [1.0])
+    with pytest.raises(ValueError):
+        O.solve(O.RHS_LINEAR, 0.5, -0.1, 10, [1.0], [1.0])
+    with pytest.raises(ValueError):
+        O.solve(O.RHS_LINEAR, 0.5, 0.1, 0, [1.0], [1.0])
