@@ -1,0 +1,183 @@
+"""Benchmark of the fractional ABM history sums on one MI355X.
+
+One step = one abm_solve_batch call over the forcing sweep (B = 1024 forced
+Duffing oscillators, alpha = 0.95, h = 2^-8, N = 65536, amplitudes uniform in
+[0.1, 0.6] from seed 1710): weight tables resident, far-field products on the
+matrix cores, near band and predictor/corrector chain, outputs every 1024th
+state.  Inputs are synthetic and already in HBM when the timed region starts.
+
+Printed: one JSON line with history MACs/s (d*N(N+1)/2 per trajectory) of the
+batched path, the plain per-step path on the single 200000-step oscillator
+for comparison, the far-field kernel's roofline position (live HIP-event
+timing of its launches), the error against the double oracle, and the oracle
+itself timed on the host cores on a bounded sample of the same sweep.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+PEAK_TFLOPS = {"fp64": 78.6, "fp32": 157.3, "bf16x3": 2500.0, "bf16x6": 2500.0}
+EXEC_FACTOR = {"fp64": 1, "fp32": 1, "bf16x3": 3, "bf16x6": 6}
+DTYPE = {"fp64": "f64", "fp32": "f32 far field, f64 near/state",
+         "bf16x3": "bf16x3 far field (f32 accumulate), f64 near/state",
+         "bf16x6": "bf16x6 far field (f32 accumulate), f64 near/state"}
+
+
+def normerr(y, ref):
+    return float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+
+
+def time_batch(abm, torch, plan, probs, ys, steps, warmup):
+    for _ in range(warmup):
+        abm.solve_batch(plan, probs, ys)
+    plan.check()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = None
+    for _ in range(steps):
+        st = abm.solve_batch(plan, probs, ys)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    plan.check()
+    return dt, st
+
+
+def cpu_baseline(inputs, budget_s=20.0):
+    """The oracle as it stands on the host cores: a bounded sample of the
+    sweep (whole trajectories at full N, OpenMP over trajectories)."""
+    import oracle as O
+    nthr = O.num_threads()
+    sweep = inputs.duffing_sweep()
+    # one trajectory takes ~7 s on one core: sample as many as there are threads
+    idx = list(range(nthr))
+    sample = [sweep[i] for i in idx]
+    t0 = time.perf_counter()
+    O.solve_batch([O.RHS_DUFFING] * len(sample), [p.alpha for p in sample],
+                  [p.h for p in sample], [p.N for p in sample], [p.x0 for p in sample],
+                  [p.p for p in sample], out_stride=0)
+    dt = time.perf_counter() - t0
+    macs = sum(p.history_macs() for p in sample)
+    return {"value": macs / dt, "unit": "history MACs/s", "cores": nthr, "kind": "oracle",
+            "sample": "%d of the 1024 sweep trajectories at full N=65536 (OpenMP over "
+                      "trajectories), %.1f s wall" % (len(sample), dt)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--prec", default="fp64", choices=list(PEAK_TFLOPS))
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the batched sweep is sized for one MI355X and no "
+              "multi-GPU path is built (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1710_01133_amd import abm, inputs
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    ctx = abm.Context(0)
+
+    stride = 1024
+    probs = inputs.duffing_sweep(far_prec=args.prec)
+    t0 = time.perf_counter()
+    plan = abm.Plan(ctx, probs, out_stride=stride)
+    torch.cuda.synchronize()
+    plan_s = time.perf_counter() - t0
+    ys = [abm.alloc_out(p, stride) for p in probs]
+    dt, st = time_batch(abm, torch, plan, probs, ys, args.steps, args.warmup)
+    macs = st["history_macs"]
+    value = macs / dt
+
+    # error against the stored double-precision oracle runs of four members
+    gold_path = os.path.join(ROOT, "tests", "golden", "oracle_fullsize.json")
+    errs = {}
+    if os.path.exists(gold_path):
+        with open(gold_path) as f:
+            g = json.load(f)
+        for i in (0, 1, 511, 1023):
+            key = "duffing_sweep_%d" % i
+            if key in g:
+                errs[i] = normerr(ys[i].cpu().numpy(), np.array(g[key]["y"]))
+    max_err = max(errs.values()) if errs else None
+
+    # roofline of the far-field kernel: one more solve with per-launch events
+    plan.timing(True)
+    stt = abm.solve_batch(plan, probs, ys)
+    plan.timing(False)
+    plan.check()
+    far_flop = 4.0 * stt["far_macs"]          # predictor + corrector multiply-add per history MAC
+    far_s = stt["far_ms"] / 1e3
+    achieved = far_flop / far_s / 1e12
+    peak = PEAK_TFLOPS[args.prec]
+    roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
+            "frac": achieved / peak, "traffic": None,
+            "kernel": "far-field Toeplitz x history product (%s)" % args.prec,
+            "launches": stt["far_launches"], "avg_launch_ms": stt["far_ms"] / stt["far_launches"],
+            "flop_per_launch": far_flop / stt["far_launches"],
+            "executed_frac": achieved * EXEC_FACTOR[args.prec] / peak,
+            "chain_ms_total": stt["chain_ms"], "far_ms_total": stt["far_ms"]}
+
+    plain = None
+    if not args.no_plain:
+        p1 = inputs.duffing_single()
+        pp = abm.Plan(ctx, [p1], out_stride=0)
+        y1 = abm.alloc_out(p1, 0)
+        abm.solve(pp, p1, y1)
+        pp.check()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        abm.solve(pp, p1, y1)
+        torch.cuda.synchronize()
+        dt1 = time.perf_counter() - t1
+        pp.check()
+        plain = {"workload": "forced Duffing, alpha=0.9, h=1e-3, N=200000, d=2, one trajectory",
+                 "seconds": dt1, "history_macs_per_s": p1.history_macs() / dt1,
+                 "us_per_step": dt1 / p1.N * 1e6}
+        pp.close()
+
+    cpu = None if args.no_cpu else cpu_baseline(inputs)
+
+    out = {
+        "metric": "history MACs/s (d*N(N+1)/2 per trajectory), batched sweep",
+        "value": value,
+        "unit": "history MACs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": dt * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": DTYPE[args.prec],
+        "data": "synthetic (seeded forcing sweep)",
+        "config": {"workload": "forcing sweep: B=1024 forced Duffing, alpha=0.95, h=2^-8, "
+                               "N=65536, d=2, far field %s" % args.prec,
+                   "B": 1024, "N": 65536, "d": 2, "block_L": st["block_L"],
+                   "far_prec": args.prec},
+        "max_rel_err_vs_oracle": max_err,
+        "err_members": errs,
+        "plan_seconds": plan_s,
+        "roofline": roof,
+        "plain": plain,
+        "batched_over_plain": (value / plain["history_macs_per_s"]) if plain else None,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+    plan.close()
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,357 @@
+// libabm runtime: contexts, plans, argument checking and the C ABI entry
+// points declared in include/abm.h.  Every arithmetic step of the method runs
+// in the kernels (K0 weights, K1 plain path, far-field and chain kernels of
+// the blocked path); this file only validates, allocates and enqueues.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "abm.h"
+#include "abm_kernels.h"
+#include "abm_runtime.h"
+
+namespace abm {
+
+static thread_local std::string g_last_error;
+
+abm_status fail(abm_status code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+abm_status hip_fail(hipError_t e, const char* what)
+{
+    return fail(e == hipErrorOutOfMemory ? ABM_ENOMEM : ABM_EDEVICE, "%s: %s", what,
+                hipGetErrorString(e));
+}
+
+int rhs_dim(int rhs)
+{
+    switch (rhs) {
+    case ABM_RHS_LINEAR: return 1;
+    case ABM_RHS_DUFFING: return 2;
+    case ABM_RHS_LORENZ: return 3;
+    case ABM_RHS_POLY: return 1;
+    case ABM_RHS_LCR: return 2;
+    default: return -1;
+    }
+}
+
+int64_t n_out(int64_t N, int64_t stride)
+{
+    if (stride == 0) return 1;
+    return N / stride + 1 + (N % stride ? 1 : 0);
+}
+
+abm_status validate(const abm_problem& p, int idx)
+{
+    const int d = rhs_dim(p.rhs);
+    if (d < 0) return fail(ABM_EINVAL, "problem %d: unknown rhs %d", idx, p.rhs);
+    if (p.d != d) return fail(ABM_EINVAL, "problem %d: d=%d but rhs %d has dimension %d", idx, p.d, p.rhs, d);
+    if (!(p.alpha > 0.0 && p.alpha <= 1.0))
+        return fail(ABM_EINVAL, "problem %d: alpha=%g outside (0, 1]", idx, p.alpha);
+    if (!(p.h > 0.0) || !std::isfinite(p.h))
+        return fail(ABM_EINVAL, "problem %d: h=%g must be positive and finite", idx, p.h);
+    if (p.N < 1 || p.N > kMaxSteps)
+        return fail(ABM_EINVAL, "problem %d: N=%lld outside [1, %lld]", idx, (long long)p.N,
+                    (long long)kMaxSteps);
+    if (p.out_stride < 0) return fail(ABM_EINVAL, "problem %d: out_stride < 0", idx);
+    if (p.far_prec < ABM_FAR_FP64 || p.far_prec > ABM_FAR_BF16X6)
+        return fail(ABM_EINVAL, "problem %d: unknown far_prec %d", idx, p.far_prec);
+    for (int i = 0; i < d; ++i)
+        if (!std::isfinite(p.x0[i])) return fail(ABM_EINVAL, "problem %d: x0 not finite", idx);
+    for (int i = 0; i < 8; ++i)
+        if (!std::isfinite(p.p[i])) return fail(ABM_EINVAL, "problem %d: p not finite", idx);
+    return ABM_OK;
+}
+
+// Shape fields a plan fixes; x0, p and h may change between solves.
+static bool same_shape(const abm_problem& a, const abm_problem& b)
+{
+    return a.rhs == b.rhs && a.d == b.d && a.alpha == b.alpha && a.N == b.N &&
+           a.far_prec == b.far_prec && a.out_stride == b.out_stride;
+}
+
+int env_int(const char* name, int dflt)
+{
+    const char* v = getenv(name);
+    if (!v || !*v) return dflt;
+    return atoi(v);
+}
+
+abm_status dev_alloc(void** p, size_t bytes, const char* what)
+{
+    *p = nullptr;
+    if (bytes == 0) return ABM_OK;
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        return hip_fail(e, what);
+    }
+    return ABM_OK;
+}
+
+void dev_free(void* p)
+{
+    if (p) (void)hipFree(p);
+}
+
+static void free_tables(abm_plan_s* pl)
+{
+    for (auto& t : pl->tables) {
+        dev_free(t.gam);
+        dev_free(t.b);
+        dev_free(t.a);
+        dev_free(t.c);
+        free_reduced(t);
+    }
+    pl->tables.clear();
+}
+
+}  // namespace abm
+
+using namespace abm;
+
+extern "C" {
+
+const char* abm_strerror(abm_status s)
+{
+    switch (s) {
+    case ABM_OK: return "ok";
+    case ABM_EINVAL: return "invalid argument";
+    case ABM_ENOMEM: return "out of memory";
+    case ABM_EDEVICE: return "device failure";
+    case ABM_EAGAIN: return "not finished";
+    case ABM_ENOENT: return "unknown ticket";
+    case ABM_ECANCELED: return "cancelled";
+    default: return "unknown status";
+    }
+}
+
+const char* abm_last_error(void) { return g_last_error.c_str(); }
+
+abm_status abm_ctx_create(int device, void* hip_stream, size_t arena_bytes, abm_ctx** out)
+{
+    if (!out) return fail(ABM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= n) return fail(ABM_EINVAL, "device %d of %d", device, n);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    abm_ctx* c = new abm_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->arena_bytes = arena_bytes ? arena_bytes : ((size_t)1 << 30);
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipGetDeviceProperties");
+    }
+    c->n_cu = prop.multiProcessorCount;
+    *out = c;
+    return ABM_OK;
+}
+
+void abm_ctx_destroy(abm_ctx* ctx)
+{
+    if (!ctx) return;
+    serve_shutdown(ctx);
+    delete ctx;
+}
+
+abm_status abm_plan(abm_ctx* ctx, const abm_problem* probs, int32_t B, abm_plan_t** out)
+{
+    if (!ctx || !probs || !out) return fail(ABM_EINVAL, "NULL argument");
+    *out = nullptr;
+    if (B < 1) return fail(ABM_EINVAL, "B=%d must be >= 1", B);
+    for (int i = 0; i < B; ++i) {
+        abm_status s = validate(probs[i], i);
+        if (s != ABM_OK) return s;
+    }
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    abm_plan_s* pl = new abm_plan_s();
+    pl->ctx = ctx;
+    pl->B = B;
+    pl->shape.assign(probs, probs + B);
+    abm_status st = ABM_OK;
+
+    // one weight table per distinct alpha, long enough for its longest member
+    pl->table_of.resize(B);
+    for (int i = 0; i < B; ++i) {
+        int found = -1;
+        for (size_t j = 0; j < pl->tables.size(); ++j)
+            if (pl->tables[j].alpha == probs[i].alpha) found = (int)j;
+        if (found < 0) {
+            WeightTable t{};
+            t.alpha = probs[i].alpha;
+            pl->tables.push_back(t);
+            found = (int)pl->tables.size() - 1;
+        }
+        pl->tables[found].n = std::max<int64_t>(pl->tables[found].n, probs[i].N);
+        pl->table_of[i] = found;
+    }
+    for (auto& t : pl->tables) {
+        // padded so that block kernels may read a full tile past N
+        const int64_t n = t.n + kWeightPad;
+        if ((st = dev_alloc((void**)&t.gam, 2 * sizeof(double), "weights")) ||
+            (st = dev_alloc((void**)&t.b, n * sizeof(double), "weights")) ||
+            (st = dev_alloc((void**)&t.a, n * sizeof(double), "weights")) ||
+            (st = dev_alloc((void**)&t.c, n * sizeof(double), "weights")))
+            break;
+        e = launch_weights(t.alpha, n, t.gam, t.b, t.a, t.c, ctx->stream);
+        if (e != hipSuccess) {
+            st = hip_fail(e, "weight kernel");
+            break;
+        }
+    }
+    if (st == ABM_OK) st = dev_alloc((void**)&pl->status, sizeof(uint32_t), "status");
+    if (st == ABM_OK) {
+        e = launch_fill_u32(pl->status, 0, 1, ctx->stream);
+        if (e != hipSuccess) st = hip_fail(e, "fill");
+    }
+    if (st == ABM_OK && B == 1) {
+        // the plain path is optional: a history too long for it leaves plain_G = 0
+        const abm_status ps = plain_setup(pl);
+        if (ps == ABM_ENOMEM || ps == ABM_EDEVICE) st = ps;
+        if (ps != ABM_OK) pl->plain_error = abm_last_error();
+    }
+    if (st == ABM_OK) st = batch_setup(pl);
+    if (st != ABM_OK) {
+        abm_plan_destroy(pl);
+        return st;
+    }
+    *out = pl;
+    return ABM_OK;
+}
+
+void abm_plan_destroy(abm_plan_t* pl)
+{
+    if (!pl) return;
+    (void)hipSetDevice(pl->ctx->device);
+    (void)hipStreamSynchronize(pl->ctx->stream);
+    free_tables(pl);
+    dev_free(pl->part);
+    dev_free(pl->flags);
+    dev_free(pl->status);
+    batch_teardown(pl);
+    delete pl;
+}
+
+abm_status abm_plan_check(abm_plan_t* pl)
+{
+    if (!pl) return fail(ABM_EINVAL, "plan is NULL");
+    hipError_t e = hipStreamSynchronize(pl->ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    uint32_t bits = 0;
+    e = hipMemcpy(&bits, pl->status, sizeof bits, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "status read");
+    if (bits) {
+        (void)launch_fill_u32(pl->status, 0, 1, pl->ctx->stream);
+        (void)hipStreamSynchronize(pl->ctx->stream);
+        return fail(ABM_EDEVICE, "device status 0x%x (%s%s)", bits,
+                    (bits & 1u) ? "wait timed out " : "", (bits & 2u) ? "non-finite state" : "");
+    }
+    return ABM_OK;
+}
+
+abm_status abm_plan_weights(abm_plan_t* pl, int32_t idx, int64_t n, double* b, double* a,
+                            double* c)
+{
+    if (!pl) return fail(ABM_EINVAL, "plan is NULL");
+    if (idx < 0 || idx >= pl->B) return fail(ABM_EINVAL, "idx %d outside [0, %d)", idx, pl->B);
+    const WeightTable& t = pl->tables[pl->table_of[idx]];
+    if (n < 0 || n > t.n + kWeightPad)
+        return fail(ABM_EINVAL, "n=%lld outside [0, %lld]", (long long)n, (long long)(t.n + kWeightPad));
+    hipError_t e = hipSetDevice(pl->ctx->device);
+    if (e == hipSuccess) e = hipStreamSynchronize(pl->ctx->stream);
+    if (e == hipSuccess && b) e = hipMemcpy(b, t.b, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && a) e = hipMemcpy(a, t.a, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && c) e = hipMemcpy(c, t.c, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "weight copy");
+    return ABM_OK;
+}
+
+abm_status abm_solve(abm_plan_t* pl, const abm_problem* prob, double* y_out)
+{
+    if (!pl || !prob || !y_out) return fail(ABM_EINVAL, "NULL argument");
+    if (pl->B != 1) return fail(ABM_EINVAL, "abm_solve needs a plan made for one problem (B=%d)", pl->B);
+    if (pl->plain_G <= 0) return fail(ABM_EINVAL, "plain path unavailable: %s", pl->plain_error.c_str());
+    abm_status s = validate(*prob, 0);
+    if (s != ABM_OK) return s;
+    if (!same_shape(*prob, pl->shape[0]))
+        return fail(ABM_EINVAL, "problem does not match the plan (rhs, d, alpha, N, far_prec, out_stride)");
+    hipError_t e = hipSetDevice(pl->ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    const WeightTable& t = pl->tables[pl->table_of[0]];
+    PlainArgs A{};
+    A.b = t.b;
+    A.a = t.a;
+    A.c = t.c;
+    A.gam = t.gam;
+    A.alpha = prob->alpha;
+    A.h = prob->h;
+    for (int i = 0; i < 4; ++i) A.x0[i] = prob->x0[i];
+    for (int i = 0; i < 8; ++i) A.p[i] = prob->p[i];
+    A.N = prob->N;
+    A.G = pl->plain_G;
+    A.nloc = pl->plain_nloc;
+    A.part = pl->part;
+    A.flags = pl->flags;
+    A.y_out = y_out;
+    A.out_stride = prob->out_stride;
+    A.status = pl->status;
+    A.spin_limit = kSpinLimit;
+    e = launch_fill_u32(pl->flags, 0, pl->plain_G, pl->ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "flag reset");
+    e = launch_plain(A, prob->rhs, pl->ctx->stream);
+    if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
+    return ABM_OK;
+}
+
+}  // extern "C"
+
+namespace abm {
+
+abm_status plain_setup(abm_plan_s* pl)
+{
+    const abm_problem& p = pl->shape[0];
+    const int ch = plain_chunk();
+    const int64_t nchunks = std::max<int64_t>(1, (p.N + ch - 1) / ch);   // indices 0..N-1
+    const int nloc_max = plain_max_local_chunks(p.d);
+    int occ = 0;
+    // co-residency bound: one workgroup per CU is always possible for this kernel
+    int gcap = std::min(pl->ctx->n_cu, 256);
+    (void)occ;
+    const int gmin = (int)((nchunks + nloc_max - 1) / nloc_max);
+    if (gmin > gcap)
+        return fail(ABM_EINVAL, "N=%lld too long for the plain path (history does not fit the LDS of %d workgroups)",
+                    (long long)p.N, gcap);
+    int G = env_int("ABM_PLAIN_G", 0);
+    if (G <= 0) G = (int)std::min<int64_t>(nchunks, kPlainDefaultG);
+    G = std::max(G, gmin);
+    G = std::min(G, gcap);
+    pl->plain_G = G;
+    pl->plain_nloc = (int)((nchunks + G - 1) / G);
+    abm_status st = dev_alloc((void**)&pl->part, plain_part_doubles(G) * sizeof(double), "plain partials");
+    if (st == ABM_OK) st = dev_alloc((void**)&pl->flags, G * sizeof(uint32_t), "plain flags");
+    return st;
+}
+
+}  // namespace abm
