@@ -41,6 +41,47 @@ __device__ __forceinline__ void rhs_eval(const double* __restrict__ p, double t,
     }
 }
 
+// The part of f(t, y) that depends on t only (the forcing), so that it can be
+// evaluated ahead of a sequential chain: rhs_eval_forced(p, y, force, f)
+// equals rhs_eval(p, t, y, f) when force = forcing<R>(p, t).
+template <int R>
+__device__ __forceinline__ double forcing(const double* __restrict__ p, double t)
+{
+    if constexpr (R == ABM_RHS_DUFFING) return p[1] * cos(p[2] * t);
+    else if constexpr (R == ABM_RHS_POLY) return p[0] + p[1] * t;
+    else if constexpr (R == ABM_RHS_LCR) return p[4] * sin(p[1] * t);
+    else return 0.0;
+}
+
+template <int R, int D>
+__device__ __forceinline__ void rhs_eval_forced(const double* __restrict__ p, const double* y,
+                                                double force, double* f)
+{
+    if constexpr (R == ABM_RHS_LINEAR) {
+        f[0] = -p[0] * y[0];
+    } else if constexpr (R == ABM_RHS_DUFFING) {
+        f[0] = y[1];
+        f[1] = -p[0] * y[1] - y[0] - y[0] * y[0] * y[0] + force;
+    } else if constexpr (R == ABM_RHS_LORENZ) {
+        f[0] = p[0] * (y[1] - y[0]);
+        f[1] = y[0] * (p[1] - y[2]) - y[1];
+        f[2] = y[0] * y[1] - p[2] * y[2];
+    } else if constexpr (R == ABM_RHS_POLY) {
+        f[0] = force;
+    } else if constexpr (R == ABM_RHS_LCR) {
+        const double x = y[0];
+        double g;
+        if (x <= -1.0)
+            g = p[3] * x - p[2] + p[3];
+        else if (x >= 1.0)
+            g = p[3] * x + p[2] - p[3];
+        else
+            g = p[2] * x;
+        f[0] = y[1] - g;
+        f[1] = -p[0] * y[1] - y[0] + force;
+    }
+}
+
 // Butterfly sum over the 64 lanes of a wavefront.  Every lane ends with the
 // same bits: each stage adds a value and its partner's (x + y == y + x).
 __device__ __forceinline__ double wave_sum(double v)
@@ -67,6 +108,35 @@ template <typename T>
 __device__ __forceinline__ void st_release(T* p, T v)
 {
     __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// bf16 helpers: round-to-nearest-even of a finite float, and back.
+__device__ __forceinline__ uint16_t bf16_rn(float x)
+{
+    uint32_t u = __builtin_bit_cast(uint32_t, x);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_f(uint16_t h)
+{
+    return __builtin_bit_cast(float, (uint32_t)h << 16);
+}
+// Split x (rounded once to float) into bf16 terms t0 + t1 + t2 that carry its
+// 24 significant bits; t0 + t1 alone keep 16 of them.
+__device__ __forceinline__ void bf16_split3(double x, uint16_t* t)
+{
+    const float x32 = (float)x;
+    t[0] = bf16_rn(x32);
+    const float r1 = x32 - bf16_f(t[0]);
+    t[1] = bf16_rn(r1);
+    t[2] = bf16_rn(r1 - bf16_f(t[1]));
+}
+
+// Index of history row k >= 1, column col, in the k-blocked layout of the
+// bf16 history copies: 8 consecutive rows of one column are contiguous.
+__device__ __forceinline__ int64_t kblocked_index(int64_t k, int64_t col, int64_t ld)
+{
+    return (((k - 1) >> 3) * ld + col) * 8 + ((k - 1) & 7);
 }
 
 // Device status word bits (written with atomic OR, read by the host).

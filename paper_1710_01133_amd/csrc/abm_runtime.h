@@ -15,6 +15,7 @@ namespace abm {
 constexpr int64_t kMaxSteps = (int64_t)1 << 30;   // step counters are 32-bit on the device
 constexpr int64_t kWeightPad = 2048;                // weight tables extend this far past N
 constexpr int kPlainDefaultG = 128;
+constexpr size_t kMaxLds = 160 * 1024;              // LDS of one gfx950 CU
 constexpr uint32_t kSpinLimit = 1u << 22;           // a few seconds of polling (each poll is a memory round trip)
 
 struct ServeState;
@@ -52,6 +53,7 @@ struct Group {
     float* F32;
     uint16_t* Fh[3];
     TrajDesc* traj_dev;           // members' descriptors (device)
+    double* accn;                 // sums carried into the next block [member][2][d][L]
     TrajDesc* traj_host;          // pinned staging copy of the descriptors
     hipEvent_t traj_ev;           // recorded after the last upload from traj_host
     bool traj_ev_live;
@@ -83,9 +85,14 @@ struct abm_plan_s {
     // blocked path
     int L = 0;
     int kchunk = 0;
+    int max_split = 8;
     std::vector<abm::Group> groups;
     double* ffpart = nullptr;     // far partials, sized for the largest group
     size_t ffpart_bytes = 0;
+    // far field on its own stream, overlapping the chain
+    bool overlap = true;
+    hipStream_t far_stream = nullptr;
+    std::vector<hipEvent_t> sync_events;
     // optional per-launch timing
     bool timing = false;
     std::vector<hipEvent_t> events;

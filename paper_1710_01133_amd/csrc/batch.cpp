@@ -43,12 +43,17 @@ void batch_teardown(abm_plan_s* pl)
         dev_free(g.F32);
         for (int i = 0; i < 3; ++i) dev_free(g.Fh[i]);
         dev_free(g.traj_dev);
+        dev_free(g.accn);
         if (g.traj_host) (void)hipHostFree(g.traj_host);
         if (g.traj_ev) (void)hipEventDestroy(g.traj_ev);
     }
     pl->groups.clear();
     dev_free(pl->ffpart);
     pl->ffpart = nullptr;
+    for (hipEvent_t ev : pl->sync_events) (void)hipEventDestroy(ev);
+    pl->sync_events.clear();
+    if (pl->far_stream) (void)hipStreamDestroy(pl->far_stream);
+    pl->far_stream = nullptr;
 }
 
 abm_status batch_setup(abm_plan_s* pl)
@@ -57,18 +62,23 @@ abm_status batch_setup(abm_plan_s* pl)
     int L = env_int("ABM_BLOCK_L", 256);
     if (!valid_L(L)) return fail(ABM_EINVAL, "ABM_BLOCK_L=%d not in {64,128,256,512}", L);
     int kchunk = env_int("ABM_KCHUNK", 2048);
-    if (kchunk < 64 || kchunk % 64) return fail(ABM_EINVAL, "ABM_KCHUNK=%d must be a multiple of 64", kchunk);
-    while (kchunk > 64 && far_lds_bytes(L, kchunk, ABM_FAR_FP64) > 65536) kchunk /= 2;
+    if (kchunk < 512 || kchunk % 512)
+        return fail(ABM_EINVAL, "ABM_KCHUNK=%d must be a positive multiple of 512", kchunk);
+    for (int i = 0; i < pl->B; ++i)
+        if (pl->shape[i].far_prec != ABM_FAR_FP64 && L < 128)
+            return fail(ABM_EINVAL, "problem %d: reduced-precision far field needs block length >= 128", i);
+    // largest chunk whose LDS footprint fits every precision used by the plan
+    for (int i = 0; i < pl->B; ++i)
+        while (kchunk > 512 && far_lds_bytes(L, kchunk, pl->shape[i].far_prec) > kMaxLds) kchunk -= 512;
     pl->L = L;
     pl->kchunk = kchunk;
+    pl->max_split = env_int("ABM_MAX_SPLIT", 8);
+    if (pl->max_split < 1) return fail(ABM_EINVAL, "ABM_MAX_SPLIT must be >= 1");
 
     // groups: (weight table, rhs, precision); members sorted by N descending
     std::map<std::tuple<int, int, int>, int> key_to_group;
     for (int i = 0; i < pl->B; ++i) {
         const abm_problem& p = pl->shape[i];
-        if (p.far_prec != ABM_FAR_FP64)
-            return fail(ABM_EINVAL, "problem %d: far_prec %d is not available in this build", i,
-                        p.far_prec);
         auto key = std::make_tuple(pl->table_of[i], p.rhs, p.far_prec);
         auto it = key_to_group.find(key);
         if (it == key_to_group.end()) {
@@ -82,9 +92,9 @@ abm_status batch_setup(abm_plan_s* pl)
         }
         pl->groups[it->second].members.push_back(i);
     }
-    const int TN = far_tile_cols(L, ABM_FAR_FP64);
     size_t ff_need = 0;
     for (auto& g : pl->groups) {
+        const int TN = far_tile_cols(L, g.prec);
         std::stable_sort(g.members.begin(), g.members.end(),
                          [&](int x, int y) { return pl->shape[x].N > pl->shape[y].N; });
         g.nmax = pl->shape[g.members[0]].N;
@@ -103,25 +113,69 @@ abm_status batch_setup(abm_plan_s* pl)
             g.active_traj[m] = cnt;
             g.active_cols[m] = round_up((int64_t)cnt * g.d, TN);
         }
-        const int64_t kfar_max = (nblocks - 1) * L;
-        const int64_t nch = (kfar_max + kchunk - 1) / kchunk;
-        ff_need = std::max(ff_need, (size_t)nch * g.ldF * 2 * L * sizeof(double));
+        int nc = 0, cps = 0;
+        const int64_t kfar_max = nblocks >= 2 ? (nblocks - 2) * L : 0;   // far(m) covers (m-1)L
+        const int64_t nsp = far_split_plan(kfar_max, kchunk, pl->max_split, &nc, &cps);
+        ff_need = std::max(ff_need, (size_t)nsp * g.ldF * 2 * L * sizeof(double));
         abm_status s;
         if ((s = dev_alloc((void**)&g.F, (size_t)g.rows * g.ldF * sizeof(double), "history")))
             return s;
         hipError_t e = hipMemsetAsync(g.F, 0, (size_t)g.rows * g.ldF * sizeof(double), st);
         if (e != hipSuccess) return hip_fail(e, "history clear");
+        // reduced copies of the history read by the far field
+        if (g.prec == ABM_FAR_FP32) {
+            const size_t bytes = (size_t)g.rows * g.ldF * sizeof(float);
+            if ((s = dev_alloc((void**)&g.F32, bytes, "float history"))) return s;
+            if ((e = hipMemsetAsync(g.F32, 0, bytes, st)) != hipSuccess) return hip_fail(e, "clear");
+        } else if (g.prec == ABM_FAR_BF16X3 || g.prec == ABM_FAR_BF16X6) {
+            const int terms = g.prec == ABM_FAR_BF16X3 ? 2 : 3;
+            const size_t bytes = (size_t)((g.rows + 7) / 8) * g.ldF * 8 * sizeof(uint16_t);
+            for (int tt = 0; tt < terms; ++tt) {
+                if ((s = dev_alloc((void**)&g.Fh[tt], bytes, "bf16 history"))) return s;
+                if ((e = hipMemsetAsync(g.Fh[tt], 0, bytes, st)) != hipSuccess) return hip_fail(e, "clear");
+            }
+        }
+        // reduced copies of the weights, once per table
+        WeightTable& W = pl->tables[g.table];
+        const int64_t wn = W.n + kWeightPad;
+        if (g.prec == ABM_FAR_FP32 && !W.b32) {
+            if ((s = dev_alloc((void**)&W.b32, wn * sizeof(float), "float weights")) ||
+                (s = dev_alloc((void**)&W.a32, wn * sizeof(float), "float weights")))
+                return s;
+            uint16_t* none[3] = {nullptr, nullptr, nullptr};
+            if ((e = launch_weights_lowp(wn, W.b, W.a, W.b32, W.a32, none, none, st)) != hipSuccess)
+                return hip_fail(e, "weight conversion");
+        }
+        if ((g.prec == ABM_FAR_BF16X3 || g.prec == ABM_FAR_BF16X6) && !W.bh[2]) {
+            for (int tt = 0; tt < 3; ++tt) {
+                if (W.bh[tt]) continue;
+                if ((s = dev_alloc((void**)&W.bh[tt], wn * sizeof(uint16_t), "bf16 weights")) ||
+                    (s = dev_alloc((void**)&W.ah[tt], wn * sizeof(uint16_t), "bf16 weights")))
+                    return s;
+            }
+            if ((e = launch_weights_lowp(wn, W.b, W.a, nullptr, nullptr, W.bh, W.ah, st)) != hipSuccess)
+                return hip_fail(e, "weight conversion");
+        }
         if ((s = dev_alloc((void**)&g.traj_dev, g.members.size() * sizeof(TrajDesc), "descriptors")))
+            return s;
+        if ((s = dev_alloc((void**)&g.accn, g.members.size() * 2 * g.d * L * sizeof(double), "carried sums")))
             return s;
         e = hipHostMalloc((void**)&g.traj_host, g.members.size() * sizeof(TrajDesc), hipHostMallocDefault);
         if (e != hipSuccess) return hip_fail(e, "pinned descriptors");
         e = hipEventCreateWithFlags(&g.traj_ev, hipEventDisableTiming);
         if (e != hipSuccess) return hip_fail(e, "event");
     }
+    // two partial buffers: the far field of block m+1 is written while the
+    // chain of block m reads block m's
     pl->ffpart_bytes = ff_need;
     if (ff_need) {
-        abm_status s = dev_alloc((void**)&pl->ffpart, ff_need, "far partials");
+        abm_status s = dev_alloc((void**)&pl->ffpart, 2 * ff_need, "far partials");
         if (s) return s;
+    }
+    pl->overlap = env_int("ABM_OVERLAP", 1) != 0;
+    if (pl->overlap) {
+        hipError_t e = hipStreamCreateWithFlags(&pl->far_stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return hip_fail(e, "far stream");
     }
     return ABM_OK;
 }
@@ -161,18 +215,28 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
         }
         return pl->events[ev_used++];
     };
-    auto timed = [&](int kind, auto&& launch) -> hipError_t {
+    auto timed = [&](int kind, hipStream_t sx, auto&& launch) -> hipError_t {
         if (!pl->timing) return launch();
         hipEvent_t a = ev_next(), b = ev_next();
         if (!a || !b) return hipErrorOutOfMemory;
         const int ia = (int)ev_used - 2;
-        hipError_t e1 = hipEventRecord(a, st);
+        hipError_t e1 = hipEventRecord(a, sx);
         if (e1 != hipSuccess) return e1;
         e1 = launch();
         if (e1 != hipSuccess) return e1;
-        e1 = hipEventRecord(b, st);
+        e1 = hipEventRecord(b, sx);
         tev.push_back({kind, ia});
         return e1;
+    };
+    // ordering events (no timing), reused across calls
+    size_t sync_used = 0;
+    auto sync_event = [&]() -> hipEvent_t {
+        if (sync_used == pl->sync_events.size()) {
+            hipEvent_t ev;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+            pl->sync_events.push_back(ev);
+        }
+        return pl->sync_events[sync_used++];
     };
     S.block_L = L;
     S.n_groups = (int32_t)pl->groups.size();
@@ -227,37 +291,75 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
         FarArgs Fa{};
         Fa.b = W.b;
         Fa.a = W.a;
+        Fa.b32 = W.b32;
+        Fa.a32 = W.a32;
+        for (int tt = 0; tt < 3; ++tt) {
+            Fa.bh[tt] = W.bh[tt];
+            Fa.ah[tt] = W.ah[tt];
+            Fa.Fh[tt] = g.Fh[tt];
+        }
+        Fa.F32 = g.F32;
         Fa.F = g.F;
         Fa.ldF = g.ldF;
         Fa.kchunk = pl->kchunk;
-        Fa.part = pl->ffpart;
+        C.accn = g.accn;
+
+        // far field on s1, chain on s0; far(m+1) overlaps chain(m)
+        hipStream_t s1 = pl->overlap ? pl->far_stream : st;
         const int64_t nblocks = (int64_t)g.active_traj.size();
+        const size_t ffhalf = pl->ffpart_bytes / sizeof(double);
+        hipEvent_t fork = sync_event();
+        if (!fork) return fail(ABM_EDEVICE, "event pool");
+        if ((e = hipEventRecord(fork, st)) != hipSuccess || (e = hipStreamWaitEvent(s1, fork, 0)) != hipSuccess)
+            return hip_fail(e, "stream fork");
+        std::vector<hipEvent_t> ev_chain(nblocks, nullptr), ev_far(nblocks + 1, nullptr);
+        std::vector<int> nsplit(nblocks + 1, 0);
         for (int64_t m = 0; m < nblocks; ++m) {
-            const int64_t kfar = m * L;
-            Fa.mL = m * L;
-            Fa.kfar = kfar;
-            Fa.ldP = g.active_cols[m];
-            if (kfar >= 1) {
-                e = timed(0, [&]() { return launch_far(Fa, L, g.prec, st); });
+            const int64_t mf = m + 1;           // far field of the next block
+            if (mf < nblocks && mf >= 2) {
+                const int64_t kfar = (mf - 1) * L;
+                Fa.mL = mf * L;
+                Fa.kfar = kfar;
+                Fa.ldP = g.active_cols[mf];
+                Fa.nsplit = far_split_plan(kfar, pl->kchunk, pl->max_split, &Fa.nchunks,
+                                           &Fa.chunks_per_split);
+                Fa.part = pl->ffpart + (mf & 1) * ffhalf;
+                nsplit[mf] = Fa.nsplit;
+                if ((e = hipStreamWaitEvent(s1, ev_chain[m - 1], 0)) != hipSuccess)
+                    return hip_fail(e, "stream wait");
+                e = timed(0, s1, [&]() { return launch_far(Fa, L, g.prec, s1); });
                 if (e != hipSuccess) return hip_fail(e, "far-field launch");
                 ++S.far_launches;
-                for (int32_t j = 0; j < g.active_traj[m]; ++j) {
-                    const abm_problem& p = probs[g.members[j]];
-                    const int64_t rows = std::min<int64_t>(L, p.N - m * L);
+                for (int32_t jj = 0; jj < g.active_traj[mf]; ++jj) {
+                    const abm_problem& p = probs[g.members[jj]];
+                    const int64_t rows = std::min<int64_t>(L, p.N - mf * L);
                     S.far_macs += (int64_t)p.d * rows * kfar;
                 }
+                ev_far[mf] = sync_event();
+                if (!ev_far[mf] || (e = hipEventRecord(ev_far[mf], s1)) != hipSuccess)
+                    return fail(ABM_EDEVICE, "far event");
             }
+            if (ev_far[m] && (e = hipStreamWaitEvent(st, ev_far[m], 0)) != hipSuccess)
+                return hip_fail(e, "stream wait");
             C.ntraj = g.active_traj[m];
-            C.nchunks = (int32_t)((kfar + pl->kchunk - 1) / pl->kchunk);
+            C.nchunks = nsplit[m];
             C.ldP = g.active_cols[m];
+            C.part = pl->ffpart + (m & 1) * ffhalf;
             C.mL = m * L;
-            e = timed(1, [&]() { return launch_chain(C, g.rhs, L, st); });
+            e = timed(1, st, [&]() { return launch_chain(C, g.rhs, L, st); });
             if (e != hipSuccess) return hip_fail(e, "chain launch");
             ++S.chain_launches;
+            ev_chain[m] = sync_event();
+            if (!ev_chain[m] || (e = hipEventRecord(ev_chain[m], st)) != hipSuccess)
+                return fail(ABM_EDEVICE, "chain event");
         }
+        hipEvent_t join = sync_event();
+        if (!join || (e = hipEventRecord(join, s1)) != hipSuccess ||
+            (e = hipStreamWaitEvent(st, join, 0)) != hipSuccess)
+            return fail(ABM_EDEVICE, "stream join");
     }
     if (pl->timing && !tev.empty()) {
-        e = hipEventSynchronize(pl->events[ev_used - 1]);
+        e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "timing sync");
         for (auto& te : tev) {
             float ms = 0.f;

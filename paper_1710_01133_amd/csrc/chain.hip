@@ -1,17 +1,24 @@
 // K3: near band and predictor/corrector chain of the blocked method.
 //
 // One wavefront advances one trajectory through block m (rows r = 0..L-1,
-// step s = mL + r + 1, n = s - 1).  Lane l owns the rows r = l + 64q and keeps
-// two running sums per row and component:
-//   accP[r] = sum_{k<=n} b_{n-k} f_k   (predictor history sum of eq. abm)
-//   accC[r] = c_n f_0 + sum_{1<=k<=n} a_{n-k} f_k   (corrector history sum)
-// They start as the far-field sums (chunks added in order) plus the k = 0
-// terms; each new f_s is then scattered into every later row of the block
-// (weight index n' - s = r' - r - 1), so when row r comes up its sums are
-// complete and are broadcast from the owning lane with readlane.  The update
+// step s = mL + r + 1, n = s - 1).  The far-field product of block m covers
+// the history k = 1..(m-1)L, so it can run while block m-1 is still being
+// stepped; everything newer is handled here.  Lane l owns the rows
+// r of block m and of block m+1 and keeps, per row and component,
+//   accP = sum_k b_{n-k} f_k   (predictor history sum of eq. abm)
+//   accC = c_n f_0 + sum_{k>=1} a_{n-k} f_k   (corrector history sum)
+// Block m's sums start as the far-field partials (added in order) plus the
+// k = 0 terms plus what block m-1 scattered into them (history
+// (m-1)L+1 .. mL); block m+1's sums start at zero.  Each new f_s is scattered
+// into every later row of block m (weight index r' - r - 1) and into every row
+// of block m+1 (weight index L + r'' - r - 1), so when row r comes up its sums
+// are complete and are broadcast from the owning lane with readlane.  The
+// update
 //   yP = x0 + h^a accP,  y = x0 + h^a (accC + f(t_s, yP) / Gamma(a+2))
-// is computed identically by every lane; lane 0 stores f_s (and its reduced
-// copies for the far field) and the output states.
+// is computed identically by every lane; the lane owning row r keeps f_s and
+// y_s, and the wave writes them (and the reduced copies of f for the far
+// field) 64 rows at a time, so no memory operation sits on the sequential
+// path.  At the end of the block the next block's sums go to global memory.
 #include "abm_dev.h"
 #include "abm_kernels.h"
 
@@ -27,18 +34,6 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
-// bf16 of a float, round to nearest even (finite inputs)
-__device__ __forceinline__ uint16_t bf16_rn(float x)
-{
-    uint32_t u = __builtin_bit_cast(uint32_t, x);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-__device__ __forceinline__ float bf16_f(uint16_t h)
-{
-    return __builtin_bit_cast(float, (uint32_t)h << 16);
-}
-
 template <int D>
 __device__ __forceinline__ void store_history(const ChainArgs& A, const TrajDesc& T, int64_t s,
                                               const double* fs)
@@ -50,16 +45,15 @@ __device__ __forceinline__ void store_history(const ChainArgs& A, const TrajDesc
 #pragma unroll
         for (int i = 0; i < D; ++i) A.F32[row + i] = (float)fs[i];
     }
-    if (A.Fhi) {
+    if (A.Fhi && s >= 1) {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const float x = (float)fs[i];
-            const uint16_t hi = bf16_rn(x);
-            const float r1 = x - bf16_f(hi);
-            const uint16_t mid = bf16_rn(r1);
-            A.Fhi[row + i] = hi;
-            A.Fmid[row + i] = mid;
-            if (A.Flo) A.Flo[row + i] = bf16_rn(r1 - bf16_f(mid));
+            uint16_t t[3];
+            bf16_split3(fs[i], t);
+            const int64_t at = kblocked_index(s, T.col0 + i, A.ldF);
+            A.Fhi[at] = t[0];
+            A.Fmid[at] = t[1];
+            if (A.Flo) A.Flo[at] = t[2];
         }
     }
 }
@@ -85,8 +79,8 @@ template <int R, int D, int L>
 __global__ __launch_bounds__(256) void k_chain(ChainArgs A)
 {
     constexpr int Q = L / 64;
-    __shared__ double swb[L], swa[L];
-    for (int x = threadIdx.x; x < L; x += 256) {
+    __shared__ double swb[2 * L], swa[2 * L];
+    for (int x = threadIdx.x; x < 2 * L; x += 256) {
         swb[x] = A.b[x];
         swa[x] = A.a[x];
     }
@@ -99,6 +93,7 @@ __global__ __launch_bounds__(256) void k_chain(ChainArgs A)
     const int64_t mL = A.mL;
     if (mL >= T.N) return;
     const int rows = (int)((T.N - mL) < L ? (T.N - mL) : L);
+    const bool more = T.N > mL + L;           // a next block follows
 
     double x0[D], F0[D], p[8];
 #pragma unroll
@@ -107,14 +102,17 @@ __global__ __launch_bounds__(256) void k_chain(ChainArgs A)
     for (int i = 0; i < 8; ++i) p[i] = T.p[i];
     const double h = T.h;
     const double ha = pow(h, A.alpha);
-    const double g2 = A.gam[1];
+    const double g2inv = 1.0 / A.gam[1];
 #pragma unroll
     for (int i = 0; i < D; ++i) F0[i] = A.F[T.col0 + i];
 
-    double accP[Q][D], accC[Q][D];
+    const int r0 = Q * lane;                  // first row of this lane
+    // carried sums of block m (written by the previous block's chain)
+    double* accn = A.accn + (size_t)j * 2 * D * L;
+    double accP[Q][D], accC[Q][D], nxtP[Q][D], nxtC[Q][D];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        const int r = lane + 64 * q;
+        const int r = r0 + q;
         const int64_t n = mL + r;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -124,49 +122,120 @@ __global__ __launch_bounds__(256) void k_chain(ChainArgs A)
                 sp += pc[r];
                 sc += pc[L + r];
             }
-            accP[q][i] = sp + A.b[n] * F0[i];
-            accC[q][i] = sc + A.c[n] * F0[i];
+            sp += A.b[n] * F0[i];
+            sc += A.c[n] * F0[i];
+            if (mL > 0) {
+                sp += accn[i * L + r];
+                sc += accn[(D + i) * L + r];
+            }
+            accP[q][i] = sp;
+            accC[q][i] = sc;
+            nxtP[q][i] = 0.0;
+            nxtC[q][i] = 0.0;
         }
     }
 
+    // forcing terms of this lane's rows, evaluated off the sequential chain
+    double frc[Q];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) frc[q] = forcing<R>(p, (double)(mL + r0 + q + 1) * h);
+
+    // weight rings: at step r slot (x mod Q) holds w[x] for x = r0-r-1 .. r0-r-2+Q
+    // (block m rows, zero for x < 0) and w[L + x] (block m+1 rows)
+    double rbc[Q], rac[Q], rbn[Q], ran[Q];
+#pragma unroll
+    for (int i = 0; i < Q; ++i) {
+        const int x = r0 - 1 + i;
+        const int sl = (x % Q + Q) % Q;
+        rbc[sl] = x < 0 ? 0.0 : swb[x < 0 ? 0 : x];
+        rac[sl] = x < 0 ? 0.0 : swa[x < 0 ? 0 : x];
+        rbn[sl] = swb[L + x];
+        ran[sl] = swa[L + x];
+    }
+
+    double myF[Q][D], myY[Q][D];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+        for (int i = 0; i < D; ++i) myF[q][i] = myY[q][i] = 0.0;
+
+    for (int rb = 0; rb < rows; rb += Q) {
+#pragma unroll
+        for (int jq = 0; jq < Q; ++jq) {
+            const int r = rb + jq;             // r mod Q == jq
+            if (r < rows) {
+                const int owner = r / Q;
+                // the weight entering the rings after this step: x = r0 - r - 2
+                const int xn = r0 - r - 2;
+                const double nbc = xn < 0 ? 0.0 : swb[xn < 0 ? 0 : xn];
+                const double nac = xn < 0 ? 0.0 : swa[xn < 0 ? 0 : xn];
+                const double nbn = swb[L + xn];
+                const double nan_ = swa[L + xn];
+                const int64_t s = mL + r + 1;
+                (void)s;
+                double P[D], C[D], yP[D], fP[D], y[D], fs[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    P[i] = readlane_d(accP[jq][i], owner);
+                    C[i] = readlane_d(accC[jq][i], owner);
+                }
+                const double force = readlane_d(frc[jq], owner);
+#pragma unroll
+                for (int i = 0; i < D; ++i) yP[i] = x0[i] + ha * P[i];
+                rhs_eval_forced<R, D>(p, yP, force, fP);
+#pragma unroll
+                for (int i = 0; i < D; ++i) y[i] = x0[i] + ha * (C[i] + fP[i] * g2inv);
+                rhs_eval_forced<R, D>(p, y, force, fs);
+                const bool mine = lane == owner;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    myF[jq][i] = mine ? fs[i] : myF[jq][i];
+                    myY[jq][i] = mine ? y[i] : myY[jq][i];
+                }
+                // scatter f_s: row r0+q gets w[r0+q-r-1] (block m) and w[L+r0+q-r-1]
+                // (block m+1); that weight sits in slot (q - jq - 1) mod Q
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    const int sl = ((q - jq - 1) % Q + Q) % Q;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        accP[q][i] = fma(rbc[sl], fs[i], accP[q][i]);
+                        accC[q][i] = fma(rac[sl], fs[i], accC[q][i]);
+                        nxtP[q][i] = fma(rbn[sl], fs[i], nxtP[q][i]);
+                        nxtC[q][i] = fma(ran[sl], fs[i], nxtC[q][i]);
+                    }
+                }
+                // slide the rings: x = r0 - r - 2 replaces x = r0 - r - 2 + Q
+                const int sn = ((-jq - 2) % Q + Q) % Q;
+                rbc[sn] = nbc;
+                rac[sn] = nac;
+                rbn[sn] = nbn;
+                ran[sn] = nan_;
+            }
+        }
+    }
+
+    // history rows, reduced copies and output states of this lane's rows
     bool bad = false;
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
-        for (int rr = 0; rr < 64; ++rr) {
-            const int r = 64 * q + rr;
-            if (r >= rows) break;
+        const int r = r0 + q;
+        if (r < rows) {
             const int64_t s = mL + r + 1;
-            const double td = (double)s * h;
-            double P[D], C[D], yP[D], fP[D], y[D], fs[D];
+            store_history<D>(A, T, s, myF[q]);
+            store_output<D>(T, s, myY[q]);
+#pragma unroll
+            for (int i = 0; i < D; ++i) bad |= !isfinite(myY[q][i]);
+        }
+    }
+    if (more) {
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int r = r0 + q;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                P[i] = readlane_d(accP[q][i], rr);
-                C[i] = readlane_d(accC[q][i], rr);
-            }
-#pragma unroll
-            for (int i = 0; i < D; ++i) yP[i] = x0[i] + ha * P[i];
-            rhs_eval<R, D>(p, td, yP, fP);
-#pragma unroll
-            for (int i = 0; i < D; ++i) y[i] = x0[i] + ha * (C[i] + fP[i] / g2);
-            rhs_eval<R, D>(p, td, y, fs);
-            if (lane == 0) {
-                store_history<D>(A, T, s, fs);
-                store_output<D>(T, s, y);
-#pragma unroll
-                for (int i = 0; i < D; ++i) bad |= !isfinite(y[i]);
-            }
-            // scatter f_s into the later rows of the block
-#pragma unroll
-            for (int q2 = 0; q2 < Q; ++q2) {
-                const int widx = lane + 64 * q2 - r - 1;
-                if (widx >= 0) {
-                    const double wbv = swb[widx], wav = swa[widx];
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        accP[q2][i] = fma(wbv, fs[i], accP[q2][i]);
-                        accC[q2][i] = fma(wav, fs[i], accC[q2][i]);
-                    }
-                }
+                accn[i * L + r] = nxtP[q][i];
+                accn[(D + i) * L + r] = nxtC[q][i];
             }
         }
     }

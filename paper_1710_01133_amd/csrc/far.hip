@@ -10,15 +10,15 @@
 // The k = 0 terms (b_n f_0, c_n f_0) and the near band are added by the chain
 // kernel.
 //
-// Tiling: one workgroup computes all 2L rows for 16*NT columns over one fixed
-// history chunk [k_lo, k_hi) (chunk boundaries depend only on m, never on
-// which trajectories are batched, so every column's arithmetic is the same
-// alone or in a batch).  Each of the 4 waves owns L/2 rows (MT = L/32 tiles
+// Tiling: one workgroup computes all 2L rows for 16*NT columns over a fixed
+// range of history chunks [k_lo, k_hi) (chunk boundaries and their grouping
+// depend only on m, never on which trajectories are batched, so every
+// column's arithmetic is the same alone or in a batch).  Each of the 4 waves owns L/2 rows (MT = L/32 tiles
 // of 16 rows); every 16x16 output tile is a chain of matrix-core products
 // over 4-row slices of the history.  The Toeplitz operand is never formed:
 // lane (i, kk) of a fragment reads the weight at index mL + r - k from an LDS
-// copy of the chunk's weight window.  Partial results of each chunk go to
-// FFpart[chunk][col][2L]; the chain kernel adds the chunks in order.
+// copy of the chunk's weight window.  The partial result of each workgroup
+// goes to FFpart[split][col][2L]; the chain kernel adds the splits in order.
 #include "abm_dev.h"
 #include "abm_kernels.h"
 
@@ -43,20 +43,7 @@ __global__ __launch_bounds__(256) void k_far_f64(FarArgs A)
 
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int col0 = blockIdx.x * TN;
-    const int chunk = blockIdx.y;
-    const int64_t k_lo = 1 + (int64_t)chunk * A.kchunk;
-    int64_t k_hi = k_lo + A.kchunk;
-    if (k_hi > A.kfar + 1) k_hi = A.kfar + 1;
     const int64_t mL = A.mL;
-    const int nk = (int)(k_hi - k_lo);                    // multiple of kKS
-    const int64_t jb = mL - k_hi + 1;                     // lowest weight index used (>= 0)
-    const int wlen = L + nk - 1;
-
-    for (int x = t; x < wlen; x += 256) {
-        wb[x] = A.b[jb + x];
-        wa[x] = A.a[jb + x];
-    }
-
     // rows of this wave: waves 0,1 predictor rows, waves 2,3 corrector rows
     const bool corr = wid >= 2;
     const int rbase = (wid & 1) * (L / 2);
@@ -93,37 +80,54 @@ __global__ __launch_bounds__(256) void k_far_f64(FarArgs A)
         }
     };
 
-    load_stage(k_lo);
-    store_stage(0);
-    __syncthreads();
-    const int nstages = nk / kKS;
-    for (int st = 0; st < nstages; ++st) {
-        const int buf = st & 1;
-        if (st + 1 < nstages) load_stage(k_lo + (int64_t)(st + 1) * kKS);
-        const double* Fs = Ft + buf * kStageElems;
-#pragma unroll
-        for (int kq = 0; kq < kKS / 4; ++kq) {
-            // history index of this lane's fragment column
-            const int64_t k = k_lo + (int64_t)st * kKS + kq * 4 + lk;
-            double bf[NT];
-#pragma unroll
-            for (int j = 0; j < NT; ++j) bf[j] = Fs[(kq * 4 + lk) * TN + j * 16 + li];
-#pragma unroll
-            for (int i = 0; i < MT; ++i) {
-                const int r = rbase + i * 16 + li;
-                const double af = wwin[(int)(mL + r - k - jb)];
-#pragma unroll
-                for (int j = 0; j < NT; ++j)
-                    acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[j], acc[i][j], 0, 0, 0);
-            }
+    // this workgroup's fixed range of history chunks, summed in order
+    const int c_begin = blockIdx.y * A.chunks_per_split;
+    int c_end = c_begin + A.chunks_per_split;
+    if (c_end > A.nchunks) c_end = A.nchunks;
+    for (int chunk = c_begin; chunk < c_end; ++chunk) {
+        const int64_t k_lo = 1 + (int64_t)chunk * A.kchunk;
+        int64_t k_hi = k_lo + A.kchunk;
+        if (k_hi > A.kfar + 1) k_hi = A.kfar + 1;
+        const int nk = (int)(k_hi - k_lo);                    // multiple of kKS
+        const int64_t jb = mL - k_hi + 1;                     // lowest weight index used (>= 0)
+        const int wlen = L + nk - 1;
+        __syncthreads();   // previous chunk's readers are done with the LDS
+        for (int x = t; x < wlen; x += 256) {
+            wb[x] = A.b[jb + x];
+            wa[x] = A.a[jb + x];
         }
-        if (st + 1 < nstages) store_stage(buf ^ 1);
+        load_stage(k_lo);
+        store_stage(0);
         __syncthreads();
+        const int nstages = nk / kKS;
+        for (int st = 0; st < nstages; ++st) {
+            const int buf = st & 1;
+            if (st + 1 < nstages) load_stage(k_lo + (int64_t)(st + 1) * kKS);
+            const double* Fs = Ft + buf * kStageElems;
+#pragma unroll
+            for (int kq = 0; kq < kKS / 4; ++kq) {
+                // history index of this lane's fragment column
+                const int64_t k = k_lo + (int64_t)st * kKS + kq * 4 + lk;
+                double bf[NT];
+#pragma unroll
+                for (int j = 0; j < NT; ++j) bf[j] = Fs[(kq * 4 + lk) * TN + j * 16 + li];
+#pragma unroll
+                for (int i = 0; i < MT; ++i) {
+                    const int r = rbase + i * 16 + li;
+                    const double af = wwin[(int)(mL + r - k - jb)];
+#pragma unroll
+                    for (int j = 0; j < NT; ++j)
+                        acc[i][j] = __builtin_amdgcn_mfma_f64_16x16x4f64(af, bf[j], acc[i][j], 0, 0, 0);
+                }
+            }
+            if (st + 1 < nstages) store_stage(buf ^ 1);
+            __syncthreads();
+        }
     }
 
-    // FFpart[chunk][col][2L].  The double 16x16x4 product returns row
+    // FFpart[split][col][2L].  The double 16x16x4 product returns row
     // lk + 4v of column li of the tile in register v of lane (li, lk).
-    double* out = A.part + (size_t)chunk * A.ldP * (2 * L);
+    double* out = A.part + (size_t)blockIdx.y * A.ldP * (2 * L);
     const int prow = (corr ? L : 0) + rbase;
 #pragma unroll
     for (int i = 0; i < MT; ++i)
@@ -137,11 +141,13 @@ __global__ __launch_bounds__(256) void k_far_f64(FarArgs A)
 }
 
 template <int MT, int NT>
-hipError_t launch_t(const FarArgs& A, int nchunks, hipStream_t st)
+hipError_t launch_t(const FarArgs& A, hipStream_t st)
 {
     constexpr int L = 32 * MT, TN = 16 * NT;
     const size_t shmem = (2 * (size_t)(L + A.kchunk) + 2 * kKS * TN) * sizeof(double);
-    dim3 grid((unsigned)(A.ldP / TN), (unsigned)nchunks);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_f64<MT, NT>), shmem);
+    if (e != hipSuccess) return e;
+    dim3 grid((unsigned)(A.ldP / TN), (unsigned)A.nsplit);
     hipLaunchKernelGGL((k_far_f64<MT, NT>), grid, dim3(256), shmem, st, A);
     return hipGetLastError();
 }
@@ -150,7 +156,7 @@ hipError_t launch_t(const FarArgs& A, int nchunks, hipStream_t st)
 
 int far_tile_cols(int L, int prec)
 {
-    (void)prec;
+    if (prec != ABM_FAR_FP64) return 16;
     switch (L) {
     case 64: return 128;
     case 128: return 64;
@@ -164,20 +170,40 @@ int far_stage_rows() { return kKS; }
 
 size_t far_lds_bytes(int L, int kchunk, int prec)
 {
-    (void)prec;
+    if (prec != ABM_FAR_FP64) return far_lp_lds_bytes(L, kchunk, prec);
     return (2 * (size_t)(L + kchunk) + 2 * kKS * far_tile_cols(L, prec)) * sizeof(double);
+}
+
+hipError_t allow_lds(const void* fn, size_t bytes)
+{
+    if (bytes <= 65536) return hipSuccess;
+    return hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+int far_split_plan(int64_t kfar, int kchunk, int max_split, int* nchunks, int* chunks_per_split)
+{
+    if (kfar < 1) {
+        *nchunks = 0;
+        *chunks_per_split = 0;
+        return 0;
+    }
+    const int nc = (int)((kfar + kchunk - 1) / kchunk);
+    const int ns0 = nc < max_split ? nc : max_split;
+    const int cps = (nc + ns0 - 1) / ns0;
+    *nchunks = nc;
+    *chunks_per_split = cps;
+    return (nc + cps - 1) / cps;
 }
 
 hipError_t launch_far(const FarArgs& A, int L, int prec, hipStream_t st)
 {
-    (void)prec;
-    if (A.kfar < 1) return hipSuccess;
-    const int nchunks = (int)((A.kfar + A.kchunk - 1) / A.kchunk);
+    if (A.kfar < 1 || A.nsplit < 1) return hipSuccess;
+    if (prec != ABM_FAR_FP64) return launch_far_lp(A, L, prec, st);
     switch (L) {
-    case 64: return launch_t<2, 8>(A, nchunks, st);
-    case 128: return launch_t<4, 4>(A, nchunks, st);
-    case 256: return launch_t<8, 2>(A, nchunks, st);
-    case 512: return launch_t<16, 1>(A, nchunks, st);
+    case 64: return launch_t<2, 8>(A, st);
+    case 128: return launch_t<4, 4>(A, st);
+    case 256: return launch_t<8, 2>(A, st);
+    case 512: return launch_t<16, 1>(A, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,356 @@
+// K2 in reduced precision: the far-field products of the blocked method with
+// the weights and the history rounded once to float, or split into bf16
+// terms, on the matrix cores.  The sums are the same as in far.hip:
+//   FF[r]     = sum_{k=1..K} b_{mL+r-k} F_k,   FF[L + r] = sum_{k=1..K} a_{mL+r-k} F_k.
+// Accumulation is float only inside short runs of history rows (one 32-row
+// bf16 product step, or 16 rows of float products): their results are then
+// added into double accumulators, so float rounding is never applied to a
+// sum that has grown over many rows.  A workgroup walks a fixed range of
+// history chunks, carrying the double sums, and writes one partial per
+// column; the chain adds the partials of the block in double.
+//
+// bf16 split: x ~ x0 + x1 (+ x2) with x0 = bf16(x), x1 = bf16(x - x0), ...
+// (the float value of x is carried exactly by three terms).  Products kept:
+//   bf16x3: w0 F0 + w0 F1 + w1 F0
+//   bf16x6: the above + w1 F1 + w0 F2 + w2 F0
+// so the dropped products are below 2^-16 (x3) and 2^-24 (x6) of w F.
+//
+// Tiling: a workgroup of 8 waves computes all 2L rows of the block for 16
+// columns; waves 0-3 hold L/4 predictor rows each, waves 4-7 the corrector
+// rows, so every SIMD runs two waves and one wave's double flushes run under
+// the other's matrix work.  Reduced precision needs L >= 128.
+//
+// Operand layout of the bf16 16x16x32 product: lane (li = lane%16, g = lane/16)
+// supplies row li, history rows 8g..8g+7 of the A fragment and column li,
+// the same history rows of the B fragment; the result row 4g + v, column li
+// sits in register v.  The Toeplitz A fragment of M-tile t at K-step q starts
+// at LDS offset  L-1-rbase-li + 8g + 32q - 16t  of the reversed weight window,
+// so fragment(t, q) = fragment(t+2, q+1): a ring of MT fragments per split
+// term is kept in registers and only two new ones are read per K-step (the
+// 2-byte-aligned 16-byte LDS reads are single ds_read_b128 on gfx950).
+#include "abm_dev.h"
+#include "abm_kernels.h"
+
+namespace abm {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef unsigned u4 __attribute__((ext_vector_type(4)));
+
+struct ChunkBounds {
+    int64_t k_lo, k_hi, jb;
+    int nk, wlen;
+};
+
+__device__ __forceinline__ ChunkBounds chunk_bounds(const FarArgs& A, int L, int chunk)
+{
+    ChunkBounds c;
+    c.k_lo = 1 + (int64_t)chunk * A.kchunk;
+    c.k_hi = c.k_lo + A.kchunk;
+    if (c.k_hi > A.kfar + 1) c.k_hi = A.kfar + 1;
+    c.nk = (int)(c.k_hi - c.k_lo);
+    c.jb = A.mL - c.k_hi + 1;
+    c.wlen = L + c.nk - 1;
+    return c;
+}
+
+template <int MT, int NT>
+__device__ __forceinline__ void flush_acc(f4 (&acc)[MT][NT], d4 (&acc64)[MT][NT])
+{
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) acc64[i][j][v] += (double)acc[i][j][v];
+            acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+}
+
+// Result of the workgroup: FFpart[split][col][2L]; float/bf16 products return
+// row 4g + v of column li of a tile in register v of lane (li, g).
+template <int MT, int NT>
+__device__ __forceinline__ void store_part(const FarArgs& A, const d4 (&acc64)[MT][NT], int col0,
+                                           int prow, int li, int g, int L)
+{
+    double* out = A.part + (size_t)blockIdx.y * A.ldP * (2 * L);
+#pragma unroll
+    for (int i = 0; i < MT; ++i)
+#pragma unroll
+        for (int j = 0; j < NT; ++j) {
+            double* o = out + (size_t)(col0 + j * 16 + li) * (2 * L) + prow + i * 16 + 4 * g;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) o[v] = acc64[i][j][v];
+        }
+}
+
+// ------------------------------------------------------------------ float
+// 8 waves: waves 0-3 own predictor rows, 4-7 corrector rows, L/4 rows each.
+template <int MT>
+__global__ __launch_bounds__(512, (MT <= 8) ? 1 : 1) void k_far_f32(FarArgs A)
+{
+    constexpr int L = 64 * MT, TN = 16;
+    constexpr int KS = 32;                      // history rows per LDS stage
+    constexpr int kFlushSteps = 4;              // 16 history rows per float run
+    extern __shared__ float smf[];
+    const int win = L + A.kchunk;
+    float* wb = smf;
+    float* wa = smf + win;
+    float* Ft = smf + 2 * win;                  // [2][KS][TN]
+
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int col0 = blockIdx.x * TN;
+    const int64_t mL = A.mL;
+    const bool corr = wid >= 4;
+    const int rbase = (wid & 3) * (L / 4);
+    const float* wwin = corr ? wa : wb;
+    const int li = lane & 15, lk = lane >> 4;
+
+    f4 acc[MT][1];
+    d4 acc64[MT][1];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+        acc[i][0] = f4{0.f, 0.f, 0.f, 0.f};
+        acc64[i][0] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+    constexpr int kStageElems = KS * TN;        // 512: one element per thread
+    float pre = 0.f;
+    auto load_stage = [&](int64_t k0) { pre = A.F32[(k0 + t / TN) * A.ldF + col0 + t % TN]; };
+    auto store_stage = [&](int buf) { Ft[buf * kStageElems + t] = pre; };
+
+    const int c_begin = blockIdx.y * A.chunks_per_split;
+    int c_end = c_begin + A.chunks_per_split;
+    if (c_end > A.nchunks) c_end = A.nchunks;
+    for (int chunk = c_begin; chunk < c_end; ++chunk) {
+        const ChunkBounds cb = chunk_bounds(A, L, chunk);
+        __syncthreads();   // previous chunk's readers are done with the LDS
+        for (int x = t; x < cb.wlen; x += 512) {
+            wb[x] = A.b32[cb.jb + x];
+            wa[x] = A.a32[cb.jb + x];
+        }
+        load_stage(cb.k_lo);
+        store_stage(0);
+        __syncthreads();
+        const int nstages = cb.nk / KS;
+        for (int st = 0; st < nstages; ++st) {
+            const int buf = st & 1;
+            if (st + 1 < nstages) load_stage(cb.k_lo + (int64_t)(st + 1) * KS);
+            const float* Fs = Ft + buf * kStageElems;
+#pragma unroll
+            for (int kq = 0; kq < KS / 4; ++kq) {
+                const int64_t k = cb.k_lo + (int64_t)st * KS + kq * 4 + lk;
+                const float bf = Fs[(kq * 4 + lk) * TN + li];
+#pragma unroll
+                for (int i = 0; i < MT; ++i) {
+                    const int r = rbase + i * 16 + li;
+                    const float af = wwin[(int)(mL + r - k - cb.jb)];
+                    acc[i][0] = __builtin_amdgcn_mfma_f32_16x16x4f32(af, bf, acc[i][0], 0, 0, 0);
+                }
+                if ((kq + 1) % kFlushSteps == 0) flush_acc<MT, 1>(acc, acc64);
+            }
+            if (st + 1 < nstages) store_stage(buf ^ 1);
+            __syncthreads();
+        }
+    }
+    store_part<MT, 1>(A, acc64, col0, (corr ? L : 0) + rbase, li, lk, L);
+}
+
+// ------------------------------------------------------------------ bf16 split
+template <int MT, int TERMS>
+__global__ __launch_bounds__(512, 1) void k_far_bf16(FarArgs A)
+{
+    constexpr int L = 64 * MT, TN = 16;
+    constexpr int QS = 4;                       // K-steps (32 rows) per stage
+    constexpr int KS = 32 * QS;                 // history rows per stage
+    constexpr int NB8 = KS / 8;                 // 8-row blocks per stage
+    constexpr int kStageU4 = TERMS * NB8 * TN;  // 16-byte units per stage
+    static_assert((2 * QS) % MT == 0, "ring slots must repeat within a stage");
+    extern __shared__ __attribute__((aligned(16))) uint16_t smh[];
+    const int win = L + A.kchunk;               // multiple of 8
+    uint16_t* wrb = smh;                        // [TERMS][win] reversed b windows
+    uint16_t* wra = smh + TERMS * win;          // [TERMS][win] reversed a windows
+    u4* Bst = reinterpret_cast<u4*>(smh + 2 * TERMS * win);   // [2][TERMS][NB8][TN]
+
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int col0 = blockIdx.x * TN;
+    const bool corr = wid >= 4;
+    const int rbase = (wid & 3) * (L / 4);
+    const uint16_t* wr = corr ? wra : wrb;
+    const int li = lane & 15, g = lane >> 4;
+    const int abase = L - 1 - rbase - li + 8 * g;   // fragment v starts at abase + 16 v
+
+    f4 acc[MT][1];
+    d4 acc64[MT][1];
+#pragma unroll
+    for (int i = 0; i < MT; ++i) {
+        acc[i][0] = f4{0.f, 0.f, 0.f, 0.f};
+        acc64[i][0] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+    constexpr int kPerThread = (kStageU4 + 511) / 512;
+    u4 pre[kPerThread];
+    auto load_stage = [&](int64_t kb8, int st) {
+#pragma unroll
+        for (int e = 0; e < kPerThread; ++e) {
+            const int idx = t + e * 512;
+            if (idx < kStageU4) {
+                const int tt = idx / (NB8 * TN);
+                const int rem = idx % (NB8 * TN);
+                const int b = rem / TN, c = rem % TN;
+                const int64_t blk = kb8 + (int64_t)st * NB8 + b;
+                pre[e] = *reinterpret_cast<const u4*>(A.Fh[tt] + (blk * A.ldF + col0 + c) * 8);
+            }
+        }
+    };
+    auto store_stage = [&](int buf) {
+#pragma unroll
+        for (int e = 0; e < kPerThread; ++e) {
+            const int idx = t + e * 512;
+            if (idx < kStageU4) Bst[buf * kStageU4 + idx] = pre[e];
+        }
+    };
+    auto afrag = [&](int tt, int v) -> bf8 {
+        u4 x;
+        __builtin_memcpy(&x, wr + tt * win + abase + 16 * v, 16);
+        return __builtin_bit_cast(bf8, x);
+    };
+
+    const int c_begin = blockIdx.y * A.chunks_per_split;
+    int c_end = c_begin + A.chunks_per_split;
+    if (c_end > A.nchunks) c_end = A.nchunks;
+    for (int chunk = c_begin; chunk < c_end; ++chunk) {
+        const ChunkBounds cb = chunk_bounds(A, L, chunk);
+        const int64_t kb8 = (cb.k_lo - 1) >> 3;
+        __syncthreads();   // previous chunk's readers are done with the LDS
+        // reversed windows: wr[x] = w[jb + wlen - 1 - x]
+        for (int x = t; x < cb.wlen; x += 512) {
+            const int64_t j = cb.jb + cb.wlen - 1 - x;
+#pragma unroll
+            for (int tt = 0; tt < TERMS; ++tt) {
+                wrb[tt * win + x] = A.bh[tt][j];
+                wra[tt * win + x] = A.ah[tt][j];
+            }
+        }
+        load_stage(kb8, 0);
+        store_stage(0);
+        __syncthreads();
+        // ring[tt][slot]: fragment v lives in slot v mod MT; start with v = -(MT-1) .. 0
+        bf8 ring[TERMS][MT];
+#pragma unroll
+        for (int tt = 0; tt < TERMS; ++tt)
+#pragma unroll
+            for (int tm = 0; tm < MT; ++tm) ring[tt][(MT - tm) % MT] = afrag(tt, -tm);
+
+        const int nstages = cb.nk / KS;
+        for (int st = 0; st < nstages; ++st) {
+            const int buf = st & 1;
+            if (st + 1 < nstages) load_stage(kb8, st + 1);
+            const u4* Bs = Bst + buf * kStageU4;
+#pragma unroll
+            for (int qq = 0; qq < QS; ++qq) {
+                const int q = st * QS + qq;
+                if (qq > 0 || st > 0) {
+                    // fragments v = 2q-1 and 2q replace v = 2q-1-MT and 2q-MT
+#pragma unroll
+                    for (int tt = 0; tt < TERMS; ++tt) {
+                        ring[tt][(2 * qq - 1 + 2 * QS) % MT] = afrag(tt, 2 * q - 1);
+                        ring[tt][(2 * qq) % MT] = afrag(tt, 2 * q);
+                    }
+                }
+                bf8 bfr[TERMS];
+#pragma unroll
+                for (int tt = 0; tt < TERMS; ++tt)
+                    bfr[tt] = __builtin_bit_cast(bf8, Bs[(tt * NB8 + 4 * qq + g) * TN + li]);
+                // small products first, the leading w0 F0 last
+                constexpr int NP = (TERMS == 2) ? 3 : 6;
+                constexpr int pa[6] = {2, 0, 1, 1, 0, 0};
+                constexpr int pb[6] = {0, 2, 1, 0, 1, 0};
+                constexpr int p0 = (TERMS == 2) ? 3 : 0;
+#pragma unroll
+                for (int pp = p0; pp < p0 + NP; ++pp) {
+#pragma unroll
+                    for (int tm = 0; tm < MT; ++tm) {
+                        const bf8 af = ring[pa[pp]][(2 * qq - tm + 2 * QS * MT) % MT];
+                        acc[tm][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[pb[pp]],
+                                                                             acc[tm][0], 0, 0, 0);
+                    }
+                }
+                flush_acc<MT, 1>(acc, acc64);   // one 32-row step per float run
+            }
+            if (st + 1 < nstages) store_stage(buf ^ 1);
+            __syncthreads();
+        }
+    }
+    store_part<MT, 1>(A, acc64, col0, (corr ? L : 0) + rbase, li, g, L);
+}
+
+template <int MT>
+hipError_t launch_f32_t(const FarArgs& A, hipStream_t st)
+{
+    constexpr int L = 64 * MT, TN = 16;
+    const size_t shmem = far_lp_lds_bytes(L, A.kchunk, ABM_FAR_FP32);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_f32<MT>), shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_far_f32<MT>), dim3((unsigned)(A.ldP / TN), (unsigned)A.nsplit),
+                       dim3(512), shmem, st, A);
+    return hipGetLastError();
+}
+
+template <int MT, int TERMS>
+hipError_t launch_bf16_t(const FarArgs& A, hipStream_t st)
+{
+    constexpr int L = 64 * MT, TN = 16;
+    const size_t shmem =
+        far_lp_lds_bytes(L, A.kchunk, TERMS == 2 ? ABM_FAR_BF16X3 : ABM_FAR_BF16X6);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_bf16<MT, TERMS>), shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_far_bf16<MT, TERMS>), dim3((unsigned)(A.ldP / TN), (unsigned)A.nsplit),
+                       dim3(512), shmem, st, A);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+size_t far_lp_lds_bytes(int L, int kchunk, int prec)
+{
+    const int TN = 16;
+    if (prec == ABM_FAR_FP32) return (2 * (size_t)(L + kchunk) + 2 * 32 * TN) * sizeof(float);
+    const int terms = prec == ABM_FAR_BF16X3 ? 2 : 3;
+    // reversed weight windows + two history stages of 128 rows
+    return 2 * (size_t)terms * (L + kchunk) * 2 + 2 * (size_t)terms * (128 / 8) * TN * 16;
+}
+
+hipError_t launch_far_lp(const FarArgs& A, int L, int prec, hipStream_t st)
+{
+    if (prec == ABM_FAR_FP32) {
+        switch (L) {
+        case 128: return launch_f32_t<2>(A, st);
+        case 256: return launch_f32_t<4>(A, st);
+        case 512: return launch_f32_t<8>(A, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (prec == ABM_FAR_BF16X3) {
+        switch (L) {
+        case 128: return launch_bf16_t<2, 2>(A, st);
+        case 256: return launch_bf16_t<4, 2>(A, st);
+        case 512: return launch_bf16_t<8, 2>(A, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (prec == ABM_FAR_BF16X6) {
+        switch (L) {
+        case 128: return launch_bf16_t<2, 3>(A, st);
+        case 256: return launch_bf16_t<4, 3>(A, st);
+        case 512: return launch_bf16_t<8, 3>(A, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace abm

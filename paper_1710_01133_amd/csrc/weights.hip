@@ -125,7 +125,45 @@ __global__ void k_gammas(double al, double* g)
     }
 }
 
+// Reduced copies of b and a for the far field: float, and the bf16 split
+// terms (see bf16_split3).  Any output pointer may be null.
+__global__ __launch_bounds__(256) void k_weights_lowp(int64_t n, const double* __restrict__ b,
+                                                      const double* __restrict__ a, float* b32,
+                                                      float* a32, uint16_t* bh0, uint16_t* bh1,
+                                                      uint16_t* bh2, uint16_t* ah0, uint16_t* ah1,
+                                                      uint16_t* ah2)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < n; k += stride) {
+        const double bk = b[k], ak = a[k];
+        if (b32) b32[k] = (float)bk;
+        if (a32) a32[k] = (float)ak;
+        if (bh0) {
+            uint16_t t[3];
+            bf16_split3(bk, t);
+            bh0[k] = t[0];
+            bh1[k] = t[1];
+            if (bh2) bh2[k] = t[2];
+            bf16_split3(ak, t);
+            ah0[k] = t[0];
+            ah1[k] = t[1];
+            if (ah2) ah2[k] = t[2];
+        }
+    }
+}
+
 }  // namespace
+
+hipError_t launch_weights_lowp(int64_t n, const double* b, const double* a, float* b32, float* a32,
+                               uint16_t* const* bh, uint16_t* const* ah, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    hipLaunchKernelGGL(k_weights_lowp, dim3((unsigned)blocks), dim3(256), 0, st, n, b, a, b32, a32,
+                       bh[0], bh[1], bh[2], ah[0], ah[1], ah[2]);
+    return hipGetLastError();
+}
 
 hipError_t launch_weights(double alpha, int64_t n, double* gam, double* b, double* a, double* c,
                           hipStream_t st)

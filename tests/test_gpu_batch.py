@@ -30,6 +30,7 @@ def _sweep(Ns, alpha=0.95, h=2 ** -6, seed=7):
 def test_batch_ragged_vs_oracle(ctx, L, monkeypatch):
     monkeypatch.setenv("ABM_BLOCK_L", str(L))
     monkeypatch.setenv("ABM_KCHUNK", "1024")
+    monkeypatch.setenv("ABM_MAX_SPLIT", "2")   # workgroups walk several chunks
     probs = _sweep([3000, 2 * L, 777, 1, 2 * L + 1, 64, 1500, 40])
     outs, st = run_batch(ctx, probs, 1)
     assert st["block_L"] == L
@@ -39,7 +40,7 @@ def test_batch_ragged_vs_oracle(ctx, L, monkeypatch):
 
 def test_batch_many_columns_several_tiles(ctx, monkeypatch):
     monkeypatch.setenv("ABM_BLOCK_L", "128")
-    monkeypatch.setenv("ABM_KCHUNK", "256")
+    monkeypatch.setenv("ABM_KCHUNK", "512")
     Ns = [2100] * 40 + [1900, 333]
     probs = _sweep(Ns, seed=11)
     outs, _ = run_batch(ctx, probs, 10)

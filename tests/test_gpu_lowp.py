@@ -1,0 +1,89 @@
+"""Reduced-precision far field (float, bf16 split x3 / x6) of the blocked path
+against the double oracle, through the C ABI.  Here the error is the quantity
+measured: each precision has a stated bound on the normwise relative error
+max_s |y_s - yref_s|_inf / max_s |yref_s|_inf."""
+import numpy as np
+import pytest
+
+from paper_1710_01133_amd import abm, inputs
+from gpu_common import golden, normerr, oracle_run, run_batch
+
+pytestmark = pytest.mark.gpu
+
+# stated error bounds of the far-field precisions (near band and state stay double)
+BOUND = {"fp32": 1e-6, "bf16x3": 1e-4, "bf16x6": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.init()
+    c = abm.Context(0)
+    yield c
+    c.close()
+
+
+def _sweep(Ns, prec, alpha=0.95, h=2 ** -6, seed=5):
+    amps = np.random.default_rng(seed).uniform(0.1, 0.6, len(Ns))
+    return [inputs.Problem("DUFFING", alpha, h, int(N), (0.1, 0.0), (0.1, float(A), 1.2), prec)
+            for N, A in zip(Ns, amps)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("L", [128, 256, 512])
+def test_lowp_ragged_vs_oracle(ctx, prec, L, monkeypatch):
+    monkeypatch.setenv("ABM_BLOCK_L", str(L))
+    monkeypatch.setenv("ABM_KCHUNK", "1024")
+    monkeypatch.setenv("ABM_MAX_SPLIT", "2")   # workgroups walk several chunks
+    probs = _sweep([4000, 2 * L + 1, 1, 3 * L, 2500, 100], prec)
+    outs, _ = run_batch(ctx, probs, 1)
+    errs = [normerr(y, oracle_run(p, 1)) for p, y in zip(probs, outs)]
+    print(prec, L, "max err %.3e" % max(errs))
+    assert max(errs) <= BOUND[prec], errs
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_lowp_mixed_rhs(ctx, prec):
+    probs = [
+        inputs.Problem("LORENZ", 0.97, 2 ** -8, 3000, (1.0, 1.0, 1.0), (10.0, 28.0, 8 / 3), prec),
+        inputs.Problem("LCR", 0.9, 0.02, 3000, (1.2, -0.4), (1.015, 0.55, -1.02, -0.58, 0.117), prec),
+        inputs.Problem("LINEAR", 0.8, 2 ** -9, 4096, (1.0,), (1.0,), prec),
+    ]
+    outs, _ = run_batch(ctx, probs, 1)
+    for p, y in zip(probs, outs):
+        e = normerr(y, oracle_run(p, 1))
+        print(prec, p.rhs, "err %.3e" % e)
+        assert e <= BOUND[prec], (p.rhs, e)
+
+
+def test_lowp_needs_block_128(ctx, monkeypatch):
+    monkeypatch.setenv("ABM_BLOCK_L", "64")
+    with pytest.raises(abm.AbmError) as e:
+        abm.Plan(ctx, _sweep([500], "fp32"))
+    assert e.value.code == abm.ABM_EINVAL
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_lowp_batch_invariance(ctx, prec):
+    probs = _sweep([3000, 2200, 3000], prec, seed=9)
+    outs, _ = run_batch(ctx, probs, 1)
+    alone, _ = run_batch(ctx, [probs[1]], 1)
+    assert np.array_equal(alone[0], outs[1])
+    again, _ = run_batch(ctx, probs, 1)
+    for a, b in zip(outs, again):
+        assert np.array_equal(a, b)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+def test_lowp_sweep_full_size(ctx, prec):
+    """B = 1024, N = 65536: error of sampled members against the stored double
+    oracle runs, at the launch shape the benchmark times."""
+    probs = inputs.duffing_sweep(far_prec=prec)
+    outs, _ = run_batch(ctx, probs, 1024)
+    g = golden()
+    errs = {i: normerr(outs[i], np.array(g["duffing_sweep_%d" % i]["y"])) for i in (0, 1, 511, 1023)}
+    print(prec, "full-size errors", errs)
+    assert max(errs.values()) <= BOUND[prec]
+    allv = np.stack(outs)
+    assert np.all(np.isfinite(allv)) and np.max(np.abs(allv)) < 10
