@@ -139,6 +139,15 @@ __device__ __forceinline__ int64_t kblocked_index(int64_t k, int64_t col, int64_
     return (((k - 1) >> 3) * ld + col) * 8 + ((k - 1) & 7);
 }
 
+// Index of history row k, column col, in the column-blocked layout of the
+// float history copy: 16 columns form a block and each block stores its rows
+// contiguously (rows * 16 floats), so a far-field workgroup reading one block
+// streams whole cache lines.
+__device__ __forceinline__ int64_t colblocked_index(int64_t k, int64_t col, int64_t rows)
+{
+    return ((col >> 4) * rows + k) * 16 + (col & 15);
+}
+
 // Device status word bits (written with atomic OR, read by the host).
 constexpr uint32_t kStatusTimeout = 1u;   // a bounded device-side wait gave up
 constexpr uint32_t kStatusNonFinite = 2u; // a state became NaN/Inf

@@ -40,39 +40,12 @@ int plain_chunk();
 int plain_part_doubles(int G);
 hipError_t launch_plain(const PlainArgs& A, int rhs, hipStream_t st);
 
-// ---- K2: far-field products of the blocked method ------------------------
-struct FarArgs {
-    const double* b;       // weight tables (padded past N by at least L)
-    const double* a;
-    const float* b32;      // float copies (far_prec fp32)
-    const float* a32;
-    const uint16_t* bh[3]; // bf16 split terms (far_prec bf16x3 / bf16x6)
-    const uint16_t* ah[3];
-    const double* F;       // time-major double history [k][ldF]
-    const float* F32;      // time-major float history [k][ldF]
-    const uint16_t* Fh[3]; // bf16 split terms of the history, k-blocked (kblocked_index)
-    int64_t ldF;
-    int64_t mL;            // first history index of the block, m*L
-    int64_t kfar;          // far field covers k = 1..kfar (multiple of L)
-    int32_t kchunk;        // history rows per chunk (multiple of 512)
-    int32_t nchunks;       // ceil(kfar / kchunk)
-    int32_t chunks_per_split;
-    int32_t nsplit;        // workgroups along the history = partial slices written
-    double* part;          // [nsplit][ldP][2L]
-    int64_t ldP;           // columns (multiple of the tile width)
-};
-int far_tile_cols(int L, int prec);
-int far_stage_rows();
-size_t far_lds_bytes(int L, int kchunk, int prec);
-hipError_t launch_far(const FarArgs& A, int L, int prec, hipStream_t st);
-size_t far_lp_lds_bytes(int L, int kchunk, int prec);
-hipError_t launch_far_lp(const FarArgs& A, int L, int prec, hipStream_t st);
-// Chunks of the far range 1..kfar and their grouping into at most max_split
-// workgroup ranges; returns the number of partial slices.
-int far_split_plan(int64_t kfar, int kchunk, int max_split, int* nchunks, int* chunks_per_split);
-hipError_t allow_lds(const void* fn, size_t bytes);   // dynamic LDS above 64 KiB
-
-// ---- K3: near band + predictor/corrector chain ---------------------------
+// ---- blocked method: groups and work items --------------------------------
+// A group is a set of trajectories sharing one weight table (one alpha), one
+// right-hand side and one far-field precision; their components are the
+// columns of one time-major history.  Launches take lists of work items that
+// point at group descriptors in device memory, so one launch can advance
+// groups that are at different blocks (differing N, alpha, start time).
 struct TrajDesc {
     double x0[4];
     double p[8];
@@ -83,29 +56,76 @@ struct TrajDesc {
     int32_t col0;          // first column of this trajectory in its group's history
     int32_t pad_;
 };
-struct ChainArgs {
-    const TrajDesc* traj;  // device array, ntraj entries
-    int32_t ntraj;
-    int32_t nchunks;       // far-field partial slices of this block (0 when m = 0)
-    const double* b;
+
+struct GroupDev {
+    const double* b;       // weight tables (padded past N by at least 2L)
     const double* a;
     const double* c;
-    const double* gam;
+    const double* gam;     // Gamma(alpha+1), Gamma(alpha+2)
+    const float* b32;      // float copies (far_prec fp32)
+    const float* a32;
+    const uint16_t* bh[3]; // bf16 split terms (far_prec bf16x3 / bf16x6)
+    const uint16_t* ah[3];
     double alpha;
-    double* F;             // double history [k][ldF]
-    float* F32;            // float copy (or null)
-    uint16_t* Fhi;         // bf16 split terms (or null): hi, second, third
-    uint16_t* Fmid;
-    uint16_t* Flo;
-    int64_t ldF;
-    const double* part;    // far partials [nchunks][ldP][2L]
-    int64_t ldP;
-    int64_t mL;
-    double* accn;          // [ntraj][2][d][L] sums carried into the next block
-    uint32_t* status;
+    double* F;             // time-major double history [k][ldF]
+    float* F32;            // float copy, column-blocked (colblocked_index)
+    uint16_t* Fh[3];       // bf16 split terms of the history, k-blocked (kblocked_index)
+    int64_t ldF;           // padded columns
+    int64_t rows;          // history rows allocated
+    double* accn;          // [member][2][d][L] sums carried into the next block
+    double* part[2];       // far partials [split][col][2L], by block parity
+    const TrajDesc* traj;  // members
+    int32_t d;
+    int32_t pad_;
 };
-hipError_t launch_chain(const ChainArgs& A, int rhs, int L, hipStream_t st);
-hipError_t launch_chain_init(const ChainArgs& A, int rhs, hipStream_t st);
+
+// Far field of one group for block m: history k = 1..kfar, kfar = (m-1)L.
+struct FarItem {
+    int32_t group;
+    int32_t ncoltiles;     // active columns / tile width
+    int32_t nchunks;       // ceil(kfar / kchunk)
+    int32_t chunks_per_split;
+    int32_t nsplit;        // partial slices written
+    int32_t pad_;
+    int64_t mL;
+    int64_t kfar;
+    int64_t ldP;           // column stride of the partial slices (active columns, padded)
+};
+
+// Chain of one trajectory (group member) through block m.
+struct ChainItem {
+    int32_t group;
+    int32_t member;
+    int32_t nsplit;        // far partial slices of this block (0 when m < 2)
+    int32_t pad_;
+    int64_t mL;
+    int64_t ldP;
+};
+
+// ---- K2: far-field products ------------------------------------------------
+int far_tile_cols(int L, int prec);
+size_t far_lds_bytes(int L, int kchunk, int prec);
+// Chunks of the far range 1..kfar and their grouping into at most max_split
+// workgroup ranges; returns the number of partial slices.
+int far_split_plan(int64_t kfar, int kchunk, int max_split, int* nchunks, int* chunks_per_split);
+// Upper bound of far_split_plan's slice count over every kfar <= kfar_max.
+int far_split_bound(int64_t kfar_max, int kchunk, int max_split);
+// One launch over n items (all of precision prec); grid (max_coltiles,
+// max_nsplit, n); workgroups beyond an item's own tiles/splits exit.
+hipError_t launch_far(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
+                      int max_nsplit, int kchunk, int L, int prec, hipStream_t st);
+size_t far_lp_lds_bytes(int L, int kchunk, int prec);
+hipError_t launch_far_lp(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
+                         int max_nsplit, int kchunk, int L, int prec, hipStream_t st);
+hipError_t allow_lds(const void* fn, size_t bytes);   // dynamic LDS above 64 KiB
+
+// ---- K3: near band + predictor/corrector chain -----------------------------
+// One wave per item; all items of a launch share the right-hand side.
+hipError_t launch_chain(const GroupDev* groups, const ChainItem* items, int n, int rhs, int L,
+                        uint32_t* status, hipStream_t st);
+// f_0 into history row 0 and y_0 = x0 for every member of the listed groups.
+hipError_t launch_chain_init(const GroupDev* groups, const ChainItem* items, int n, int rhs,
+                             hipStream_t st);
 
 // ---- utilities -----------------------------------------------------------
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t st);

@@ -14,7 +14,7 @@ namespace abm {
 
 constexpr int64_t kMaxSteps = (int64_t)1 << 30;   // step counters are 32-bit on the device
 constexpr int64_t kWeightPad = 2048;                // weight tables extend this far past N
-constexpr int kPlainDefaultG = 128;
+constexpr int kPlainDefaultG = 32;       // measured: per-step sync cost grows beyond ~32 workgroups
 constexpr size_t kMaxLds = 160 * 1024;              // LDS of one gfx950 CU
 constexpr uint32_t kSpinLimit = 1u << 22;           // a few seconds of polling (each poll is a memory round trip)
 
@@ -37,26 +37,36 @@ struct WeightTable {
 // Trajectories sharing one weight table, one right-hand side and one far-field
 // precision: their components form the columns of one time-major history.
 struct Group {
-    int table;
-    int rhs;
-    int d;
-    int prec;
-    int64_t nmax;                 // longest trajectory
+    int table = 0;
+    int rhs = 0;
+    int d = 0;
+    int prec = 0;
+    int64_t nmax = 0;             // longest trajectory
     std::vector<int> members;     // problem indices, N descending
     std::vector<int32_t> col0;    // first column of each member
-    std::vector<int64_t> active_cols;   // per block m: columns of members with N > mL
-    std::vector<int32_t> active_traj;   // per block m: members with N > mL
-    int64_t cols;                 // real columns
-    int64_t ldF;                  // padded columns
-    int64_t rows;                 // history rows allocated
-    double* F;
-    float* F32;
-    uint16_t* Fh[3];
-    TrajDesc* traj_dev;           // members' descriptors (device)
-    double* accn;                 // sums carried into the next block [member][2][d][L]
-    TrajDesc* traj_host;          // pinned staging copy of the descriptors
-    hipEvent_t traj_ev;           // recorded after the last upload from traj_host
-    bool traj_ev_live;
+    int64_t cols = 0;             // real columns
+    int64_t ldF = 0;              // padded columns
+    int64_t rows = 0;             // history rows allocated
+    double* F = nullptr;
+    float* F32 = nullptr;
+    uint16_t* Fh[3] = {nullptr, nullptr, nullptr};
+    TrajDesc* traj_dev = nullptr;   // members' descriptors (device)
+    double* accn = nullptr;         // sums carried into the next block [member][2][d][L]
+    double* part[2] = {nullptr, nullptr};   // far partials by block parity
+    size_t part_half = 0;           // doubles per partial buffer
+    int nsplit_cap = 0;             // partial slices each buffer holds
+    TrajDesc* traj_host = nullptr;  // pinned staging copy of the descriptors
+    hipEvent_t traj_ev = nullptr;   // recorded after the last upload from traj_host
+    bool traj_ev_live = false;
+};
+
+// A run of work items of one launch: offset/count in an item array and the
+// grid extents it needs.
+struct Span {
+    int64_t offset = 0;
+    int32_t count = 0;
+    int32_t max_x = 0;
+    int32_t max_y = 0;
 };
 
 }  // namespace abm
@@ -82,13 +92,20 @@ struct abm_plan_s {
     std::string plain_error;
     double* part = nullptr;
     uint32_t* flags = nullptr;
-    // blocked path
+    // blocked path: groups and their static tick schedule
     int L = 0;
     int kchunk = 0;
     int max_split = 8;
     std::vector<abm::Group> groups;
-    double* ffpart = nullptr;     // far partials, sized for the largest group
-    size_t ffpart_bytes = 0;
+    abm::GroupDev* groups_dev = nullptr;
+    abm::FarItem* far_items_dev = nullptr;
+    abm::ChainItem* chain_items_dev = nullptr;
+    abm::ChainItem* init_items_dev = nullptr;
+    int64_t ticks = 0;
+    std::vector<abm::Span> far_spans;     // [tick][precision]
+    std::vector<abm::Span> chain_spans;   // [tick][rhs]
+    std::vector<abm::Span> init_spans;    // [rhs]
+    int64_t far_macs = 0;
     // far field on its own stream, overlapping the chain
     bool overlap = true;
     hipStream_t far_stream = nullptr;
@@ -113,6 +130,15 @@ abm_status plain_setup(abm_plan_s* pl);
 abm_status batch_setup(abm_plan_s* pl);
 void batch_teardown(abm_plan_s* pl);
 void free_reduced(WeightTable& t);
+void free_group(Group& g);
+abm_status ensure_reduced_weights(WeightTable& W, int prec, hipStream_t st);
+abm_status alloc_group(Group& g, int L, int nsplit_max, hipStream_t st);
+GroupDev group_dev(const Group& g, const WeightTable& W);
+void block_items(const Group& g, int gi, int64_t m, int L, int kchunk, int max_split,
+                 const std::vector<int64_t>& memberN, std::vector<FarItem>* far,
+                 std::vector<ChainItem>* chain);
+int64_t group_far_split_max(const Group& g, int L, int kchunk, int max_split);
+abm_status choose_blocking(abm_plan_s* pl, const abm_problem* probs, int B);
 void serve_shutdown(abm_ctx* ctx);
 
 }  // namespace abm

@@ -1,5 +1,12 @@
-// Blocked batch path: plan-time grouping and sizing, and the per-block launch
-// sequence of abm_solve_batch (far-field product, then the chain).
+// Blocked batch path: plan-time grouping, sizing and tick schedule, and the
+// launch sequence of abm_solve_batch.
+//
+// Trajectories are grouped by (weight table = alpha, right-hand side, far
+// precision).  All groups advance in lockstep ticks: at tick t every group
+// still running steps its block m = t (chain) while the far field of its
+// block t+1 is computed on a second stream.  One far launch per precision
+// class and one chain launch per right-hand side cover all groups of a tick,
+// whatever their alpha, N or parameters (work items in device memory).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,46 +41,203 @@ void free_reduced(WeightTable& t)
     t.b32 = t.a32 = nullptr;
 }
 
+void free_group(Group& g)
+{
+    dev_free(g.F);
+    dev_free(g.F32);
+    for (int i = 0; i < 3; ++i) dev_free(g.Fh[i]);
+    dev_free(g.traj_dev);
+    dev_free(g.accn);
+    dev_free(g.part[0]);
+    if (g.traj_host) (void)hipHostFree(g.traj_host);
+    if (g.traj_ev) (void)hipEventDestroy(g.traj_ev);
+    g = Group{};
+}
+
 void batch_teardown(abm_plan_s* pl)
 {
     for (hipEvent_t ev : pl->events) (void)hipEventDestroy(ev);
     pl->events.clear();
-    for (auto& g : pl->groups) {
-        dev_free(g.F);
-        dev_free(g.F32);
-        for (int i = 0; i < 3; ++i) dev_free(g.Fh[i]);
-        dev_free(g.traj_dev);
-        dev_free(g.accn);
-        if (g.traj_host) (void)hipHostFree(g.traj_host);
-        if (g.traj_ev) (void)hipEventDestroy(g.traj_ev);
-    }
+    for (auto& g : pl->groups) free_group(g);
     pl->groups.clear();
-    dev_free(pl->ffpart);
-    pl->ffpart = nullptr;
+    dev_free(pl->groups_dev);
+    dev_free(pl->far_items_dev);
+    dev_free(pl->chain_items_dev);
+    dev_free(pl->init_items_dev);
+    pl->groups_dev = nullptr;
+    pl->far_items_dev = nullptr;
+    pl->chain_items_dev = nullptr;
+    pl->init_items_dev = nullptr;
     for (hipEvent_t ev : pl->sync_events) (void)hipEventDestroy(ev);
     pl->sync_events.clear();
     if (pl->far_stream) (void)hipStreamDestroy(pl->far_stream);
     pl->far_stream = nullptr;
 }
 
-abm_status batch_setup(abm_plan_s* pl)
+// Reduced copies of a weight table for far precision prec (once per table).
+abm_status ensure_reduced_weights(WeightTable& W, int prec, hipStream_t st)
 {
-    hipStream_t st = pl->ctx->stream;
-    int L = env_int("ABM_BLOCK_L", 256);
+    abm_status s;
+    hipError_t e;
+    const int64_t wn = W.n + kWeightPad;
+    if (prec == ABM_FAR_FP32 && !W.b32) {
+        if ((s = dev_alloc((void**)&W.b32, wn * sizeof(float), "float weights")) ||
+            (s = dev_alloc((void**)&W.a32, wn * sizeof(float), "float weights")))
+            return s;
+        uint16_t* none[3] = {nullptr, nullptr, nullptr};
+        if ((e = launch_weights_lowp(wn, W.b, W.a, W.b32, W.a32, none, none, st)) != hipSuccess)
+            return hip_fail(e, "weight conversion");
+    }
+    if ((prec == ABM_FAR_BF16X3 || prec == ABM_FAR_BF16X6) && !W.bh[0]) {
+        for (int tt = 0; tt < 3; ++tt)
+            if ((s = dev_alloc((void**)&W.bh[tt], wn * sizeof(uint16_t), "bf16 weights")) ||
+                (s = dev_alloc((void**)&W.ah[tt], wn * sizeof(uint16_t), "bf16 weights")))
+                return s;
+        if ((e = launch_weights_lowp(wn, W.b, W.a, nullptr, nullptr, W.bh, W.ah, st)) != hipSuccess)
+            return hip_fail(e, "weight conversion");
+    }
+    return ABM_OK;
+}
+
+// Device memory of one group: history (+ reduced copy), carried sums, far
+// partial double buffer, descriptors.  nsplit_max bounds the partial slices.
+abm_status alloc_group(Group& g, int L, int nsplit_max, hipStream_t st)
+{
+    abm_status s;
+    hipError_t e;
+    const size_t nm = g.members.size();
+    if ((s = dev_alloc((void**)&g.F, (size_t)g.rows * g.ldF * sizeof(double), "history")))
+        return s;
+    if ((e = hipMemsetAsync(g.F, 0, (size_t)g.rows * g.ldF * sizeof(double), st)) != hipSuccess)
+        return hip_fail(e, "history clear");
+    if (g.prec == ABM_FAR_FP32) {
+        const size_t bytes = (size_t)g.rows * g.ldF * sizeof(float);
+        if ((s = dev_alloc((void**)&g.F32, bytes, "float history"))) return s;
+        if ((e = hipMemsetAsync(g.F32, 0, bytes, st)) != hipSuccess) return hip_fail(e, "clear");
+    } else if (g.prec == ABM_FAR_BF16X3 || g.prec == ABM_FAR_BF16X6) {
+        const int terms = g.prec == ABM_FAR_BF16X3 ? 2 : 3;
+        const size_t bytes = (size_t)((g.rows + 7) / 8) * g.ldF * 8 * sizeof(uint16_t);
+        for (int tt = 0; tt < terms; ++tt) {
+            if ((s = dev_alloc((void**)&g.Fh[tt], bytes, "bf16 history"))) return s;
+            if ((e = hipMemsetAsync(g.Fh[tt], 0, bytes, st)) != hipSuccess) return hip_fail(e, "clear");
+        }
+    }
+    if ((s = dev_alloc((void**)&g.traj_dev, nm * sizeof(TrajDesc), "descriptors"))) return s;
+    if ((s = dev_alloc((void**)&g.accn, nm * 2 * g.d * L * sizeof(double), "carried sums"))) return s;
+    g.nsplit_cap = std::max(nsplit_max, 1);
+    g.part_half = (size_t)g.nsplit_cap * g.ldF * 2 * L;
+    if ((s = dev_alloc((void**)&g.part[0], 2 * g.part_half * sizeof(double), "far partials"))) return s;
+    g.part[1] = g.part[0] + g.part_half;
+    if ((e = hipHostMalloc((void**)&g.traj_host, nm * sizeof(TrajDesc), hipHostMallocDefault)) != hipSuccess)
+        return hip_fail(e, "pinned descriptors");
+    if ((e = hipEventCreateWithFlags(&g.traj_ev, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "event");
+    return ABM_OK;
+}
+
+GroupDev group_dev(const Group& g, const WeightTable& W)
+{
+    GroupDev d{};
+    d.b = W.b;
+    d.a = W.a;
+    d.c = W.c;
+    d.gam = W.gam;
+    d.b32 = W.b32;
+    d.a32 = W.a32;
+    for (int i = 0; i < 3; ++i) {
+        d.bh[i] = W.bh[i];
+        d.ah[i] = W.ah[i];
+        d.Fh[i] = g.Fh[i];
+    }
+    d.alpha = W.alpha;
+    d.F = g.F;
+    d.F32 = g.F32;
+    d.ldF = g.ldF;
+    d.rows = g.rows;
+    d.accn = g.accn;
+    d.part[0] = g.part[0];
+    d.part[1] = g.part[1];
+    d.traj = g.traj_dev;
+    d.d = g.d;
+    return d;
+}
+
+// Work items of group g (index gi) when it is at block m: the far field of
+// block m+1 and the chains of block m.  memberN holds the members' N in the
+// group's (descending) order, so the members still running form a prefix.
+void block_items(const Group& g, int gi, int64_t m, int L, int kchunk, int max_split,
+                 const std::vector<int64_t>& memberN, std::vector<FarItem>* far,
+                 std::vector<ChainItem>* chain)
+{
+    const int TN = far_tile_cols(L, g.prec);
+    const int64_t nblocks = (g.nmax + L - 1) / L;
+    auto active = [&](int64_t mm) {
+        int32_t cnt = 0;
+        for (int64_t N : memberN)
+            if (N > mm * L) ++cnt;
+        return cnt;
+    };
+    const int64_t mf = m + 1;
+    if (far && mf < nblocks && mf >= 2) {
+        FarItem it{};
+        it.group = gi;
+        it.kfar = (mf - 1) * L;
+        it.mL = mf * L;
+        it.ldP = round_up((int64_t)active(mf) * g.d, TN);
+        it.ncoltiles = (int32_t)(it.ldP / TN);
+        it.nsplit = far_split_plan(it.kfar, kchunk, max_split, &it.nchunks, &it.chunks_per_split);
+        far->push_back(it);
+    }
+    if (chain && m < nblocks) {
+        int nsp = 0, nc = 0, cps = 0;
+        if (m >= 2) nsp = far_split_plan((m - 1) * L, kchunk, max_split, &nc, &cps);
+        const int32_t na = active(m);
+        const int64_t ldP = round_up((int64_t)na * g.d, TN);
+        for (int32_t j = 0; j < na; ++j) {
+            ChainItem c{};
+            c.group = gi;
+            c.member = j;
+            c.nsplit = nsp;
+            c.mL = m * L;
+            c.ldP = ldP;
+            chain->push_back(c);
+        }
+    }
+}
+
+int64_t group_far_split_max(const Group& g, int L, int kchunk, int max_split)
+{
+    const int64_t nblocks = (g.nmax + L - 1) / L;
+    const int64_t kfar_max = nblocks >= 2 ? (nblocks - 2) * L : 0;   // far(m) covers (m-1)L
+    return far_split_bound(kfar_max, kchunk, max_split);
+}
+
+abm_status choose_blocking(abm_plan_s* pl, const abm_problem* probs, int B)
+{
+    int L = env_int("ABM_BLOCK_L", pl->L > 0 ? pl->L : 256);
     if (!valid_L(L)) return fail(ABM_EINVAL, "ABM_BLOCK_L=%d not in {64,128,256,512}", L);
+    for (int i = 0; i < B; ++i)
+        if (probs[i].far_prec != ABM_FAR_FP64 && L < 128)
+            return fail(ABM_EINVAL, "problem %d: reduced-precision far field needs block length >= 128", i);
     int kchunk = env_int("ABM_KCHUNK", 2048);
     if (kchunk < 512 || kchunk % 512)
         return fail(ABM_EINVAL, "ABM_KCHUNK=%d must be a positive multiple of 512", kchunk);
-    for (int i = 0; i < pl->B; ++i)
-        if (pl->shape[i].far_prec != ABM_FAR_FP64 && L < 128)
-            return fail(ABM_EINVAL, "problem %d: reduced-precision far field needs block length >= 128", i);
-    // largest chunk whose LDS footprint fits every precision used by the plan
-    for (int i = 0; i < pl->B; ++i)
-        while (kchunk > 512 && far_lds_bytes(L, kchunk, pl->shape[i].far_prec) > kMaxLds) kchunk -= 512;
+    // largest chunk whose LDS footprint fits every precision used
+    for (int prec = 0; prec < 4; ++prec)
+        while (kchunk > 512 && far_lds_bytes(L, kchunk, prec) > kMaxLds) kchunk -= 512;
     pl->L = L;
     pl->kchunk = kchunk;
     pl->max_split = env_int("ABM_MAX_SPLIT", 8);
     if (pl->max_split < 1) return fail(ABM_EINVAL, "ABM_MAX_SPLIT must be >= 1");
+    return ABM_OK;
+}
+
+abm_status batch_setup(abm_plan_s* pl)
+{
+    hipStream_t st = pl->ctx->stream;
+    abm_status s = choose_blocking(pl, pl->shape.data(), pl->B);
+    if (s) return s;
+    const int L = pl->L, kchunk = pl->kchunk;
 
     // groups: (weight table, rhs, precision); members sorted by N descending
     std::map<std::tuple<int, int, int>, int> key_to_group;
@@ -92,89 +256,104 @@ abm_status batch_setup(abm_plan_s* pl)
         }
         pl->groups[it->second].members.push_back(i);
     }
-    size_t ff_need = 0;
+    std::vector<GroupDev> gdev;
+    int64_t ticks = 0;
     for (auto& g : pl->groups) {
-        const int TN = far_tile_cols(L, g.prec);
         std::stable_sort(g.members.begin(), g.members.end(),
                          [&](int x, int y) { return pl->shape[x].N > pl->shape[y].N; });
+        const int TN = far_tile_cols(L, g.prec);
         g.nmax = pl->shape[g.members[0]].N;
         g.cols = (int64_t)g.members.size() * g.d;
         g.ldF = round_up(g.cols, TN);
         g.rows = g.nmax + 1 + L;
         g.col0.resize(g.members.size());
         for (size_t j = 0; j < g.members.size(); ++j) g.col0[j] = (int32_t)(j * g.d);
-        const int64_t nblocks = (g.nmax + L - 1) / L;
-        g.active_cols.resize(nblocks);
-        g.active_traj.resize(nblocks);
-        for (int64_t m = 0; m < nblocks; ++m) {
-            int32_t cnt = 0;
-            for (int idx : g.members)
-                if (pl->shape[idx].N > m * L) ++cnt;
-            g.active_traj[m] = cnt;
-            g.active_cols[m] = round_up((int64_t)cnt * g.d, TN);
-        }
-        int nc = 0, cps = 0;
-        const int64_t kfar_max = nblocks >= 2 ? (nblocks - 2) * L : 0;   // far(m) covers (m-1)L
-        const int64_t nsp = far_split_plan(kfar_max, kchunk, pl->max_split, &nc, &cps);
-        ff_need = std::max(ff_need, (size_t)nsp * g.ldF * 2 * L * sizeof(double));
-        abm_status s;
-        if ((s = dev_alloc((void**)&g.F, (size_t)g.rows * g.ldF * sizeof(double), "history")))
-            return s;
-        hipError_t e = hipMemsetAsync(g.F, 0, (size_t)g.rows * g.ldF * sizeof(double), st);
-        if (e != hipSuccess) return hip_fail(e, "history clear");
-        // reduced copies of the history read by the far field
-        if (g.prec == ABM_FAR_FP32) {
-            const size_t bytes = (size_t)g.rows * g.ldF * sizeof(float);
-            if ((s = dev_alloc((void**)&g.F32, bytes, "float history"))) return s;
-            if ((e = hipMemsetAsync(g.F32, 0, bytes, st)) != hipSuccess) return hip_fail(e, "clear");
-        } else if (g.prec == ABM_FAR_BF16X3 || g.prec == ABM_FAR_BF16X6) {
-            const int terms = g.prec == ABM_FAR_BF16X3 ? 2 : 3;
-            const size_t bytes = (size_t)((g.rows + 7) / 8) * g.ldF * 8 * sizeof(uint16_t);
-            for (int tt = 0; tt < terms; ++tt) {
-                if ((s = dev_alloc((void**)&g.Fh[tt], bytes, "bf16 history"))) return s;
-                if ((e = hipMemsetAsync(g.Fh[tt], 0, bytes, st)) != hipSuccess) return hip_fail(e, "clear");
-            }
-        }
-        // reduced copies of the weights, once per table
-        WeightTable& W = pl->tables[g.table];
-        const int64_t wn = W.n + kWeightPad;
-        if (g.prec == ABM_FAR_FP32 && !W.b32) {
-            if ((s = dev_alloc((void**)&W.b32, wn * sizeof(float), "float weights")) ||
-                (s = dev_alloc((void**)&W.a32, wn * sizeof(float), "float weights")))
-                return s;
-            uint16_t* none[3] = {nullptr, nullptr, nullptr};
-            if ((e = launch_weights_lowp(wn, W.b, W.a, W.b32, W.a32, none, none, st)) != hipSuccess)
-                return hip_fail(e, "weight conversion");
-        }
-        if ((g.prec == ABM_FAR_BF16X3 || g.prec == ABM_FAR_BF16X6) && !W.bh[2]) {
-            for (int tt = 0; tt < 3; ++tt) {
-                if (W.bh[tt]) continue;
-                if ((s = dev_alloc((void**)&W.bh[tt], wn * sizeof(uint16_t), "bf16 weights")) ||
-                    (s = dev_alloc((void**)&W.ah[tt], wn * sizeof(uint16_t), "bf16 weights")))
-                    return s;
-            }
-            if ((e = launch_weights_lowp(wn, W.b, W.a, nullptr, nullptr, W.bh, W.ah, st)) != hipSuccess)
-                return hip_fail(e, "weight conversion");
-        }
-        if ((s = dev_alloc((void**)&g.traj_dev, g.members.size() * sizeof(TrajDesc), "descriptors")))
-            return s;
-        if ((s = dev_alloc((void**)&g.accn, g.members.size() * 2 * g.d * L * sizeof(double), "carried sums")))
-            return s;
-        e = hipHostMalloc((void**)&g.traj_host, g.members.size() * sizeof(TrajDesc), hipHostMallocDefault);
-        if (e != hipSuccess) return hip_fail(e, "pinned descriptors");
-        e = hipEventCreateWithFlags(&g.traj_ev, hipEventDisableTiming);
-        if (e != hipSuccess) return hip_fail(e, "event");
+        ticks = std::max(ticks, (g.nmax + L - 1) / L);
+        if ((s = ensure_reduced_weights(pl->tables[g.table], g.prec, st))) return s;
+        if ((s = alloc_group(g, L, (int)group_far_split_max(g, L, kchunk, pl->max_split), st))) return s;
+        gdev.push_back(group_dev(g, pl->tables[g.table]));
     }
-    // two partial buffers: the far field of block m+1 is written while the
-    // chain of block m reads block m's
-    pl->ffpart_bytes = ff_need;
-    if (ff_need) {
-        abm_status s = dev_alloc((void**)&pl->ffpart, 2 * ff_need, "far partials");
-        if (s) return s;
+
+    // static tick schedule: far items by precision class, chain items by rhs
+    const int ngroups = (int)pl->groups.size();
+    std::vector<std::vector<int64_t>> memberN(ngroups);
+    for (int gi = 0; gi < ngroups; ++gi)
+        for (int idx : pl->groups[gi].members) memberN[gi].push_back(pl->shape[idx].N);
+    pl->ticks = ticks;
+    pl->far_spans.assign((size_t)ticks * 4, Span{});
+    pl->chain_spans.assign((size_t)ticks * 5, Span{});
+    std::vector<FarItem> far_all;
+    std::vector<ChainItem> chain_all, init_all;
+    for (int64_t t = 0; t < ticks; ++t) {
+        for (int prec = 0; prec < 4; ++prec) {
+            Span& sp = pl->far_spans[t * 4 + prec];
+            sp.offset = (int64_t)far_all.size();
+            for (int gi = 0; gi < ngroups; ++gi)
+                if (pl->groups[gi].prec == prec)
+                    block_items(pl->groups[gi], gi, t, L, kchunk, pl->max_split, memberN[gi],
+                                &far_all, nullptr);
+            sp.count = (int32_t)((int64_t)far_all.size() - sp.offset);
+            for (int64_t k = sp.offset; k < (int64_t)far_all.size(); ++k) {
+                sp.max_x = std::max(sp.max_x, far_all[k].ncoltiles);
+                sp.max_y = std::max(sp.max_y, far_all[k].nsplit);
+            }
+        }
+        for (int rhs = 0; rhs < 5; ++rhs) {
+            Span& sp = pl->chain_spans[t * 5 + rhs];
+            sp.offset = (int64_t)chain_all.size();
+            for (int gi = 0; gi < ngroups; ++gi)
+                if (pl->groups[gi].rhs == rhs)
+                    block_items(pl->groups[gi], gi, t, L, kchunk, pl->max_split, memberN[gi],
+                                nullptr, &chain_all);
+            sp.count = (int32_t)((int64_t)chain_all.size() - sp.offset);
+        }
+    }
+    pl->init_spans.assign(5, Span{});
+    for (int rhs = 0; rhs < 5; ++rhs) {
+        Span& sp = pl->init_spans[rhs];
+        sp.offset = (int64_t)init_all.size();
+        for (int gi = 0; gi < ngroups; ++gi) {
+            const Group& g = pl->groups[gi];
+            if (g.rhs != rhs) continue;
+            for (size_t j = 0; j < g.members.size(); ++j) {
+                ChainItem c{};
+                c.group = gi;
+                c.member = (int32_t)j;
+                init_all.push_back(c);
+            }
+        }
+        sp.count = (int32_t)((int64_t)init_all.size() - sp.offset);
+    }
+    // every item must fit its group's partial buffers (checked, not assumed)
+    for (const FarItem& it : far_all)
+        if (it.nsplit > pl->groups[it.group].nsplit_cap || it.ldP > pl->groups[it.group].ldF)
+            return fail(ABM_EDEVICE, "internal: far item exceeds the partial buffer of group %d", it.group);
+    for (const ChainItem& it : chain_all)
+        if (it.nsplit > pl->groups[it.group].nsplit_cap)
+            return fail(ABM_EDEVICE, "internal: chain item exceeds the partial buffer of group %d", it.group);
+    hipError_t e;
+    if ((s = dev_alloc((void**)&pl->groups_dev, gdev.size() * sizeof(GroupDev), "group table")) ||
+        (s = dev_alloc((void**)&pl->far_items_dev, std::max<size_t>(1, far_all.size()) * sizeof(FarItem), "far items")) ||
+        (s = dev_alloc((void**)&pl->chain_items_dev, std::max<size_t>(1, chain_all.size()) * sizeof(ChainItem), "chain items")) ||
+        (s = dev_alloc((void**)&pl->init_items_dev, std::max<size_t>(1, init_all.size()) * sizeof(ChainItem), "init items")))
+        return s;
+    if ((e = hipMemcpy(pl->groups_dev, gdev.data(), gdev.size() * sizeof(GroupDev), hipMemcpyHostToDevice)) ||
+        (!far_all.empty() && (e = hipMemcpy(pl->far_items_dev, far_all.data(), far_all.size() * sizeof(FarItem), hipMemcpyHostToDevice))) ||
+        (e = hipMemcpy(pl->chain_items_dev, chain_all.data(), chain_all.size() * sizeof(ChainItem), hipMemcpyHostToDevice)) ||
+        (e = hipMemcpy(pl->init_items_dev, init_all.data(), init_all.size() * sizeof(ChainItem), hipMemcpyHostToDevice)))
+        return hip_fail(e, "schedule upload");
+    // useful far-field MACs of the schedule (reported in abm_stats)
+    pl->far_macs = 0;
+    for (const FarItem& it : far_all) {
+        const Group& g = pl->groups[it.group];
+        for (int64_t N : memberN[it.group]) {
+            if (N <= it.mL) continue;
+            pl->far_macs += (int64_t)g.d * std::min<int64_t>(L, N - it.mL) * it.kfar;
+        }
     }
     pl->overlap = env_int("ABM_OVERLAP", 1) != 0;
     if (pl->overlap) {
-        hipError_t e = hipStreamCreateWithFlags(&pl->far_stream, hipStreamNonBlocking);
+        e = hipStreamCreateWithFlags(&pl->far_stream, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(e, "far stream");
     }
     return ABM_OK;
@@ -204,8 +383,8 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
     hipStream_t st = pl->ctx->stream;
     const int L = pl->L;
     abm_stats S{};
-    // event pairs around launches when timing is on: (kind, first, second)
-    std::vector<std::pair<int, int>> tev;   // kind 0 far, 1 chain; index of the start event
+    // event pairs around launches when timing is on: (kind, index of the start event)
+    std::vector<std::pair<int, int>> tev;
     size_t ev_used = 0;
     auto ev_next = [&]() -> hipEvent_t {
         if (ev_used == pl->events.size()) {
@@ -240,10 +419,10 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
     };
     S.block_L = L;
     S.n_groups = (int32_t)pl->groups.size();
+    S.far_macs = pl->far_macs;
 
+    // per-solve descriptors (x0, p, h, outputs) through the pinned staging copies
     for (auto& g : pl->groups) {
-        const WeightTable& W = pl->tables[g.table];
-        // the staging buffer may still feed the previous solve's upload
         if (g.traj_ev_live) {
             e = hipEventSynchronize(g.traj_ev);
             if (e != hipSuccess) return hip_fail(e, "descriptor staging wait");
@@ -268,96 +447,65 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
         e = hipEventRecord(g.traj_ev, st);
         if (e != hipSuccess) return hip_fail(e, "descriptor event");
         g.traj_ev_live = true;
-
-        ChainArgs C{};
-        C.traj = g.traj_dev;
-        C.ntraj = (int32_t)g.members.size();
-        C.b = W.b;
-        C.a = W.a;
-        C.c = W.c;
-        C.gam = W.gam;
-        C.alpha = W.alpha;
-        C.F = g.F;
-        C.F32 = g.F32;
-        C.Fhi = g.Fh[0];
-        C.Fmid = g.Fh[1];
-        C.Flo = g.Fh[2];
-        C.ldF = g.ldF;
-        C.part = pl->ffpart;
-        C.status = pl->status;
-        e = launch_chain_init(C, g.rhs, st);
+    }
+    for (int rhs = 0; rhs < 5; ++rhs) {
+        const Span& sp = pl->init_spans[rhs];
+        if (!sp.count) continue;
+        e = launch_chain_init(pl->groups_dev, pl->init_items_dev + sp.offset, sp.count, rhs, st);
         if (e != hipSuccess) return hip_fail(e, "chain init launch");
+    }
 
-        FarArgs Fa{};
-        Fa.b = W.b;
-        Fa.a = W.a;
-        Fa.b32 = W.b32;
-        Fa.a32 = W.a32;
-        for (int tt = 0; tt < 3; ++tt) {
-            Fa.bh[tt] = W.bh[tt];
-            Fa.ah[tt] = W.ah[tt];
-            Fa.Fh[tt] = g.Fh[tt];
-        }
-        Fa.F32 = g.F32;
-        Fa.F = g.F;
-        Fa.ldF = g.ldF;
-        Fa.kchunk = pl->kchunk;
-        C.accn = g.accn;
-
-        // far field on s1, chain on s0; far(m+1) overlaps chain(m)
-        hipStream_t s1 = pl->overlap ? pl->far_stream : st;
-        const int64_t nblocks = (int64_t)g.active_traj.size();
-        const size_t ffhalf = pl->ffpart_bytes / sizeof(double);
-        hipEvent_t fork = sync_event();
-        if (!fork) return fail(ABM_EDEVICE, "event pool");
-        if ((e = hipEventRecord(fork, st)) != hipSuccess || (e = hipStreamWaitEvent(s1, fork, 0)) != hipSuccess)
-            return hip_fail(e, "stream fork");
-        std::vector<hipEvent_t> ev_chain(nblocks, nullptr), ev_far(nblocks + 1, nullptr);
-        std::vector<int> nsplit(nblocks + 1, 0);
-        for (int64_t m = 0; m < nblocks; ++m) {
-            const int64_t mf = m + 1;           // far field of the next block
-            if (mf < nblocks && mf >= 2) {
-                const int64_t kfar = (mf - 1) * L;
-                Fa.mL = mf * L;
-                Fa.kfar = kfar;
-                Fa.ldP = g.active_cols[mf];
-                Fa.nsplit = far_split_plan(kfar, pl->kchunk, pl->max_split, &Fa.nchunks,
-                                           &Fa.chunks_per_split);
-                Fa.part = pl->ffpart + (mf & 1) * ffhalf;
-                nsplit[mf] = Fa.nsplit;
-                if ((e = hipStreamWaitEvent(s1, ev_chain[m - 1], 0)) != hipSuccess)
-                    return hip_fail(e, "stream wait");
-                e = timed(0, s1, [&]() { return launch_far(Fa, L, g.prec, s1); });
+    // far field on s1, chain on s0; far(t+1) overlaps chain(t)
+    hipStream_t s1 = pl->overlap ? pl->far_stream : st;
+    hipEvent_t fork = sync_event();
+    if (!fork) return fail(ABM_EDEVICE, "event pool");
+    if ((e = hipEventRecord(fork, st)) != hipSuccess || (e = hipStreamWaitEvent(s1, fork, 0)) != hipSuccess)
+        return hip_fail(e, "stream fork");
+    hipEvent_t ev_chain_prev = nullptr, ev_far_prev = nullptr;
+    for (int64_t t = 0; t < pl->ticks; ++t) {
+        bool any_far = false;
+        for (int prec = 0; prec < 4; ++prec)
+            if (pl->far_spans[t * 4 + prec].count) any_far = true;
+        hipEvent_t ev_far = nullptr;
+        if (any_far) {
+            if (ev_chain_prev && (e = hipStreamWaitEvent(s1, ev_chain_prev, 0)) != hipSuccess)
+                return hip_fail(e, "stream wait");
+            for (int prec = 0; prec < 4; ++prec) {
+                const Span& sp = pl->far_spans[t * 4 + prec];
+                if (!sp.count) continue;
+                e = timed(0, s1, [&]() {
+                    return launch_far(pl->groups_dev, pl->far_items_dev + sp.offset, sp.count,
+                                      sp.max_x, sp.max_y, pl->kchunk, L, prec, s1);
+                });
                 if (e != hipSuccess) return hip_fail(e, "far-field launch");
                 ++S.far_launches;
-                for (int32_t jj = 0; jj < g.active_traj[mf]; ++jj) {
-                    const abm_problem& p = probs[g.members[jj]];
-                    const int64_t rows = std::min<int64_t>(L, p.N - mf * L);
-                    S.far_macs += (int64_t)p.d * rows * kfar;
-                }
-                ev_far[mf] = sync_event();
-                if (!ev_far[mf] || (e = hipEventRecord(ev_far[mf], s1)) != hipSuccess)
-                    return fail(ABM_EDEVICE, "far event");
             }
-            if (ev_far[m] && (e = hipStreamWaitEvent(st, ev_far[m], 0)) != hipSuccess)
-                return hip_fail(e, "stream wait");
-            C.ntraj = g.active_traj[m];
-            C.nchunks = nsplit[m];
-            C.ldP = g.active_cols[m];
-            C.part = pl->ffpart + (m & 1) * ffhalf;
-            C.mL = m * L;
-            e = timed(1, st, [&]() { return launch_chain(C, g.rhs, L, st); });
+            ev_far = sync_event();
+            if (!ev_far || (e = hipEventRecord(ev_far, s1)) != hipSuccess)
+                return fail(ABM_EDEVICE, "far event");
+        }
+        if (ev_far_prev && (e = hipStreamWaitEvent(st, ev_far_prev, 0)) != hipSuccess)
+            return hip_fail(e, "stream wait");
+        for (int rhs = 0; rhs < 5; ++rhs) {
+            const Span& sp = pl->chain_spans[t * 5 + rhs];
+            if (!sp.count) continue;
+            e = timed(1, st, [&]() {
+                return launch_chain(pl->groups_dev, pl->chain_items_dev + sp.offset, sp.count, rhs,
+                                    L, pl->status, st);
+            });
             if (e != hipSuccess) return hip_fail(e, "chain launch");
             ++S.chain_launches;
-            ev_chain[m] = sync_event();
-            if (!ev_chain[m] || (e = hipEventRecord(ev_chain[m], st)) != hipSuccess)
-                return fail(ABM_EDEVICE, "chain event");
         }
-        hipEvent_t join = sync_event();
-        if (!join || (e = hipEventRecord(join, s1)) != hipSuccess ||
-            (e = hipStreamWaitEvent(st, join, 0)) != hipSuccess)
-            return fail(ABM_EDEVICE, "stream join");
+        ev_chain_prev = sync_event();
+        if (!ev_chain_prev || (e = hipEventRecord(ev_chain_prev, st)) != hipSuccess)
+            return fail(ABM_EDEVICE, "chain event");
+        ev_far_prev = ev_far;
     }
+    hipEvent_t join = sync_event();
+    if (!join || (e = hipEventRecord(join, s1)) != hipSuccess ||
+        (e = hipStreamWaitEvent(st, join, 0)) != hipSuccess)
+        return fail(ABM_EDEVICE, "stream join");
+
     if (pl->timing && !tev.empty()) {
         e = hipStreamSynchronize(st);
         if (e != hipSuccess) return hip_fail(e, "timing sync");

@@ -26,6 +26,50 @@ namespace abm {
 
 namespace {
 
+// Per-wave view of one chain work item.
+struct ChainArgs {
+    const double* b;
+    const double* a;
+    const double* c;
+    const double* gam;
+    double alpha;
+    double* F;
+    float* F32;
+    uint16_t* Fhi;
+    uint16_t* Fmid;
+    uint16_t* Flo;
+    int64_t ldF;
+    int64_t rows;
+    const double* part;
+    int64_t ldP;
+    int64_t mL;
+    int32_t nchunks;
+    double* accn;          // this member's carried sums [2][d][L]
+};
+
+template <int L>
+__device__ __forceinline__ void chain_view(const GroupDev& G, const ChainItem& it, int D,
+                                           ChainArgs& A)
+{
+    A.b = G.b;
+    A.a = G.a;
+    A.c = G.c;
+    A.gam = G.gam;
+    A.alpha = G.alpha;
+    A.F = G.F;
+    A.F32 = G.F32;
+    A.Fhi = G.Fh[0];
+    A.Fmid = G.Fh[1];
+    A.Flo = G.Fh[2];
+    A.ldF = G.ldF;
+    A.rows = G.rows;
+    A.part = G.part[(it.mL / L) & 1];
+    A.ldP = it.ldP;
+    A.mL = it.mL;
+    A.nchunks = it.nsplit;
+    A.accn = G.accn + (size_t)it.member * 2 * D * L;
+}
+
 __device__ __forceinline__ double readlane_d(double v, int l)
 {
     const unsigned long long u = __builtin_bit_cast(unsigned long long, v);
@@ -43,7 +87,7 @@ __device__ __forceinline__ void store_history(const ChainArgs& A, const TrajDesc
     for (int i = 0; i < D; ++i) A.F[row + i] = fs[i];
     if (A.F32) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) A.F32[row + i] = (float)fs[i];
+        for (int i = 0; i < D; ++i) A.F32[colblocked_index(s, T.col0 + i, A.rows)] = (float)fs[i];
     }
     if (A.Fhi && s >= 1) {
 #pragma unroll
@@ -76,20 +120,28 @@ __device__ __forceinline__ void store_output(const TrajDesc& T, int64_t s, const
 }
 
 template <int R, int D, int L>
-__global__ __launch_bounds__(256) void k_chain(ChainArgs A)
+__global__ __launch_bounds__(256) void k_chain(const GroupDev* __restrict__ groups,
+                                               const ChainItem* __restrict__ items, int nitems,
+                                               uint32_t* status)
 {
     constexpr int Q = L / 64;
-    __shared__ double swb[2 * L], swa[2 * L];
-    for (int x = threadIdx.x; x < 2 * L; x += 256) {
+    extern __shared__ double smc[];           // per wave: b[0..2L), a[0..2L)
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int j = blockIdx.x * 4 + wid;
+    if (j >= nitems) return;                  // whole wave: no barrier below
+    const ChainItem it = items[j];
+    const GroupDev& G = groups[it.group];
+    ChainArgs A;
+    chain_view<L>(G, it, D, A);
+    const TrajDesc T = G.traj[it.member];
+    double* swb = smc + (size_t)wid * 4 * L;
+    double* swa = swb + 2 * L;
+    for (int x = lane; x < 2 * L; x += 64) {
         swb[x] = A.b[x];
         swa[x] = A.a[x];
     }
-    __syncthreads();
-
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int j = blockIdx.x * 4 + wid;
-    if (j >= A.ntraj) return;
-    const TrajDesc T = A.traj[j];
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     const int64_t mL = A.mL;
     if (mL >= T.N) return;
     const int rows = (int)((T.N - mL) < L ? (T.N - mL) : L);
@@ -108,7 +160,7 @@ __global__ __launch_bounds__(256) void k_chain(ChainArgs A)
 
     const int r0 = Q * lane;                  // first row of this lane
     // carried sums of block m (written by the previous block's chain)
-    double* accn = A.accn + (size_t)j * 2 * D * L;
+    double* accn = A.accn;
     double accP[Q][D], accC[Q][D], nxtP[Q][D], nxtC[Q][D];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -239,18 +291,25 @@ __global__ __launch_bounds__(256) void k_chain(ChainArgs A)
             }
         }
     }
-    if (bad) raise_status(A.status, kStatusNonFinite);
+    if (bad) raise_status(status, kStatusNonFinite);
 }
 
 template <int R, int D>
-hipError_t launch_rd(const ChainArgs& A, int L, hipStream_t st)
+hipError_t launch_rd(const GroupDev* groups, const ChainItem* items, int n, int L, uint32_t* status,
+                     hipStream_t st)
 {
-    const dim3 grid((unsigned)((A.ntraj + 3) / 4));
+    const dim3 grid((unsigned)((n + 3) / 4));
+    const size_t shmem = 4 * 4 * (size_t)L * sizeof(double);
+    hipError_t e = hipSuccess;
     switch (L) {
-    case 64: hipLaunchKernelGGL((k_chain<R, D, 64>), grid, dim3(256), 0, st, A); break;
-    case 128: hipLaunchKernelGGL((k_chain<R, D, 128>), grid, dim3(256), 0, st, A); break;
-    case 256: hipLaunchKernelGGL((k_chain<R, D, 256>), grid, dim3(256), 0, st, A); break;
-    case 512: hipLaunchKernelGGL((k_chain<R, D, 512>), grid, dim3(256), 0, st, A); break;
+    case 64: hipLaunchKernelGGL((k_chain<R, D, 64>), grid, dim3(256), shmem, st, groups, items, n, status); break;
+    case 128: hipLaunchKernelGGL((k_chain<R, D, 128>), grid, dim3(256), shmem, st, groups, items, n, status); break;
+    case 256: hipLaunchKernelGGL((k_chain<R, D, 256>), grid, dim3(256), shmem, st, groups, items, n, status); break;
+    case 512:
+        e = allow_lds(reinterpret_cast<const void*>(&k_chain<R, D, 512>), shmem);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_chain<R, D, 512>), grid, dim3(256), shmem, st, groups, items, n, status);
+        break;
     default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -258,11 +317,15 @@ hipError_t launch_rd(const ChainArgs& A, int L, hipStream_t st)
 
 // Solve start: f_0 = f(0, x0) into history row 0 (and reduced copies), y_0 = x0.
 template <int R, int D>
-__global__ void k_chain_init(ChainArgs A)
+__global__ void k_chain_init(const GroupDev* groups, const ChainItem* items, int n)
 {
     const int j = blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= A.ntraj) return;
-    const TrajDesc T = A.traj[j];
+    if (j >= n) return;
+    const ChainItem it = items[j];
+    const GroupDev& G = groups[it.group];
+    ChainArgs A;
+    chain_view<64>(G, it, D, A);
+    const TrajDesc T = G.traj[it.member];
     double x0[D], f0[D], p[8];
 #pragma unroll
     for (int i = 0; i < D; ++i) x0[i] = T.x0[i];
@@ -277,37 +340,39 @@ __global__ void k_chain_init(ChainArgs A)
 }
 
 template <int R, int D>
-hipError_t launch_init_rd(const ChainArgs& A, hipStream_t st)
+hipError_t launch_init_rd(const GroupDev* groups, const ChainItem* items, int n, hipStream_t st)
 {
-    hipLaunchKernelGGL((k_chain_init<R, D>), dim3((unsigned)((A.ntraj + 63) / 64)), dim3(64), 0, st,
-                       A);
+    hipLaunchKernelGGL((k_chain_init<R, D>), dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st,
+                       groups, items, n);
     return hipGetLastError();
 }
 
 }  // namespace
 
-hipError_t launch_chain(const ChainArgs& A, int rhs, int L, hipStream_t st)
+hipError_t launch_chain(const GroupDev* groups, const ChainItem* items, int n, int rhs, int L,
+                        uint32_t* status, hipStream_t st)
 {
-    if (A.ntraj <= 0) return hipSuccess;
+    if (n <= 0) return hipSuccess;
     switch (rhs) {
-    case ABM_RHS_LINEAR: return launch_rd<ABM_RHS_LINEAR, 1>(A, L, st);
-    case ABM_RHS_DUFFING: return launch_rd<ABM_RHS_DUFFING, 2>(A, L, st);
-    case ABM_RHS_LORENZ: return launch_rd<ABM_RHS_LORENZ, 3>(A, L, st);
-    case ABM_RHS_POLY: return launch_rd<ABM_RHS_POLY, 1>(A, L, st);
-    case ABM_RHS_LCR: return launch_rd<ABM_RHS_LCR, 2>(A, L, st);
+    case ABM_RHS_LINEAR: return launch_rd<ABM_RHS_LINEAR, 1>(groups, items, n, L, status, st);
+    case ABM_RHS_DUFFING: return launch_rd<ABM_RHS_DUFFING, 2>(groups, items, n, L, status, st);
+    case ABM_RHS_LORENZ: return launch_rd<ABM_RHS_LORENZ, 3>(groups, items, n, L, status, st);
+    case ABM_RHS_POLY: return launch_rd<ABM_RHS_POLY, 1>(groups, items, n, L, status, st);
+    case ABM_RHS_LCR: return launch_rd<ABM_RHS_LCR, 2>(groups, items, n, L, status, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_chain_init(const ChainArgs& A, int rhs, hipStream_t st)
+hipError_t launch_chain_init(const GroupDev* groups, const ChainItem* items, int n, int rhs,
+                             hipStream_t st)
 {
-    if (A.ntraj <= 0) return hipSuccess;
+    if (n <= 0) return hipSuccess;
     switch (rhs) {
-    case ABM_RHS_LINEAR: return launch_init_rd<ABM_RHS_LINEAR, 1>(A, st);
-    case ABM_RHS_DUFFING: return launch_init_rd<ABM_RHS_DUFFING, 2>(A, st);
-    case ABM_RHS_LORENZ: return launch_init_rd<ABM_RHS_LORENZ, 3>(A, st);
-    case ABM_RHS_POLY: return launch_init_rd<ABM_RHS_POLY, 1>(A, st);
-    case ABM_RHS_LCR: return launch_init_rd<ABM_RHS_LCR, 2>(A, st);
+    case ABM_RHS_LINEAR: return launch_init_rd<ABM_RHS_LINEAR, 1>(groups, items, n, st);
+    case ABM_RHS_DUFFING: return launch_init_rd<ABM_RHS_DUFFING, 2>(groups, items, n, st);
+    case ABM_RHS_LORENZ: return launch_init_rd<ABM_RHS_LORENZ, 3>(groups, items, n, st);
+    case ABM_RHS_POLY: return launch_init_rd<ABM_RHS_POLY, 1>(groups, items, n, st);
+    case ABM_RHS_LCR: return launch_init_rd<ABM_RHS_LCR, 2>(groups, items, n, st);
     default: return hipErrorInvalidValue;
     }
 }

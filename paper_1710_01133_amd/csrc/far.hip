@@ -19,8 +19,7 @@
 // lane (i, kk) of a fragment reads the weight at index mL + r - k from an LDS
 // copy of the chunk's weight window.  The partial result of each workgroup
 // goes to FFpart[split][col][2L]; the chain kernel adds the splits in order.
-#include "abm_dev.h"
-#include "abm_kernels.h"
+#include "far_common.h"
 
 namespace abm {
 
@@ -31,10 +30,13 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 constexpr int kKS = 16;   // history rows per LDS stage
 
 template <int MT, int NT>
-__global__ __launch_bounds__(256) void k_far_f64(FarArgs A)
+__global__ __launch_bounds__(256) void k_far_f64(const GroupDev* groups, const FarItem* items,
+                                                 int kchunk)
 {
     constexpr int L = 32 * MT;       // block length
     constexpr int TN = 16 * NT;      // columns per workgroup
+    FarArgs A;
+    if (!far_view(groups, items, kchunk, L, A)) return;
     extern __shared__ double sm[];
     const int win = L + A.kchunk;    // weight window length (padded)
     double* wb = sm;                 // b window
@@ -141,14 +143,16 @@ __global__ __launch_bounds__(256) void k_far_f64(FarArgs A)
 }
 
 template <int MT, int NT>
-hipError_t launch_t(const FarArgs& A, hipStream_t st)
+hipError_t launch_t(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
+                    int max_nsplit, int kchunk, hipStream_t st)
 {
     constexpr int L = 32 * MT, TN = 16 * NT;
-    const size_t shmem = (2 * (size_t)(L + A.kchunk) + 2 * kKS * TN) * sizeof(double);
+    (void)TN;
+    const size_t shmem = (2 * (size_t)(L + kchunk) + 2 * kKS * TN) * sizeof(double);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_f64<MT, NT>), shmem);
     if (e != hipSuccess) return e;
-    dim3 grid((unsigned)(A.ldP / TN), (unsigned)A.nsplit);
-    hipLaunchKernelGGL((k_far_f64<MT, NT>), grid, dim3(256), shmem, st, A);
+    dim3 grid((unsigned)max_coltiles, (unsigned)max_nsplit, (unsigned)n);
+    hipLaunchKernelGGL((k_far_f64<MT, NT>), grid, dim3(256), shmem, st, groups, items, kchunk);
     return hipGetLastError();
 }
 
@@ -195,15 +199,26 @@ int far_split_plan(int64_t kfar, int kchunk, int max_split, int* nchunks, int* c
     return (nc + cps - 1) / cps;
 }
 
-hipError_t launch_far(const FarArgs& A, int L, int prec, hipStream_t st)
+int far_split_bound(int64_t kfar_max, int kchunk, int max_split)
 {
-    if (A.kfar < 1 || A.nsplit < 1) return hipSuccess;
-    if (prec != ABM_FAR_FP64) return launch_far_lp(A, L, prec, st);
+    // the slice count of far_split_plan is not monotone in kfar (e.g. 8
+    // chunks give 8 slices, 10 chunks give 5), so bound it over all blocks
+    if (kfar_max < 1) return 0;
+    const int64_t nc = (kfar_max + kchunk - 1) / kchunk;
+    return (int)(nc < max_split ? nc : max_split);
+}
+
+hipError_t launch_far(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
+                      int max_nsplit, int kchunk, int L, int prec, hipStream_t st)
+{
+    if (n < 1 || max_coltiles < 1 || max_nsplit < 1) return hipSuccess;
+    if (prec != ABM_FAR_FP64)
+        return launch_far_lp(groups, items, n, max_coltiles, max_nsplit, kchunk, L, prec, st);
     switch (L) {
-    case 64: return launch_t<2, 8>(A, st);
-    case 128: return launch_t<4, 4>(A, st);
-    case 256: return launch_t<8, 2>(A, st);
-    case 512: return launch_t<16, 1>(A, st);
+    case 64: return launch_t<2, 8>(groups, items, n, max_coltiles, max_nsplit, kchunk, st);
+    case 128: return launch_t<4, 4>(groups, items, n, max_coltiles, max_nsplit, kchunk, st);
+    case 256: return launch_t<8, 2>(groups, items, n, max_coltiles, max_nsplit, kchunk, st);
+    case 512: return launch_t<16, 1>(groups, items, n, max_coltiles, max_nsplit, kchunk, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -1,0 +1,63 @@
+// Per-workgroup view of one far-field work item (shared by the far kernels).
+#pragma once
+#include "abm_dev.h"
+#include "abm_kernels.h"
+
+namespace abm {
+
+struct FarArgs {
+    const double* b;
+    const double* a;
+    const float* b32;
+    const float* a32;
+    const uint16_t* bh[3];
+    const uint16_t* ah[3];
+    const double* F;
+    const float* F32;
+    const uint16_t* Fh[3];
+    int64_t ldF;
+    int64_t rows;
+    int64_t mL;
+    int64_t kfar;
+    int32_t kchunk;
+    int32_t nchunks;
+    int32_t chunks_per_split;
+    double* part;
+    int64_t ldP;
+};
+
+// Fills A for work item blockIdx.z; false when this workgroup lies beyond the
+// item's column tiles or history splits (the launch grid covers the largest
+// item).
+__device__ __forceinline__ bool far_view(const GroupDev* __restrict__ groups,
+                                         const FarItem* __restrict__ items, int kchunk, int L,
+                                         FarArgs& A)
+{
+    const FarItem it = items[blockIdx.z];
+    if ((int)blockIdx.x >= it.ncoltiles || (int)blockIdx.y >= it.nsplit) return false;
+    const GroupDev& G = groups[it.group];
+    A.b = G.b;
+    A.a = G.a;
+    A.b32 = G.b32;
+    A.a32 = G.a32;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        A.bh[i] = G.bh[i];
+        A.ah[i] = G.ah[i];
+        A.Fh[i] = G.Fh[i];
+    }
+    A.F = G.F;
+    A.F32 = G.F32;
+    A.ldF = G.ldF;
+    A.rows = G.rows;
+    A.mL = it.mL;
+    A.kfar = it.kfar;
+    A.kchunk = kchunk;
+    A.nchunks = it.nchunks;
+    A.chunks_per_split = it.chunks_per_split;
+    A.part = G.part[(it.mL / L) & 1];
+    A.ldP = it.ldP;
+    return true;
+}
+
+}  // namespace abm

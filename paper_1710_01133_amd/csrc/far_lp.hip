@@ -28,8 +28,7 @@
 // so fragment(t, q) = fragment(t+2, q+1): a ring of MT fragments per split
 // term is kept in registers and only two new ones are read per K-step (the
 // 2-byte-aligned 16-byte LDS reads are single ds_read_b128 on gfx950).
-#include "abm_dev.h"
-#include "abm_kernels.h"
+#include "far_common.h"
 
 namespace abm {
 
@@ -90,9 +89,12 @@ __device__ __forceinline__ void store_part(const FarArgs& A, const d4 (&acc64)[M
 // ------------------------------------------------------------------ float
 // 8 waves: waves 0-3 own predictor rows, 4-7 corrector rows, L/4 rows each.
 template <int MT>
-__global__ __launch_bounds__(512, (MT <= 8) ? 1 : 1) void k_far_f32(FarArgs A)
+__global__ __launch_bounds__(512, 1) void k_far_f32(const GroupDev* groups, const FarItem* items,
+                                                    int kchunk)
 {
     constexpr int L = 64 * MT, TN = 16;
+    FarArgs A;
+    if (!far_view(groups, items, kchunk, L, A)) return;
     constexpr int KS = 32;                      // history rows per LDS stage
     constexpr int kFlushSteps = 4;              // 16 history rows per float run
     extern __shared__ float smf[];
@@ -119,7 +121,9 @@ __global__ __launch_bounds__(512, (MT <= 8) ? 1 : 1) void k_far_f32(FarArgs A)
 
     constexpr int kStageElems = KS * TN;        // 512: one element per thread
     float pre = 0.f;
-    auto load_stage = [&](int64_t k0) { pre = A.F32[(k0 + t / TN) * A.ldF + col0 + t % TN]; };
+    // column-blocked float history: this workgroup's 16 columns are contiguous
+    const float* Fblk = A.F32 + (int64_t)(col0 >> 4) * A.rows * 16;
+    auto load_stage = [&](int64_t k0) { pre = Fblk[k0 * 16 + t]; };
     auto store_stage = [&](int buf) { Ft[buf * kStageElems + t] = pre; };
 
     const int c_begin = blockIdx.y * A.chunks_per_split;
@@ -161,9 +165,12 @@ __global__ __launch_bounds__(512, (MT <= 8) ? 1 : 1) void k_far_f32(FarArgs A)
 
 // ------------------------------------------------------------------ bf16 split
 template <int MT, int TERMS>
-__global__ __launch_bounds__(512, 1) void k_far_bf16(FarArgs A)
+__global__ __launch_bounds__(512, 1) void k_far_bf16(const GroupDev* groups, const FarItem* items,
+                                                     int kchunk)
 {
     constexpr int L = 64 * MT, TN = 16;
+    FarArgs A;
+    if (!far_view(groups, items, kchunk, L, A)) return;
     constexpr int QS = 4;                       // K-steps (32 rows) per stage
     constexpr int KS = 32 * QS;                 // history rows per stage
     constexpr int NB8 = KS / 8;                 // 8-row blocks per stage
@@ -288,28 +295,35 @@ __global__ __launch_bounds__(512, 1) void k_far_bf16(FarArgs A)
     store_part<MT, 1>(A, acc64, col0, (corr ? L : 0) + rbase, li, g, L);
 }
 
+struct LpLaunch {
+    const GroupDev* groups;
+    const FarItem* items;
+    int n, max_coltiles, max_nsplit, kchunk;
+};
+
 template <int MT>
-hipError_t launch_f32_t(const FarArgs& A, hipStream_t st)
+hipError_t launch_f32_t(const LpLaunch& P, hipStream_t st)
 {
-    constexpr int L = 64 * MT, TN = 16;
-    const size_t shmem = far_lp_lds_bytes(L, A.kchunk, ABM_FAR_FP32);
+    constexpr int L = 64 * MT;
+    const size_t shmem = far_lp_lds_bytes(L, P.kchunk, ABM_FAR_FP32);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_f32<MT>), shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_far_f32<MT>), dim3((unsigned)(A.ldP / TN), (unsigned)A.nsplit),
-                       dim3(512), shmem, st, A);
+    hipLaunchKernelGGL((k_far_f32<MT>), dim3((unsigned)P.max_coltiles, (unsigned)P.max_nsplit, (unsigned)P.n),
+                       dim3(512), shmem, st, P.groups, P.items, P.kchunk);
     return hipGetLastError();
 }
 
 template <int MT, int TERMS>
-hipError_t launch_bf16_t(const FarArgs& A, hipStream_t st)
+hipError_t launch_bf16_t(const LpLaunch& P, hipStream_t st)
 {
-    constexpr int L = 64 * MT, TN = 16;
+    constexpr int L = 64 * MT;
     const size_t shmem =
-        far_lp_lds_bytes(L, A.kchunk, TERMS == 2 ? ABM_FAR_BF16X3 : ABM_FAR_BF16X6);
+        far_lp_lds_bytes(L, P.kchunk, TERMS == 2 ? ABM_FAR_BF16X3 : ABM_FAR_BF16X6);
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_bf16<MT, TERMS>), shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_far_bf16<MT, TERMS>), dim3((unsigned)(A.ldP / TN), (unsigned)A.nsplit),
-                       dim3(512), shmem, st, A);
+    hipLaunchKernelGGL((k_far_bf16<MT, TERMS>),
+                       dim3((unsigned)P.max_coltiles, (unsigned)P.max_nsplit, (unsigned)P.n),
+                       dim3(512), shmem, st, P.groups, P.items, P.kchunk);
     return hipGetLastError();
 }
 
@@ -324,8 +338,10 @@ size_t far_lp_lds_bytes(int L, int kchunk, int prec)
     return 2 * (size_t)terms * (L + kchunk) * 2 + 2 * (size_t)terms * (128 / 8) * TN * 16;
 }
 
-hipError_t launch_far_lp(const FarArgs& A, int L, int prec, hipStream_t st)
+hipError_t launch_far_lp(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
+                         int max_nsplit, int kchunk, int L, int prec, hipStream_t st)
 {
+    const LpLaunch A{groups, items, n, max_coltiles, max_nsplit, kchunk};
     if (prec == ABM_FAR_FP32) {
         switch (L) {
         case 128: return launch_f32_t<2>(A, st);

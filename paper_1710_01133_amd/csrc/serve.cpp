@@ -1,12 +1,591 @@
-// Serving loop of libabm (abm_submit / abm_poll / abm_cancel).
+// Serving loop of libabm: abm_submit / abm_poll / abm_cancel.
+//
+// A server thread per context owns two HIP streams and a device arena.
+// Requests queue in arrival order; the head of the queue is admitted as soon
+// as its device footprint (weight tables, history and its reduced copy,
+// carried sums, far partials) fits the free arena memory, so admission is
+// FIFO and never over-commits the arena.  Every admitted request is a group
+// of one trajectory with its own weight table.  The server advances all
+// admitted requests in ticks, exactly like abm_solve_batch: one far-field
+// launch per precision class and one chain launch per right-hand side per
+// tick cover every active request, whatever its alpha, N or start time;
+// requests admitted while others run join at the next tick (continuous
+// batching).  A request's arithmetic does not depend on what else is running
+// (each group has its own columns and chunking), so its result is the same
+// alone and in the mix.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
 #include "abm.h"
+#include "abm_kernels.h"
 #include "abm_runtime.h"
 
 namespace abm {
 
-void serve_shutdown(abm_ctx* ctx) { (void)ctx; }
+namespace {
+
+constexpr int kMaxActive = 1024;     // group slots on the device
+constexpr int kRing = 8;             // ticks in flight (item staging ring)
+constexpr size_t kAlign = 256;
+
+double now_s()
+{
+    return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+enum ReqState { kQueued, kRunning, kDone };
+
+struct Request {
+    uint64_t ticket = 0;
+    abm_problem prob{};
+    double* y_out = nullptr;
+    double t_submit = 0, t_start = 0, t_done = 0;
+    ReqState state = kQueued;
+    abm_status status = ABM_OK;
+    bool cancel = false;
+    // device side (valid while running)
+    size_t off = 0, bytes = 0;        // arena chunk
+    int slot = -1;
+    WeightTable W{};
+    Group g{};
+    int64_t m = 0, nblocks = 0;
+    bool finishing = false;           // last work enqueued; waiting for done_ev
+    bool cancel_seen = false;         // cancellation observed by the server thread
+    hipEvent_t done_ev = nullptr;
+    double* final_host = nullptr;     // pinned: last state (4 doubles), then the descriptor
+    double max_abs_y = 0;
+};
+
+}  // namespace
+
+struct ServeState {
+    abm_ctx* ctx = nullptr;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::thread th;
+    bool stop = false;
+    bool started = false;
+    std::deque<Request*> pending;
+    std::unordered_map<uint64_t, Request*> all;
+    uint64_t next_ticket = 1;
+    // owned by the server thread
+    int L = 256, kchunk = 2048, max_split = 8;
+    char* arena = nullptr;
+    size_t arena_cap = 0;
+    std::map<size_t, size_t> free_list;   // offset -> size
+    std::vector<Request*> active;
+    std::vector<int> free_slots;
+    hipStream_t s0 = nullptr, s1 = nullptr;
+    GroupDev* groups_dev = nullptr;
+    GroupDev* groups_host = nullptr;      // pinned staging, one entry per slot
+    FarItem* far_dev = nullptr;           // [kRing][kMaxActive]
+    ChainItem* chain_dev = nullptr;       // [kRing][kMaxActive]
+    ChainItem* init_dev = nullptr;        // [kRing][kMaxActive]
+    FarItem* far_host = nullptr;
+    ChainItem* chain_host = nullptr;
+    ChainItem* init_host = nullptr;
+    hipEvent_t ring_ev[kRing] = {};
+    bool ring_live[kRing] = {};
+    int64_t tick = 0;
+    hipEvent_t ev_chain_prev = nullptr, ev_far_prev = nullptr;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_next = 0;
+    uint32_t* status = nullptr;
+    std::string error;
+};
+
+namespace {
+
+bool arena_alloc(ServeState* S, size_t bytes, size_t* off)
+{
+    for (auto it = S->free_list.begin(); it != S->free_list.end(); ++it) {
+        if (it->second >= bytes) {
+            *off = it->first;
+            const size_t rest = it->second - bytes;
+            const size_t roff = it->first + bytes;
+            S->free_list.erase(it);
+            if (rest) S->free_list[roff] = rest;
+            return true;
+        }
+    }
+    return false;
+}
+
+void arena_free(ServeState* S, size_t off, size_t bytes)
+{
+    auto it = S->free_list.emplace(off, bytes).first;
+    auto nx = std::next(it);
+    if (nx != S->free_list.end() && it->first + it->second == nx->first) {
+        it->second += nx->second;
+        S->free_list.erase(nx);
+    }
+    if (it != S->free_list.begin()) {
+        auto pv = std::prev(it);
+        if (pv->first + pv->second == it->first) {
+            pv->second += it->second;
+            S->free_list.erase(it);
+        }
+    }
+}
+
+// Layout of one request's arena chunk (all offsets 256-byte aligned).
+struct ReqLayout {
+    size_t gam, b, a, c, b32, a32, bh[3], ah[3], F, F32, Fh[3], traj, accn, part, total;
+    int64_t wn, rows, ldF;
+    size_t part_half;
+};
+
+ReqLayout layout_of(const abm_problem& p, int L, int kchunk, int max_split)
+{
+    ReqLayout r{};
+    const int TN = far_tile_cols(L, p.far_prec);
+    r.wn = p.N + kWeightPad;
+    r.rows = p.N + 1 + L;
+    r.ldF = (p.d + TN - 1) / TN * TN;
+    size_t o = 0;
+    auto take = [&](size_t bytes) { const size_t at = o; o += align_up(bytes); return at; };
+    r.gam = take(2 * sizeof(double));
+    r.b = take(r.wn * sizeof(double));
+    r.a = take(r.wn * sizeof(double));
+    r.c = take(r.wn * sizeof(double));
+    r.b32 = r.a32 = 0;
+    for (int i = 0; i < 3; ++i) r.bh[i] = r.ah[i] = r.Fh[i] = 0;
+    if (p.far_prec == ABM_FAR_FP32) {
+        r.b32 = take(r.wn * sizeof(float));
+        r.a32 = take(r.wn * sizeof(float));
+    } else if (p.far_prec != ABM_FAR_FP64) {
+        for (int i = 0; i < 3; ++i) {
+            r.bh[i] = take(r.wn * sizeof(uint16_t));
+            r.ah[i] = take(r.wn * sizeof(uint16_t));
+        }
+    }
+    r.F = take((size_t)r.rows * r.ldF * sizeof(double));
+    r.F32 = 0;
+    if (p.far_prec == ABM_FAR_FP32) r.F32 = take((size_t)r.rows * r.ldF * sizeof(float));
+    if (p.far_prec == ABM_FAR_BF16X3 || p.far_prec == ABM_FAR_BF16X6) {
+        const int terms = p.far_prec == ABM_FAR_BF16X3 ? 2 : 3;
+        for (int i = 0; i < terms; ++i)
+            r.Fh[i] = take((size_t)((r.rows + 7) / 8) * r.ldF * 8 * sizeof(uint16_t));
+    }
+    r.traj = take(sizeof(TrajDesc));
+    r.accn = take((size_t)2 * p.d * L * sizeof(double));
+    const int64_t nblocks = (p.N + L - 1) / L;
+    const int64_t kfar_max = nblocks >= 2 ? (nblocks - 2) * L : 0;
+    const int nsp = std::max(1, far_split_bound(kfar_max, kchunk, max_split));
+    r.part_half = (size_t)nsp * r.ldF * 2 * L;
+    r.part = take(2 * r.part_half * sizeof(double));
+    r.total = o;
+    return r;
+}
+
+hipEvent_t pooled_event(ServeState* S)
+{
+    // events are recycled round-robin; a pool much larger than the ticks in
+    // flight guarantees an event is never re-recorded while still awaited
+    if (S->ev_pool.empty()) return nullptr;
+    hipEvent_t ev = S->ev_pool[S->ev_next];
+    S->ev_next = (S->ev_next + 1) % S->ev_pool.size();
+    return ev;
+}
+
+abm_status server_init(ServeState* S)
+{
+    abm_ctx* ctx = S->ctx;
+    hipError_t e = hipSetDevice(ctx->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    S->L = env_int("ABM_SERVE_BLOCK_L", 256);
+    if (S->L != 128 && S->L != 256 && S->L != 512)
+        return fail(ABM_EINVAL, "ABM_SERVE_BLOCK_L must be 128, 256 or 512");
+    S->kchunk = 2048;
+    for (int prec = 0; prec < 4; ++prec)
+        while (S->kchunk > 512 && far_lds_bytes(S->L, S->kchunk, prec) > kMaxLds) S->kchunk -= 512;
+    S->arena_cap = ctx->arena_bytes;
+    if ((e = hipMalloc((void**)&S->arena, S->arena_cap)) != hipSuccess) return hip_fail(e, "arena");
+    S->free_list[0] = S->arena_cap;
+    if ((e = hipStreamCreateWithFlags(&S->s0, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipStreamCreateWithFlags(&S->s1, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "server streams");
+    abm_status s;
+    if ((s = dev_alloc((void**)&S->groups_dev, kMaxActive * sizeof(GroupDev), "group slots")) ||
+        (s = dev_alloc((void**)&S->far_dev, (size_t)kRing * kMaxActive * sizeof(FarItem), "far ring")) ||
+        (s = dev_alloc((void**)&S->chain_dev, (size_t)kRing * kMaxActive * sizeof(ChainItem), "chain ring")) ||
+        (s = dev_alloc((void**)&S->init_dev, (size_t)kRing * kMaxActive * sizeof(ChainItem), "init ring")) ||
+        (s = dev_alloc((void**)&S->status, sizeof(uint32_t), "status")))
+        return s;
+    if ((e = hipHostMalloc((void**)&S->groups_host, kMaxActive * sizeof(GroupDev), hipHostMallocDefault)) ||
+        (e = hipHostMalloc((void**)&S->far_host, (size_t)kRing * kMaxActive * sizeof(FarItem), hipHostMallocDefault)) ||
+        (e = hipHostMalloc((void**)&S->chain_host, (size_t)kRing * kMaxActive * sizeof(ChainItem), hipHostMallocDefault)) ||
+        (e = hipHostMalloc((void**)&S->init_host, (size_t)kRing * kMaxActive * sizeof(ChainItem), hipHostMallocDefault)))
+        return hip_fail(e, "pinned staging");
+    for (int i = 0; i < kRing; ++i)
+        if ((e = hipEventCreateWithFlags(&S->ring_ev[i], hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "event");
+    S->ev_pool.resize(64 * kRing);
+    for (auto& ev : S->ev_pool)
+        if ((e = hipEventCreateWithFlags(&ev, hipEventDisableTiming)) != hipSuccess)
+            return hip_fail(e, "event");
+    for (int i = kMaxActive - 1; i >= 0; --i) S->free_slots.push_back(i);
+    (void)launch_fill_u32(S->status, 0, 1, S->s0);
+    return ABM_OK;
+}
+
+// Device setup of an admitted request on stream s0: carve its arena chunk,
+// generate its weight tables, publish its group slot and descriptor.
+abm_status admit(ServeState* S, Request* r, size_t off, const ReqLayout& lay)
+{
+    const abm_problem& p = r->prob;
+    char* base = S->arena + off;
+    r->off = off;
+    r->bytes = lay.total;
+    r->slot = S->free_slots.back();
+    S->free_slots.pop_back();
+    WeightTable& W = r->W;
+    W.alpha = p.alpha;
+    W.n = p.N;
+    W.gam = (double*)(base + lay.gam);
+    W.b = (double*)(base + lay.b);
+    W.a = (double*)(base + lay.a);
+    W.c = (double*)(base + lay.c);
+    W.b32 = lay.b32 ? (float*)(base + lay.b32) : nullptr;
+    W.a32 = lay.a32 ? (float*)(base + lay.a32) : nullptr;
+    for (int i = 0; i < 3; ++i) {
+        W.bh[i] = lay.bh[i] ? (uint16_t*)(base + lay.bh[i]) : nullptr;
+        W.ah[i] = lay.ah[i] ? (uint16_t*)(base + lay.ah[i]) : nullptr;
+    }
+    Group& g = r->g;
+    g.table = 0;
+    g.rhs = p.rhs;
+    g.d = p.d;
+    g.prec = p.far_prec;
+    g.nmax = p.N;
+    g.members = {0};
+    g.col0 = {0};
+    g.cols = p.d;
+    g.ldF = lay.ldF;
+    g.rows = lay.rows;
+    g.F = (double*)(base + lay.F);
+    g.F32 = lay.F32 ? (float*)(base + lay.F32) : nullptr;
+    for (int i = 0; i < 3; ++i) g.Fh[i] = lay.Fh[i] ? (uint16_t*)(base + lay.Fh[i]) : nullptr;
+    g.traj_dev = (TrajDesc*)(base + lay.traj);
+    g.accn = (double*)(base + lay.accn);
+    g.part_half = lay.part_half;
+    g.nsplit_cap = (int)(lay.part_half / ((size_t)lay.ldF * 2 * S->L));
+    g.part[0] = (double*)(base + lay.part);
+    g.part[1] = g.part[0] + lay.part_half;
+    r->m = 0;
+    r->nblocks = (p.N + S->L - 1) / S->L;
+
+    hipError_t e = launch_weights(p.alpha, lay.wn, W.gam, W.b, W.a, W.c, S->s0);
+    if (e == hipSuccess && (W.b32 || W.bh[0]))
+        e = launch_weights_lowp(lay.wn, W.b, W.a, W.b32, W.a32, W.bh, W.ah, S->s0);
+    if (e != hipSuccess) return hip_fail(e, "request weights");
+    // descriptor and group slot through pinned staging (the slot's staging
+    // entry is only rewritten when the slot is reused, long after this copy)
+    if ((e = hipHostMalloc((void**)&r->final_host, 4 * sizeof(double) + sizeof(TrajDesc),
+                           hipHostMallocDefault)) != hipSuccess)
+        return hip_fail(e, "pinned staging");
+    GroupDev gd = group_dev(g, W);
+    S->groups_host[r->slot] = gd;
+    if ((e = hipMemcpyAsync(&S->groups_dev[r->slot], &S->groups_host[r->slot], sizeof(GroupDev),
+                            hipMemcpyHostToDevice, S->s0)) != hipSuccess)
+        return hip_fail(e, "slot upload");
+    TrajDesc& T = *reinterpret_cast<TrajDesc*>(r->final_host + 4);
+    memset(&T, 0, sizeof T);
+    for (int i = 0; i < 4; ++i) T.x0[i] = p.x0[i];
+    for (int i = 0; i < 8; ++i) T.p[i] = p.p[i];
+    T.h = p.h;
+    T.N = p.N;
+    T.out_stride = p.out_stride;
+    T.y_out = r->y_out;
+    T.col0 = 0;
+    if ((e = hipMemcpyAsync(g.traj_dev, &T, sizeof T, hipMemcpyHostToDevice, S->s0)) != hipSuccess)
+        return hip_fail(e, "descriptor upload");
+    if ((e = hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming)) != hipSuccess)
+        return hip_fail(e, "event");
+    return ABM_OK;
+}
+
+void release(ServeState* S, Request* r)
+{
+    arena_free(S, r->off, r->bytes);
+    S->free_slots.push_back(r->slot);
+    if (r->done_ev) (void)hipEventDestroy(r->done_ev);
+    if (r->final_host) (void)hipHostFree(r->final_host);
+    r->done_ev = nullptr;
+    r->final_host = nullptr;
+    r->slot = -1;
+}
+
+// Enqueue one tick for every active request.
+abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
+{
+    const int ring = (int)(S->tick % kRing);
+    hipError_t e;
+    if (S->ring_live[ring] && (e = hipEventSynchronize(S->ring_ev[ring])) != hipSuccess)
+        return hip_fail(e, "ring wait");
+    FarItem* fh = S->far_host + (size_t)ring * kMaxActive;
+    ChainItem* ch = S->chain_host + (size_t)ring * kMaxActive;
+    ChainItem* ih = S->init_host + (size_t)ring * kMaxActive;
+    // items grouped by class: far by precision, chain and init by rhs
+    std::vector<FarItem> far[4];
+    std::vector<ChainItem> chain[5], init[5];
+    for (Request* r : S->active) {
+        if (r->finishing || r->cancel_seen) continue;
+        const std::vector<int64_t> memberN{r->prob.N};
+        const size_t f0 = far[r->g.prec].size(), c0 = chain[r->g.rhs].size();
+        block_items(r->g, r->slot, r->m, S->L, S->kchunk, S->max_split, memberN,
+                    &far[r->g.prec], &chain[r->g.rhs]);
+        // every item must fit the request's partial buffers (checked, not assumed)
+        for (size_t k = f0; k < far[r->g.prec].size(); ++k)
+            if (far[r->g.prec][k].nsplit > r->g.nsplit_cap || far[r->g.prec][k].ldP > r->g.ldF)
+                return fail(ABM_EDEVICE, "internal: far item exceeds a request's partial buffer");
+        for (size_t k = c0; k < chain[r->g.rhs].size(); ++k)
+            if (chain[r->g.rhs][k].nsplit > r->g.nsplit_cap)
+                return fail(ABM_EDEVICE, "internal: chain item exceeds a request's partial buffer");
+    }
+    for (Request* r : fresh) {
+        ChainItem c{};
+        c.group = r->slot;
+        c.member = 0;
+        init[r->g.rhs].push_back(c);
+    }
+    int nf = 0, nc = 0, ni = 0;
+    Span fsp[4], csp[5], isp[5];
+    for (int k = 0; k < 4; ++k) {
+        fsp[k].offset = nf;
+        fsp[k].count = (int32_t)far[k].size();
+        for (const FarItem& it : far[k]) {
+            fsp[k].max_x = std::max(fsp[k].max_x, it.ncoltiles);
+            fsp[k].max_y = std::max(fsp[k].max_y, it.nsplit);
+            fh[nf++] = it;
+        }
+    }
+    for (int k = 0; k < 5; ++k) {
+        csp[k].offset = nc;
+        csp[k].count = (int32_t)chain[k].size();
+        for (const ChainItem& it : chain[k]) ch[nc++] = it;
+        isp[k].offset = ni;
+        isp[k].count = (int32_t)init[k].size();
+        for (const ChainItem& it : init[k]) ih[ni++] = it;
+    }
+    FarItem* fd = S->far_dev + (size_t)ring * kMaxActive;
+    ChainItem* cd = S->chain_dev + (size_t)ring * kMaxActive;
+    ChainItem* id = S->init_dev + (size_t)ring * kMaxActive;
+    // items reach s1 through s0: upload on s0, then s1 waits for it
+    if (nf && (e = hipMemcpyAsync(fd, fh, nf * sizeof(FarItem), hipMemcpyHostToDevice, S->s0)))
+        return hip_fail(e, "item upload");
+    if (nc && (e = hipMemcpyAsync(cd, ch, nc * sizeof(ChainItem), hipMemcpyHostToDevice, S->s0)))
+        return hip_fail(e, "item upload");
+    if (ni && (e = hipMemcpyAsync(id, ih, ni * sizeof(ChainItem), hipMemcpyHostToDevice, S->s0)))
+        return hip_fail(e, "item upload");
+    hipEvent_t up = pooled_event(S);
+    if ((e = hipEventRecord(up, S->s0)) != hipSuccess) return hip_fail(e, "event");
+
+    hipEvent_t ev_far = nullptr;
+    if (nf) {
+        if ((e = hipStreamWaitEvent(S->s1, up, 0)) != hipSuccess) return hip_fail(e, "wait");
+        if (S->ev_chain_prev && (e = hipStreamWaitEvent(S->s1, S->ev_chain_prev, 0)) != hipSuccess)
+            return hip_fail(e, "wait");
+        for (int k = 0; k < 4; ++k) {
+            if (!fsp[k].count) continue;
+            e = launch_far(S->groups_dev, fd + fsp[k].offset, fsp[k].count, fsp[k].max_x,
+                           fsp[k].max_y, S->kchunk, S->L, k, S->s1);
+            if (e != hipSuccess) return hip_fail(e, "far-field launch");
+        }
+        ev_far = pooled_event(S);
+        if ((e = hipEventRecord(ev_far, S->s1)) != hipSuccess) return hip_fail(e, "event");
+    }
+    if (S->ev_far_prev && (e = hipStreamWaitEvent(S->s0, S->ev_far_prev, 0)) != hipSuccess)
+        return hip_fail(e, "wait");
+    for (int k = 0; k < 5; ++k) {
+        if (isp[k].count &&
+            (e = launch_chain_init(S->groups_dev, id + isp[k].offset, isp[k].count, k, S->s0)) != hipSuccess)
+            return hip_fail(e, "init launch");
+    }
+    for (int k = 0; k < 5; ++k) {
+        if (csp[k].count &&
+            (e = launch_chain(S->groups_dev, cd + csp[k].offset, csp[k].count, k, S->L, S->status,
+                              S->s0)) != hipSuccess)
+            return hip_fail(e, "chain launch");
+    }
+    // requests whose last block ran in this tick: copy the last state, mark done
+    for (Request* r : S->active) {
+        if (r->finishing) continue;
+        if (r->cancel_seen) {
+            // no more work for it; done once what was already issued has run
+            if ((e = hipEventRecord(r->done_ev, S->s0)) != hipSuccess) return hip_fail(e, "event");
+            r->finishing = true;
+            continue;
+        }
+        r->m += 1;
+        if (r->m >= r->nblocks) {
+            const int64_t nout = n_out(r->prob.N, r->prob.out_stride);
+            if ((e = hipMemcpyAsync(r->final_host, r->y_out + (nout - 1) * r->prob.d,
+                                    r->prob.d * sizeof(double), hipMemcpyDeviceToHost, S->s0)))
+                return hip_fail(e, "result copy");
+            if ((e = hipEventRecord(r->done_ev, S->s0)) != hipSuccess) return hip_fail(e, "event");
+            r->finishing = true;
+        }
+    }
+    S->ev_chain_prev = pooled_event(S);
+    if ((e = hipEventRecord(S->ev_chain_prev, S->s0)) != hipSuccess) return hip_fail(e, "event");
+    S->ev_far_prev = ev_far;
+    if ((e = hipEventRecord(S->ring_ev[ring], S->s0)) != hipSuccess) return hip_fail(e, "event");
+    S->ring_live[ring] = true;
+    ++S->tick;
+    return ABM_OK;
+}
+
+void server_loop(ServeState* S)
+{
+    if (server_init(S) != ABM_OK) {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->error = abm_last_error();
+        for (auto& kv : S->all) {
+            kv.second->state = kDone;
+            kv.second->status = ABM_EDEVICE;
+        }
+        S->stop = true;
+        return;
+    }
+    for (;;) {
+        std::vector<Request*> fresh;
+        {
+            std::unique_lock<std::mutex> lk(S->mu);
+            if (S->active.empty() && S->pending.empty() && !S->stop)
+                S->cv.wait_for(lk, std::chrono::milliseconds(50));
+            if (S->stop && S->active.empty()) break;
+            for (Request* r : S->active) r->cancel_seen = r->cancel_seen || r->cancel;
+            // FIFO admission by arena memory and slots
+            while (!S->pending.empty() && !S->free_slots.empty() &&
+                   (int)S->active.size() < kMaxActive) {
+                Request* r = S->pending.front();
+                if (r->cancel) {
+                    S->pending.pop_front();
+                    r->state = kDone;
+                    r->status = ABM_ECANCELED;
+                    r->t_done = now_s();
+                    continue;
+                }
+                const ReqLayout lay = layout_of(r->prob, S->L, S->kchunk, S->max_split);
+                if (lay.total > S->arena_cap) {   // can never fit: fail it, keep the queue moving
+                    S->pending.pop_front();
+                    r->state = kDone;
+                    r->status = ABM_ENOMEM;
+                    r->t_done = now_s();
+                    continue;
+                }
+                size_t off = 0;
+                if (!arena_alloc(S, lay.total, &off)) break;   // head waits for memory
+                S->pending.pop_front();
+                if (admit(S, r, off, lay) != ABM_OK) {
+                    arena_free(S, off, lay.total);
+                    r->state = kDone;
+                    r->status = ABM_EDEVICE;
+                    r->t_done = now_s();
+                    continue;
+                }
+                r->state = kRunning;
+                r->t_start = now_s();
+                S->active.push_back(r);
+                fresh.push_back(r);
+            }
+        }
+        bool any_work = false;
+        for (Request* r : S->active)
+            if (!r->finishing) any_work = true;   // includes a cancel to retire
+        if (any_work && enqueue_tick(S, fresh) != ABM_OK) {
+            std::lock_guard<std::mutex> lk(S->mu);
+            S->error = abm_last_error();
+            for (Request* r : S->active) {
+                r->state = kDone;
+                r->status = ABM_EDEVICE;
+            }
+            S->active.clear();
+            S->stop = true;
+            break;
+        }
+        // completions
+        std::vector<Request*> keep;
+        for (Request* r : S->active) {
+            if (r->finishing && hipEventQuery(r->done_ev) == hipSuccess) {
+                const double t = now_s();
+                double mx = 0;
+                bool bad = false;
+                for (int i = 0; i < r->prob.d && !r->cancel_seen; ++i) {
+                    bad |= !std::isfinite(r->final_host[i]);
+                    mx = std::max(mx, std::fabs(r->final_host[i]));
+                }
+                release(S, r);
+                std::lock_guard<std::mutex> lk(S->mu);
+                r->max_abs_y = mx;
+                r->status = r->cancel_seen ? ABM_ECANCELED : (bad ? ABM_EDEVICE : ABM_OK);
+                r->state = kDone;
+                r->t_done = t;
+            } else {
+                keep.push_back(r);
+            }
+        }
+        S->active.swap(keep);
+        if (!any_work && !S->active.empty()) std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+    (void)hipStreamSynchronize(S->s0);
+    (void)hipStreamSynchronize(S->s1);
+}
+
+}  // namespace
+
+void serve_shutdown(abm_ctx* ctx)
+{
+    ServeState* S = ctx->serve;
+    if (!S) return;
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        S->stop = true;
+        for (Request* r : S->pending) {
+            r->cancel = true;
+        }
+    }
+    S->cv.notify_all();
+    if (S->th.joinable()) S->th.join();
+    for (auto& kv : S->all) {
+        if (kv.second->final_host) (void)hipHostFree(kv.second->final_host);
+        if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);
+        delete kv.second;
+    }
+    for (Request* r : S->pending)
+        if (S->all.find(r->ticket) == S->all.end()) delete r;
+    if (S->arena) (void)hipFree(S->arena);
+    dev_free(S->groups_dev);
+    dev_free(S->far_dev);
+    dev_free(S->chain_dev);
+    dev_free(S->init_dev);
+    dev_free(S->status);
+    if (S->groups_host) (void)hipHostFree(S->groups_host);
+    if (S->far_host) (void)hipHostFree(S->far_host);
+    if (S->chain_host) (void)hipHostFree(S->chain_host);
+    if (S->init_host) (void)hipHostFree(S->init_host);
+    for (auto ev : S->ring_ev)
+        if (ev) (void)hipEventDestroy(ev);
+    for (auto ev : S->ev_pool) (void)hipEventDestroy(ev);
+    if (S->s0) (void)hipStreamDestroy(S->s0);
+    if (S->s1) (void)hipStreamDestroy(S->s1);
+    delete S;
+    ctx->serve = nullptr;
+}
 
 }  // namespace abm
 
@@ -16,26 +595,74 @@ extern "C" {
 
 abm_status abm_submit(abm_ctx* ctx, const abm_problem* prob, double* y_out, uint64_t* ticket)
 {
-    (void)ctx;
-    (void)prob;
-    (void)y_out;
-    (void)ticket;
-    return fail(ABM_EINVAL, "serving loop not available in this build");
+    if (!ctx || !prob || !y_out || !ticket) return fail(ABM_EINVAL, "NULL argument");
+    abm_status s = validate(*prob, 0);
+    if (s) return s;
+    if (!ctx->serve) {
+        ctx->serve = new ServeState();
+        ctx->serve->ctx = ctx;
+    }
+    ServeState* S = ctx->serve;
+    const int L = env_int("ABM_SERVE_BLOCK_L", 256);
+    if (prob->far_prec != ABM_FAR_FP64 && L < 128)
+        return fail(ABM_EINVAL, "reduced-precision far field needs block length >= 128");
+    const ReqLayout lay = layout_of(*prob, L, 2048, 8);
+    if (lay.total > ctx->arena_bytes)
+        return fail(ABM_ENOMEM, "request needs %zu bytes, the arena has %zu", lay.total,
+                    ctx->arena_bytes);
+    Request* r = new Request();
+    r->prob = *prob;
+    r->y_out = y_out;
+    r->t_submit = now_s();
+    {
+        std::lock_guard<std::mutex> lk(S->mu);
+        if (S->stop) {
+            delete r;
+            return fail(ABM_EDEVICE, "server stopped: %s", S->error.c_str());
+        }
+        r->ticket = S->next_ticket++;
+        S->all[r->ticket] = r;
+        S->pending.push_back(r);
+        if (!S->started) {
+            S->started = true;
+            S->th = std::thread(server_loop, S);
+        }
+    }
+    S->cv.notify_all();
+    *ticket = r->ticket;
+    return ABM_OK;
 }
 
 abm_status abm_poll(abm_ctx* ctx, uint64_t ticket, abm_result* res)
 {
-    (void)ctx;
-    (void)ticket;
-    (void)res;
-    return fail(ABM_ENOENT, "serving loop not available in this build");
+    if (!ctx || !res) return fail(ABM_EINVAL, "NULL argument");
+    ServeState* S = ctx->serve;
+    if (!S) return fail(ABM_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(ABM_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    Request* r = it->second;
+    if (r->state != kDone) return ABM_EAGAIN;
+    res->status = r->status;
+    res->t_submit = r->t_submit;
+    res->t_start = r->t_start;
+    res->t_done = r->t_done;
+    res->max_abs_y = r->max_abs_y;
+    S->all.erase(it);
+    delete r;
+    return ABM_OK;
 }
 
 abm_status abm_cancel(abm_ctx* ctx, uint64_t ticket)
 {
-    (void)ctx;
-    (void)ticket;
-    return fail(ABM_ENOENT, "serving loop not available in this build");
+    if (!ctx) return fail(ABM_EINVAL, "NULL argument");
+    ServeState* S = ctx->serve;
+    if (!S) return fail(ABM_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    std::lock_guard<std::mutex> lk(S->mu);
+    auto it = S->all.find(ticket);
+    if (it == S->all.end()) return fail(ABM_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
+    it->second->cancel = true;
+    return ABM_OK;
 }
 
 }  // extern "C"

@@ -94,3 +94,16 @@ def test_sweep_full_size_fp64(ctx):
     assert np.all(np.isfinite(allv)) and np.max(np.abs(allv)) < 10
     alone, _ = run_batch(ctx, [probs[511]], 1024)
     assert np.array_equal(alone[0], outs[511])
+
+
+def test_batch_partial_slices_bounded_over_all_blocks(ctx):
+    """With N = 20000 and block length 256 a middle block needs more far
+    partial slices (6) than the last one (5); three groups (three alphas) sit
+    next to each other in memory, so an undersized partial buffer would spill
+    into a neighbour.  Every member must still match the oracle."""
+    probs = [inputs.Problem("DUFFING", al, 2 ** -8, 20000, (0.1, 0.0), (0.1, 0.3, 1.2))
+             for al in (0.9, 0.91, 0.92)]
+    outs, st = run_batch(ctx, probs, 100)
+    assert st["n_groups"] == 3
+    for p, y in zip(probs, outs):
+        assert normerr(y, oracle_run(p, 100)) <= TOL_FP64

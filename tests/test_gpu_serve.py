@@ -1,0 +1,131 @@
+"""Serving loop (abm_submit / abm_poll / abm_cancel) on the GPU: results against
+the oracle, the same result alone and in a mix of concurrent requests, FIFO
+admission by arena memory, and the error paths."""
+import time
+
+import numpy as np
+import pytest
+
+from paper_1710_01133_amd import abm, inputs
+from gpu_common import TOL_FP64, normerr, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch_ready():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.init()
+    return torch
+
+
+def _wait(ctx, tickets, timeout=120.0):
+    out = {}
+    t0 = time.time()
+    while len(out) < len(tickets):
+        for t in tickets:
+            if t in out:
+                continue
+            r = abm.poll(ctx, t)
+            if r is not None:
+                out[t] = r
+        assert time.time() - t0 < timeout, "requests did not finish"
+        time.sleep(0.002)
+    return out
+
+
+def _mix(prec="fp64", n=8, seed=3):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for i in range(n):
+        N = int(np.exp(rng.uniform(np.log(300), np.log(5000))))
+        al = float(rng.uniform(0.9, 0.99))
+        if i % 2 == 0:
+            probs.append(inputs.Problem("DUFFING", al, 2 ** -8, N, (0.1, 0.0),
+                                        (0.1, float(rng.uniform(0.1, 0.6)), 1.2), prec))
+        else:
+            probs.append(inputs.Problem("LORENZ", al, 2 ** -8, N, (1.0, 1.0, 1.0), inputs.LORENZ_P,
+                                        prec))
+    return probs
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("fp32", 1e-6)])
+def test_served_results_match_oracle(torch_ready, prec, tol):
+    ctx = abm.Context(0, arena_bytes=256 << 20)
+    probs = _mix(prec)
+    ys = [abm.alloc_out(p, 1) for p in probs]
+    tickets = [abm.submit(ctx, p, y, out_stride=1) for p, y in zip(probs, ys)]
+    res = _wait(ctx, tickets)
+    torch_ready.cuda.synchronize()
+    for p, y, t in zip(probs, ys, tickets):
+        assert res[t]["status"] == abm.ABM_OK
+        e = normerr(y.cpu().numpy(), oracle_run(p, 1))
+        assert e <= tol, (p.rhs, p.N, e)
+        assert res[t]["t_submit"] <= res[t]["t_start"] <= res[t]["t_done"]
+    ctx.close()
+
+
+def test_same_result_alone_and_in_mix(torch_ready):
+    probs = _mix("fp32", n=10, seed=11)
+    target = probs[4]
+    ctx = abm.Context(0, arena_bytes=512 << 20)
+    y_alone = abm.alloc_out(target, 1)
+    _wait(ctx, [abm.submit(ctx, target, y_alone, out_stride=1)])
+    ys = [abm.alloc_out(p, 1) for p in probs]
+    tickets = []
+    for p, y in zip(probs, ys):           # staggered arrivals
+        tickets.append(abm.submit(ctx, p, y, out_stride=1))
+        time.sleep(0.001)
+    _wait(ctx, tickets)
+    torch_ready.cuda.synchronize()
+    assert np.array_equal(y_alone.cpu().numpy(), ys[4].cpu().numpy())
+    ctx.close()
+
+
+def test_fifo_admission_under_small_arena(torch_ready):
+    # an arena that holds about two of these requests at a time
+    p0 = inputs.duffing_single(N=20000, h=2 ** -8)
+    probs = [inputs.Problem("DUFFING", 0.9 + 0.01 * i, 2 ** -8, 20000, (0.1, 0.0),
+                            (0.1, 0.3, 1.2)) for i in range(6)]
+    ctx = abm.Context(0, arena_bytes=24 << 20)
+    ys = [abm.alloc_out(p, 0) for p in probs]
+    tickets = [abm.submit(ctx, p, y, out_stride=0) for p, y in zip(probs, ys)]
+    res = _wait(ctx, tickets)
+    starts = [res[t]["t_start"] for t in tickets]
+    assert starts == sorted(starts)                     # admitted in arrival order
+    dones = sorted(res[t]["t_done"] for t in tickets)
+    assert max(starts) > min(dones)                     # later ones waited for memory
+    for p, y in zip(probs, ys):
+        assert normerr(y.cpu().numpy(), oracle_run(p, 0)) <= TOL_FP64
+    ctx.close()
+    del p0
+
+
+def test_error_paths(torch_ready):
+    ctx = abm.Context(0, arena_bytes=8 << 20)
+    big = inputs.duffing_single(N=200000)
+    y = abm.alloc_out(big, 0)
+    with pytest.raises(abm.AbmError) as e:
+        abm.submit(ctx, big, y)
+    assert e.value.code == abm.ABM_ENOMEM
+    bad = inputs.Problem("DUFFING", 0.0, 0.01, 10, (0.1, 0.0), (0.1, 0.3, 1.2))
+    with pytest.raises(abm.AbmError) as e:
+        abm.submit(ctx, bad, y)
+    assert e.value.code == abm.ABM_EINVAL
+    with pytest.raises(abm.AbmError) as e:
+        abm.poll(ctx, 987654)
+    assert e.value.code == abm.ABM_ENOENT
+    # cancel a request queued behind one that fills the arena
+    p = inputs.duffing_single(N=15000, h=2 ** -8)
+    y1, y2 = abm.alloc_out(p, 0), abm.alloc_out(p, 0)
+    t1 = abm.submit(ctx, p, y1)
+    t2 = abm.submit(ctx, p, y2)
+    abm.cancel(ctx, t2)
+    res = _wait(ctx, [t1, t2])
+    assert res[t1]["status"] == abm.ABM_OK
+    assert res[t2]["status"] == abm.ABM_ECANCELED
+    with pytest.raises(abm.AbmError) as e:
+        abm.poll(ctx, t1)                                # already collected
+    assert e.value.code == abm.ABM_ENOENT
+    ctx.close()
