@@ -152,6 +152,25 @@ def cpu_baseline(inputs, budget_s=20.0):
                       "trajectories), %.1f s wall" % (len(sample), dt)}
 
 
+def plain_leg(abm, torch, inputs, ctx):
+    """The plain per-step path (abm_solve) on the single 200000-step oscillator."""
+    p1 = inputs.duffing_single()
+    pp = abm.Plan(ctx, [p1], out_stride=0)
+    y1 = abm.alloc_out(p1, 0)
+    abm.solve(pp, p1, y1)
+    pp.check()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    abm.solve(pp, p1, y1)
+    torch.cuda.synchronize()
+    dt1 = time.perf_counter() - t1
+    pp.check()
+    pp.close()
+    return {"workload": "forced Duffing, alpha=0.9, h=1e-3, N=200000, d=2, one trajectory",
+            "seconds": dt1, "history_macs_per_s": p1.history_macs() / dt1,
+            "us_per_step": dt1 / p1.N * 1e6}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -161,6 +180,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--plain-only", action="store_true",
+                    help="only the plain per-step path on the 200000-step oscillator")
     ap.add_argument("--serve-requests", type=int, default=400,
                     help="requests of the serving stream (0 skips the serving leg)")
     ap.add_argument("--serve-arena-mib", type=int, default=1024)
@@ -179,6 +200,10 @@ def main():
         copy_calibration(torch)
         return
     ctx = abm.Context(0)
+    if args.plain_only:
+        print(json.dumps({"plain": plain_leg(abm, torch, inputs, ctx)}))
+        ctx.close()
+        return
 
     stride = 1024
     probs = inputs.duffing_sweep(far_prec=args.prec)
@@ -220,23 +245,7 @@ def main():
             "executed_frac": achieved * EXEC_FACTOR[args.prec] / peak,
             "chain_ms_total": stt["chain_ms"], "far_ms_total": stt["far_ms"]}
 
-    plain = None
-    if not args.no_plain:
-        p1 = inputs.duffing_single()
-        pp = abm.Plan(ctx, [p1], out_stride=0)
-        y1 = abm.alloc_out(p1, 0)
-        abm.solve(pp, p1, y1)
-        pp.check()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        abm.solve(pp, p1, y1)
-        torch.cuda.synchronize()
-        dt1 = time.perf_counter() - t1
-        pp.check()
-        plain = {"workload": "forced Duffing, alpha=0.9, h=1e-3, N=200000, d=2, one trajectory",
-                 "seconds": dt1, "history_macs_per_s": p1.history_macs() / dt1,
-                 "us_per_step": dt1 / p1.N * 1e6}
-        pp.close()
+    plain = None if args.no_plain else plain_leg(abm, torch, inputs, ctx)
 
     serve = None
     if args.serve_requests > 0:
