@@ -132,6 +132,22 @@ def time_batch(abm, torch, plan, probs, ys, steps, warmup):
     return dt, st
 
 
+def small_batch_leg(abm, torch, inputs, ctx, steps=20):
+    """A launch-bound batch (64 forced Duffing trajectories, N=8192, fp64 far
+    field): the same solve launched eagerly and replayed from its graph."""
+    probs = inputs.duffing_sweep(B=64, N=8192, far_prec="fp64")
+    plan = abm.Plan(ctx, probs, out_stride=0)
+    ys = [abm.alloc_out(p, 0) for p in probs]
+    res = {"workload": "B=64 forced Duffing, alpha=0.95, h=2^-8, N=8192, d=2, far field fp64"}
+    for mode in ("eager", "graph"):
+        plan.graph(mode == "graph")
+        dt, st = time_batch(abm, torch, plan, probs, ys, steps, 2)
+        res[mode + "_ms"] = dt * 1e3
+        res["launches"] = st["far_launches"] + st["chain_launches"]
+    plan.close()
+    return res
+
+
 def cpu_baseline(inputs, budget_s=20.0):
     """The oracle as it stands on the host cores: a bounded sample of the
     sweep (whole trajectories at full N, OpenMP over trajectories)."""
@@ -186,6 +202,8 @@ def main():
                     help="requests of the serving stream (0 skips the serving leg)")
     ap.add_argument("--serve-arena-mib", type=int, default=1024)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--eager", action="store_true",
+                    help="launch the batched solve eagerly instead of replaying its captured graph")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU only: the batched sweep is sized for one MI355X and no "
@@ -212,9 +230,15 @@ def main():
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     ys = [abm.alloc_out(p, stride) for p in probs]
+    plan.graph(not args.eager)
     dt, st = time_batch(abm, torch, plan, probs, ys, args.steps, args.warmup)
     macs = st["history_macs"]
     value = macs / dt
+    eager_dt = None
+    if not args.eager:                      # the same solve launched eagerly, for comparison
+        plan.graph(False)
+        eager_dt, _ = time_batch(abm, torch, plan, probs, ys, args.steps, 1)
+        plan.graph(True)
 
     # error against the stored double-precision oracle runs of four members
     gold_path = os.path.join(ROOT, "tests", "golden", "oracle_fullsize.json")
@@ -246,6 +270,7 @@ def main():
             "chain_ms_total": stt["chain_ms"], "far_ms_total": stt["far_ms"]}
 
     plain = None if args.no_plain else plain_leg(abm, torch, inputs, ctx)
+    small = small_batch_leg(abm, torch, inputs, ctx)
 
     serve = None
     if args.serve_requests > 0:
@@ -270,7 +295,9 @@ def main():
         "config": {"workload": "forcing sweep: B=1024 forced Duffing, alpha=0.95, h=2^-8, "
                                "N=65536, d=2, far field %s" % args.prec,
                    "B": 1024, "N": 65536, "d": 2, "block_L": st["block_L"],
-                   "far_prec": args.prec},
+                   "far_prec": args.prec, "launch": "eager" if args.eager else "graph"},
+        "eager_ms_per_step": None if eager_dt is None else eager_dt * 1e3,
+        "launch_bound_batch": small,
         "max_rel_err_vs_oracle": max_err,
         "err_members": errs,
         "plan_seconds": plan_s,

@@ -152,6 +152,17 @@ abm_status abm_plan_check(abm_plan_t *plan);
  * ABM_EDEVICE. */
 abm_status abm_plan_timing(abm_plan_t *plan, int32_t enable);
 
+/* Replay the launch sequence of abm_solve_batch from a HIP graph.  When
+ * enable != 0, the next abm_solve_batch records its far-field, chain and
+ * initialisation launches (with the fork/join between the far-field stream
+ * and the context's stream) into a graph once, from a private stream, and
+ * every later call only uploads that solve's descriptors (x0, p, h, output
+ * pointers) and launches the graph on the context's stream.  Results are
+ * bitwise those of the eager sequence.  Timed solves (abm_plan_timing) run
+ * eagerly.  Off by default.  Errors: ABM_EINVAL (plan NULL); a failed capture
+ * is reported by abm_solve_batch as ABM_EDEVICE. */
+abm_status abm_plan_graph(abm_plan_t *plan, int32_t enable);
+
 /* Copy the first n entries of the weight tables b_k, a_k, c_k (Section 2,
  * generated on the device by abm_plan) used by problem idx of the plan into
  * host arrays of n doubles each (any of them may be NULL).  Synchronises the

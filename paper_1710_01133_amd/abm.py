@@ -21,7 +21,7 @@ RHS_ID = {"LINEAR": 0, "DUFFING": 1, "LORENZ": 2, "POLY": 3, "LCR": 4}
 PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 
 EXPORTED = ("abm_ctx_create", "abm_ctx_destroy", "abm_plan", "abm_plan_destroy", "abm_plan_check",
-            "abm_plan_weights", "abm_plan_timing", "abm_solve", "abm_solve_batch", "abm_submit", "abm_poll", "abm_cancel",
+            "abm_plan_weights", "abm_plan_timing", "abm_plan_graph", "abm_solve", "abm_solve_batch", "abm_submit", "abm_poll", "abm_cancel",
             "abm_strerror", "abm_last_error")
 
 
@@ -73,6 +73,7 @@ def load(path: str = LIB_PATH):
     dp = ctypes.POINTER(ctypes.c_double)
     lib.abm_plan_weights.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, dp, dp, dp]
     lib.abm_plan_timing.argtypes = [vp, ctypes.c_int32]
+    lib.abm_plan_graph.argtypes = [vp, ctypes.c_int32]
     lib.abm_solve.argtypes = [vp, ctypes.POINTER(AbmProblem), vp]
     lib.abm_solve_batch.argtypes = [vp, ctypes.POINTER(AbmProblem), ctypes.c_int32,
                                     ctypes.POINTER(vp), ctypes.POINTER(AbmStats)]
@@ -80,7 +81,7 @@ def load(path: str = LIB_PATH):
     lib.abm_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(AbmResult)]
     lib.abm_cancel.argtypes = [vp, ctypes.c_uint64]
     for name in ("abm_ctx_create", "abm_plan", "abm_plan_check", "abm_plan_weights",
-                 "abm_plan_timing", "abm_solve", "abm_solve_batch", "abm_submit", "abm_poll",
+                 "abm_plan_timing", "abm_plan_graph", "abm_solve", "abm_solve_batch", "abm_submit", "abm_poll",
                  "abm_cancel"):
         getattr(lib, name).restype = ctypes.c_int32
     lib.abm_strerror.argtypes = [ctypes.c_int32]
@@ -172,6 +173,10 @@ class Plan:
     def timing(self, enable: bool):
         """Per-launch device timing of solve_batch (far_ms / chain_ms in its stats)."""
         _check(load().abm_plan_timing(self._h, 1 if enable else 0), "abm_plan_timing")
+
+    def graph(self, enable: bool):
+        """Replay solve_batch's launch sequence from a HIP graph captured once."""
+        _check(load().abm_plan_graph(self._h, 1 if enable else 0), "abm_plan_graph")
 
     def weights(self, idx: int, n: int):
         """First n weights b, a, c of problem idx's table, as numpy arrays."""

@@ -113,6 +113,13 @@ struct abm_plan_s {
     // optional per-launch timing
     bool timing = false;
     std::vector<hipEvent_t> events;
+    // launch sequence replayed from a graph captured at the first graph solve
+    bool use_graph = false;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t graph_exec = nullptr;
+    int64_t graph_far_launches = 0;
+    int64_t graph_chain_launches = 0;
 };
 
 namespace abm {

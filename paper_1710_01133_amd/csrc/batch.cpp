@@ -56,6 +56,12 @@ void free_group(Group& g)
 
 void batch_teardown(abm_plan_s* pl)
 {
+    if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+    if (pl->graph) (void)hipGraphDestroy(pl->graph);
+    pl->graph_exec = nullptr;
+    pl->graph = nullptr;
+    if (pl->cap_stream) (void)hipStreamDestroy(pl->cap_stream);
+    pl->cap_stream = nullptr;
     for (hipEvent_t ev : pl->events) (void)hipEventDestroy(ev);
     pl->events.clear();
     for (auto& g : pl->groups) free_group(g);
@@ -359,6 +365,155 @@ abm_status batch_setup(abm_plan_s* pl)
     return ABM_OK;
 }
 
+namespace {
+
+// Enqueues the launch sequence of one blocked solve after its descriptor
+// upload: the chain initialisation, then per tick the far field of the next
+// block on the far stream and the chains of this block on the given stream,
+// ordered by events so that far(t+1) overlaps chain(t).  Runs eagerly
+// (optionally bracketing every launch with timing events) or under capture.
+struct TickEnqueuer {
+    abm_plan_s* pl;
+    bool timing;
+    std::vector<std::pair<int, int>> tev;   // (0 far | 1 chain, index of the start event)
+    size_t ev_used = 0, sync_used = 0;
+    int64_t far_launches = 0, chain_launches = 0;
+
+    TickEnqueuer(abm_plan_s* p, bool t) : pl(p), timing(t) {}
+
+    hipEvent_t timing_event()
+    {
+        if (ev_used == pl->events.size()) {
+            hipEvent_t ev;
+            if (hipEventCreate(&ev) != hipSuccess) return nullptr;
+            pl->events.push_back(ev);
+        }
+        return pl->events[ev_used++];
+    }
+    // ordering events (no timing), reused across calls
+    hipEvent_t sync_event()
+    {
+        if (sync_used == pl->sync_events.size()) {
+            hipEvent_t ev;
+            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return nullptr;
+            pl->sync_events.push_back(ev);
+        }
+        return pl->sync_events[sync_used++];
+    }
+    template <class Launch>
+    hipError_t timed(int kind, hipStream_t sx, Launch&& launch)
+    {
+        if (!timing) return launch();
+        hipEvent_t a = timing_event(), b = timing_event();
+        if (!a || !b) return hipErrorOutOfMemory;
+        const int ia = (int)ev_used - 2;
+        hipError_t e = hipEventRecord(a, sx);
+        if (e != hipSuccess) return e;
+        if ((e = launch()) != hipSuccess) return e;
+        e = hipEventRecord(b, sx);
+        tev.push_back({kind, ia});
+        return e;
+    }
+
+    abm_status run(hipStream_t st)
+    {
+        hipError_t e;
+        const int L = pl->L;
+        for (int rhs = 0; rhs < 5; ++rhs) {
+            const Span& sp = pl->init_spans[rhs];
+            if (!sp.count) continue;
+            e = launch_chain_init(pl->groups_dev, pl->init_items_dev + sp.offset, sp.count, rhs, st);
+            if (e != hipSuccess) return hip_fail(e, "chain init launch");
+        }
+        hipStream_t s1 = pl->overlap ? pl->far_stream : st;
+        hipEvent_t fork = sync_event();
+        if (!fork) return fail(ABM_EDEVICE, "event pool");
+        if ((e = hipEventRecord(fork, st)) != hipSuccess || (e = hipStreamWaitEvent(s1, fork, 0)) != hipSuccess)
+            return hip_fail(e, "stream fork");
+        hipEvent_t ev_chain_prev = nullptr, ev_far_prev = nullptr;
+        for (int64_t t = 0; t < pl->ticks; ++t) {
+            bool any_far = false;
+            for (int prec = 0; prec < 4; ++prec)
+                if (pl->far_spans[t * 4 + prec].count) any_far = true;
+            hipEvent_t ev_far = nullptr;
+            if (any_far) {
+                if (ev_chain_prev && (e = hipStreamWaitEvent(s1, ev_chain_prev, 0)) != hipSuccess)
+                    return hip_fail(e, "stream wait");
+                for (int prec = 0; prec < 4; ++prec) {
+                    const Span& sp = pl->far_spans[t * 4 + prec];
+                    if (!sp.count) continue;
+                    e = timed(0, s1, [&]() {
+                        return launch_far(pl->groups_dev, pl->far_items_dev + sp.offset, sp.count,
+                                          sp.max_x, sp.max_y, pl->kchunk, L, prec, s1);
+                    });
+                    if (e != hipSuccess) return hip_fail(e, "far-field launch");
+                    ++far_launches;
+                }
+                ev_far = sync_event();
+                if (!ev_far || (e = hipEventRecord(ev_far, s1)) != hipSuccess)
+                    return fail(ABM_EDEVICE, "far event");
+            }
+            if (ev_far_prev && (e = hipStreamWaitEvent(st, ev_far_prev, 0)) != hipSuccess)
+                return hip_fail(e, "stream wait");
+            for (int rhs = 0; rhs < 5; ++rhs) {
+                const Span& sp = pl->chain_spans[t * 5 + rhs];
+                if (!sp.count) continue;
+                e = timed(1, st, [&]() {
+                    return launch_chain(pl->groups_dev, pl->chain_items_dev + sp.offset, sp.count,
+                                        rhs, L, pl->status, st);
+                });
+                if (e != hipSuccess) return hip_fail(e, "chain launch");
+                ++chain_launches;
+            }
+            ev_chain_prev = sync_event();
+            if (!ev_chain_prev || (e = hipEventRecord(ev_chain_prev, st)) != hipSuccess)
+                return fail(ABM_EDEVICE, "chain event");
+            ev_far_prev = ev_far;
+        }
+        hipEvent_t join = sync_event();
+        if (!join || (e = hipEventRecord(join, s1)) != hipSuccess ||
+            (e = hipStreamWaitEvent(st, join, 0)) != hipSuccess)
+            return fail(ABM_EDEVICE, "stream join");
+        return ABM_OK;
+    }
+};
+
+// Records the launch sequence once into a graph, from a private origin stream
+// so that nothing of the caller's stream is captured.  Every pointer the
+// kernels use is fixed by the plan (per-solve data reaches them through the
+// descriptors uploaded before each launch), so the graph stays valid for the
+// plan's lifetime.
+abm_status capture_ticks(abm_plan_s* pl)
+{
+    hipError_t e;
+    if (!pl->cap_stream &&
+        (e = hipStreamCreateWithFlags(&pl->cap_stream, hipStreamNonBlocking)) != hipSuccess)
+        return hip_fail(e, "capture stream");
+    if ((e = hipStreamBeginCapture(pl->cap_stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+        return hip_fail(e, "begin capture");
+    TickEnqueuer q(pl, false);
+    const abm_status s = q.run(pl->cap_stream);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(pl->cap_stream, &g);
+    if (s) {
+        if (g) (void)hipGraphDestroy(g);
+        return s;
+    }
+    if (e != hipSuccess) return hip_fail(e, "end capture");
+    e = hipGraphInstantiateWithFlags(&pl->graph_exec, g, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        pl->graph_exec = nullptr;
+        return hip_fail(e, "graph instantiate");
+    }
+    pl->graph = g;
+    pl->graph_far_launches = q.far_launches;
+    pl->graph_chain_launches = q.chain_launches;
+    return ABM_OK;
+}
+
+}  // namespace
+
 }  // namespace abm
 
 using namespace abm;
@@ -381,43 +536,8 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
     hipError_t e = hipSetDevice(pl->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t st = pl->ctx->stream;
-    const int L = pl->L;
     abm_stats S{};
-    // event pairs around launches when timing is on: (kind, index of the start event)
-    std::vector<std::pair<int, int>> tev;
-    size_t ev_used = 0;
-    auto ev_next = [&]() -> hipEvent_t {
-        if (ev_used == pl->events.size()) {
-            hipEvent_t ev;
-            if (hipEventCreate(&ev) != hipSuccess) return nullptr;
-            pl->events.push_back(ev);
-        }
-        return pl->events[ev_used++];
-    };
-    auto timed = [&](int kind, hipStream_t sx, auto&& launch) -> hipError_t {
-        if (!pl->timing) return launch();
-        hipEvent_t a = ev_next(), b = ev_next();
-        if (!a || !b) return hipErrorOutOfMemory;
-        const int ia = (int)ev_used - 2;
-        hipError_t e1 = hipEventRecord(a, sx);
-        if (e1 != hipSuccess) return e1;
-        e1 = launch();
-        if (e1 != hipSuccess) return e1;
-        e1 = hipEventRecord(b, sx);
-        tev.push_back({kind, ia});
-        return e1;
-    };
-    // ordering events (no timing), reused across calls
-    size_t sync_used = 0;
-    auto sync_event = [&]() -> hipEvent_t {
-        if (sync_used == pl->sync_events.size()) {
-            hipEvent_t ev;
-            if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) return nullptr;
-            pl->sync_events.push_back(ev);
-        }
-        return pl->sync_events[sync_used++];
-    };
-    S.block_L = L;
+    S.block_L = pl->L;
     S.n_groups = (int32_t)pl->groups.size();
     S.far_macs = pl->far_macs;
 
@@ -448,72 +568,28 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
         if (e != hipSuccess) return hip_fail(e, "descriptor event");
         g.traj_ev_live = true;
     }
-    for (int rhs = 0; rhs < 5; ++rhs) {
-        const Span& sp = pl->init_spans[rhs];
-        if (!sp.count) continue;
-        e = launch_chain_init(pl->groups_dev, pl->init_items_dev + sp.offset, sp.count, rhs, st);
-        if (e != hipSuccess) return hip_fail(e, "chain init launch");
-    }
 
-    // far field on s1, chain on s0; far(t+1) overlaps chain(t)
-    hipStream_t s1 = pl->overlap ? pl->far_stream : st;
-    hipEvent_t fork = sync_event();
-    if (!fork) return fail(ABM_EDEVICE, "event pool");
-    if ((e = hipEventRecord(fork, st)) != hipSuccess || (e = hipStreamWaitEvent(s1, fork, 0)) != hipSuccess)
-        return hip_fail(e, "stream fork");
-    hipEvent_t ev_chain_prev = nullptr, ev_far_prev = nullptr;
-    for (int64_t t = 0; t < pl->ticks; ++t) {
-        bool any_far = false;
-        for (int prec = 0; prec < 4; ++prec)
-            if (pl->far_spans[t * 4 + prec].count) any_far = true;
-        hipEvent_t ev_far = nullptr;
-        if (any_far) {
-            if (ev_chain_prev && (e = hipStreamWaitEvent(s1, ev_chain_prev, 0)) != hipSuccess)
-                return hip_fail(e, "stream wait");
-            for (int prec = 0; prec < 4; ++prec) {
-                const Span& sp = pl->far_spans[t * 4 + prec];
-                if (!sp.count) continue;
-                e = timed(0, s1, [&]() {
-                    return launch_far(pl->groups_dev, pl->far_items_dev + sp.offset, sp.count,
-                                      sp.max_x, sp.max_y, pl->kchunk, L, prec, s1);
-                });
-                if (e != hipSuccess) return hip_fail(e, "far-field launch");
-                ++S.far_launches;
+    abm_status s;
+    if (pl->use_graph && !pl->timing) {
+        if (!pl->graph_exec && (s = capture_ticks(pl))) return s;
+        e = hipGraphLaunch(pl->graph_exec, st);
+        if (e != hipSuccess) return hip_fail(e, "graph launch");
+        S.far_launches = pl->graph_far_launches;
+        S.chain_launches = pl->graph_chain_launches;
+    } else {
+        TickEnqueuer q(pl, pl->timing);
+        if ((s = q.run(st))) return s;
+        S.far_launches = q.far_launches;
+        S.chain_launches = q.chain_launches;
+        if (pl->timing && !q.tev.empty()) {
+            e = hipStreamSynchronize(st);
+            if (e != hipSuccess) return hip_fail(e, "timing sync");
+            for (auto& te : q.tev) {
+                float ms = 0.f;
+                e = hipEventElapsedTime(&ms, pl->events[te.second], pl->events[te.second + 1]);
+                if (e != hipSuccess) return hip_fail(e, "event time");
+                (te.first == 0 ? S.far_ms : S.chain_ms) += ms;
             }
-            ev_far = sync_event();
-            if (!ev_far || (e = hipEventRecord(ev_far, s1)) != hipSuccess)
-                return fail(ABM_EDEVICE, "far event");
-        }
-        if (ev_far_prev && (e = hipStreamWaitEvent(st, ev_far_prev, 0)) != hipSuccess)
-            return hip_fail(e, "stream wait");
-        for (int rhs = 0; rhs < 5; ++rhs) {
-            const Span& sp = pl->chain_spans[t * 5 + rhs];
-            if (!sp.count) continue;
-            e = timed(1, st, [&]() {
-                return launch_chain(pl->groups_dev, pl->chain_items_dev + sp.offset, sp.count, rhs,
-                                    L, pl->status, st);
-            });
-            if (e != hipSuccess) return hip_fail(e, "chain launch");
-            ++S.chain_launches;
-        }
-        ev_chain_prev = sync_event();
-        if (!ev_chain_prev || (e = hipEventRecord(ev_chain_prev, st)) != hipSuccess)
-            return fail(ABM_EDEVICE, "chain event");
-        ev_far_prev = ev_far;
-    }
-    hipEvent_t join = sync_event();
-    if (!join || (e = hipEventRecord(join, s1)) != hipSuccess ||
-        (e = hipStreamWaitEvent(st, join, 0)) != hipSuccess)
-        return fail(ABM_EDEVICE, "stream join");
-
-    if (pl->timing && !tev.empty()) {
-        e = hipStreamSynchronize(st);
-        if (e != hipSuccess) return hip_fail(e, "timing sync");
-        for (auto& te : tev) {
-            float ms = 0.f;
-            e = hipEventElapsedTime(&ms, pl->events[te.second], pl->events[te.second + 1]);
-            if (e != hipSuccess) return hip_fail(e, "event time");
-            (te.first == 0 ? S.far_ms : S.chain_ms) += ms;
         }
     }
     if (stats) *stats = S;
@@ -524,5 +600,12 @@ extern "C" abm_status abm_plan_timing(abm_plan_t* pl, int32_t enable)
 {
     if (!pl) return fail(ABM_EINVAL, "plan is NULL");
     pl->timing = enable != 0;
+    return ABM_OK;
+}
+
+extern "C" abm_status abm_plan_graph(abm_plan_t* pl, int32_t enable)
+{
+    if (!pl) return fail(ABM_EINVAL, "plan is NULL");
+    pl->use_graph = enable != 0;
     return ABM_OK;
 }
