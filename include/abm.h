@@ -89,6 +89,9 @@ typedef struct abm_stats {
     int32_t chain_launches;
     double far_ms;        /* summed device time of the far-field launches (timing on, else 0) */
     double chain_ms;      /* summed device time of the chain launches (timing on, else 0) */
+    int32_t narrow_groups; /* groups of at most a few columns whose far field runs as a
+                              blocked convolution instead of column tiles */
+    int32_t reserved_;
 } abm_stats;
 
 typedef struct abm_result {
@@ -98,6 +101,25 @@ typedef struct abm_result {
     double t_done;        /* when its completion was observed */
     double max_abs_y;     /* max |y_s| over the written states */
 } abm_result;
+
+/* Blocking of the batched method.  A zero field takes the default (or the
+ * ABM_BLOCK_L / ABM_KCHUNK / ABM_MAX_SPLIT / ABM_NARROW environment override). */
+typedef struct abm_tuning {
+    int32_t block_L;            /* near-band block length: 64 (double far field only), 128, 256, 512 */
+    int32_t kchunk;             /* history rows per far-field chunk: a multiple of 512 (lowered
+                                   until the chunk's weight window fits the LDS) */
+    int32_t max_split;          /* most far-field workgroups along the history per column tile */
+    int32_t column_tiles_only;  /* 1: no blocked convolution for narrow groups */
+} abm_tuning;
+
+/* One configuration tried by abm_autotune and the device time of one solve
+ * with it (status != ABM_OK if the plan or the solve failed). */
+typedef struct abm_tune_trial {
+    abm_tuning cfg;
+    abm_status status;
+    int32_t reserved_;
+    double ms;
+} abm_tune_trial;
 
 typedef struct abm_ctx abm_ctx;
 typedef struct abm_plan_s abm_plan_t;
@@ -118,6 +140,31 @@ void abm_ctx_destroy(abm_ctx *ctx);
  * ABM_ENOMEM, ABM_EDEVICE. */
 abm_status abm_plan(abm_ctx *ctx, const abm_problem *probs, int32_t B, abm_plan_t **out);
 void abm_plan_destroy(abm_plan_t *plan);
+
+/* abm_plan with an explicit blocking (tune may be NULL: defaults).  The
+ * blocked method's results depend on the blocking only through rounding.
+ * Errors: as abm_plan; ABM_EINVAL for a block length or chunk out of range. */
+abm_status abm_plan_tuned(abm_ctx *ctx, const abm_problem *probs, int32_t B,
+                          const abm_tuning *tune, abm_plan_t **out);
+
+/* The blocking a plan uses (after defaults, overrides and the LDS limit). */
+abm_status abm_plan_config(abm_plan_t *plan, abm_tuning *out);
+
+/* Choose the blocking for these problems by timing whole abm_solve_batch
+ * runs on the device (the batched method's launch sequence, block lengths,
+ * chunk sizes and split counts interact through the overlap of far field and
+ * chain, so candidates are measured, not modelled): every block length
+ * first, then the split count and the chunk at the best one, then column
+ * tiles instead of the blocked convolution if the problems have narrow
+ * groups.  Stops starting new trials once budget_s seconds have passed (the
+ * block-length stage always runs at least one).  Device memory for one plan
+ * at a time plus scratch outputs.  best receives the fastest configuration;
+ * trials (may be NULL) receives up to max_trials of the trials made, in
+ * order, and n_trials their count.  Synchronises the context's stream.
+ * Errors: ABM_EINVAL, ABM_EDEVICE (no configuration could be run). */
+abm_status abm_autotune(abm_ctx *ctx, const abm_problem *probs, int32_t B, double budget_s,
+                        abm_tuning *best, abm_tune_trial *trials, int32_t max_trials,
+                        int32_t *n_trials);
 
 /* One trajectory (problem 0 of a plan made with B = 1) by the plain per-step
  * method: every step's two history sums are split over workgroups that each
@@ -177,6 +224,13 @@ abm_status abm_plan_weights(abm_plan_t *plan, int32_t idx, int64_t n, double *b,
  * done.  Thread-safe.  Errors: ABM_EINVAL, ABM_ENOMEM (larger than the whole
  * arena). */
 abm_status abm_submit(abm_ctx *ctx, const abm_problem *prob, double *y_out, uint64_t *ticket);
+
+/* Device memory the serving loop takes from the context's arena for one
+ * request (its weight tables, history, carried sums and far-field partials),
+ * for sizing arenas: a request is admitted once this many bytes are free in
+ * one piece, and rejected by abm_submit with ABM_ENOMEM if it exceeds the
+ * whole arena.  Errors: ABM_EINVAL. */
+abm_status abm_request_bytes(abm_ctx *ctx, const abm_problem *prob, size_t *bytes);
 
 /* ABM_EAGAIN while the request runs; ABM_OK once done (res filled, ticket
  * released); ABM_ENOENT for an unknown or already-collected ticket.  A

@@ -22,6 +22,7 @@ PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 
 EXPORTED = ("abm_ctx_create", "abm_ctx_destroy", "abm_plan", "abm_plan_destroy", "abm_plan_check",
             "abm_plan_weights", "abm_plan_timing", "abm_plan_graph", "abm_solve", "abm_solve_batch", "abm_submit", "abm_poll", "abm_cancel",
+            "abm_request_bytes", "abm_plan_tuned", "abm_plan_config", "abm_autotune",
             "abm_strerror", "abm_last_error")
 
 
@@ -36,13 +37,28 @@ class AbmStats(ctypes.Structure):
     _fields_ = [("block_L", ctypes.c_int32), ("n_groups", ctypes.c_int32),
                 ("history_macs", ctypes.c_int64), ("far_macs", ctypes.c_int64),
                 ("far_launches", ctypes.c_int32), ("chain_launches", ctypes.c_int32),
-                ("far_ms", ctypes.c_double), ("chain_ms", ctypes.c_double)]
+                ("far_ms", ctypes.c_double), ("chain_ms", ctypes.c_double),
+                ("narrow_groups", ctypes.c_int32), ("reserved_", ctypes.c_int32)]
 
 
 class AbmResult(ctypes.Structure):
     _fields_ = [("status", ctypes.c_int32), ("t_submit", ctypes.c_double),
                 ("t_start", ctypes.c_double), ("t_done", ctypes.c_double),
                 ("max_abs_y", ctypes.c_double)]
+
+
+class AbmTuning(ctypes.Structure):
+    _fields_ = [("block_L", ctypes.c_int32), ("kchunk", ctypes.c_int32),
+                ("max_split", ctypes.c_int32), ("column_tiles_only", ctypes.c_int32)]
+
+
+class AbmTuneTrial(ctypes.Structure):
+    _fields_ = [("cfg", AbmTuning), ("status", ctypes.c_int32), ("reserved_", ctypes.c_int32),
+                ("ms", ctypes.c_double)]
+
+
+def _tuning_dict(t: AbmTuning) -> dict:
+    return {f: getattr(t, f) for f, _ in AbmTuning._fields_}
 
 
 class AbmError(RuntimeError):
@@ -73,6 +89,12 @@ def load(path: str = LIB_PATH):
     dp = ctypes.POINTER(ctypes.c_double)
     lib.abm_plan_weights.argtypes = [vp, ctypes.c_int32, ctypes.c_int64, dp, dp, dp]
     lib.abm_plan_timing.argtypes = [vp, ctypes.c_int32]
+    lib.abm_plan_tuned.argtypes = [vp, ctypes.POINTER(AbmProblem), ctypes.c_int32,
+                                   ctypes.POINTER(AbmTuning), ctypes.POINTER(vp)]
+    lib.abm_plan_config.argtypes = [vp, ctypes.POINTER(AbmTuning)]
+    lib.abm_autotune.argtypes = [vp, ctypes.POINTER(AbmProblem), ctypes.c_int32, ctypes.c_double,
+                                 ctypes.POINTER(AbmTuning), ctypes.POINTER(AbmTuneTrial),
+                                 ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
     lib.abm_plan_graph.argtypes = [vp, ctypes.c_int32]
     lib.abm_solve.argtypes = [vp, ctypes.POINTER(AbmProblem), vp]
     lib.abm_solve_batch.argtypes = [vp, ctypes.POINTER(AbmProblem), ctypes.c_int32,
@@ -80,9 +102,11 @@ def load(path: str = LIB_PATH):
     lib.abm_submit.argtypes = [vp, ctypes.POINTER(AbmProblem), vp, ctypes.POINTER(ctypes.c_uint64)]
     lib.abm_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(AbmResult)]
     lib.abm_cancel.argtypes = [vp, ctypes.c_uint64]
+    lib.abm_request_bytes.argtypes = [vp, ctypes.POINTER(AbmProblem), ctypes.POINTER(ctypes.c_size_t)]
     for name in ("abm_ctx_create", "abm_plan", "abm_plan_check", "abm_plan_weights",
                  "abm_plan_timing", "abm_plan_graph", "abm_solve", "abm_solve_batch", "abm_submit", "abm_poll",
-                 "abm_cancel"):
+                 "abm_cancel", "abm_request_bytes", "abm_plan_tuned", "abm_plan_config",
+                 "abm_autotune"):
         getattr(lib, name).restype = ctypes.c_int32
     lib.abm_strerror.argtypes = [ctypes.c_int32]
     lib.abm_strerror.restype = ctypes.c_char_p
@@ -154,14 +178,26 @@ class Context:
 class Plan:
     """abm_plan over a list of problems (their rhs, alpha, N, precision, stride fixed)."""
 
-    def __init__(self, ctx: Context, problems: Sequence[Problem], out_stride: int = 0):
+    def __init__(self, ctx: Context, problems: Sequence[Problem], out_stride: int = 0,
+                 tuning: dict = None):
         lib = load()
         self.ctx = ctx
         self.out_stride = out_stride
         self.problems = list(problems)
         arr = (AbmProblem * len(self.problems))(*[c_problem(p, out_stride) for p in self.problems])
         self._h = ctypes.c_void_p()
-        _check(lib.abm_plan(ctx.handle, arr, len(self.problems), ctypes.byref(self._h)), "abm_plan")
+        if tuning is None:
+            _check(lib.abm_plan(ctx.handle, arr, len(self.problems), ctypes.byref(self._h)), "abm_plan")
+        else:
+            t = AbmTuning(**tuning)
+            _check(lib.abm_plan_tuned(ctx.handle, arr, len(self.problems), ctypes.byref(t),
+                                      ctypes.byref(self._h)), "abm_plan_tuned")
+
+    def config(self) -> dict:
+        """The blocking the plan uses (block_L, kchunk, max_split, column_tiles_only)."""
+        t = AbmTuning()
+        _check(load().abm_plan_config(self._h, ctypes.byref(t)), "abm_plan_config")
+        return _tuning_dict(t)
 
     @property
     def handle(self):
@@ -240,6 +276,28 @@ def poll(ctx: Context, ticket: int):
         return None
     _check(rc, "abm_poll")
     return {f: getattr(r, f) for f, _ in AbmResult._fields_}
+
+
+def autotune(ctx: Context, problems: Sequence[Problem], out_stride: int = 0,
+             budget_s: float = 10.0, max_trials: int = 32):
+    """abm_autotune: (best blocking, list of trials as dicts with cfg/status/ms)."""
+    arr = (AbmProblem * len(problems))(*[c_problem(p, out_stride) for p in problems])
+    best = AbmTuning()
+    trials = (AbmTuneTrial * max_trials)()
+    n = ctypes.c_int32()
+    _check(load().abm_autotune(ctx.handle, arr, len(problems), budget_s, ctypes.byref(best),
+                               trials, max_trials, ctypes.byref(n)), "abm_autotune")
+    out = [{"cfg": _tuning_dict(t.cfg), "status": t.status, "ms": t.ms}
+           for t in trials[:min(n.value, max_trials)]]
+    return _tuning_dict(best), out
+
+
+def request_bytes(ctx: Context, problem: Problem, out_stride: int = 0) -> int:
+    """Arena bytes the serving loop takes for this request."""
+    c = c_problem(problem, out_stride)
+    n = ctypes.c_size_t()
+    _check(load().abm_request_bytes(ctx.handle, ctypes.byref(c), ctypes.byref(n)), "abm_request_bytes")
+    return int(n.value)
 
 
 def cancel(ctx: Context, ticket: int) -> None:

@@ -177,6 +177,12 @@ void abm_ctx_destroy(abm_ctx* ctx)
 
 abm_status abm_plan(abm_ctx* ctx, const abm_problem* probs, int32_t B, abm_plan_t** out)
 {
+    return abm_plan_tuned(ctx, probs, B, nullptr, out);
+}
+
+abm_status abm_plan_tuned(abm_ctx* ctx, const abm_problem* probs, int32_t B,
+                          const abm_tuning* tune, abm_plan_t** out)
+{
     if (!ctx || !probs || !out) return fail(ABM_EINVAL, "NULL argument");
     *out = nullptr;
     if (B < 1) return fail(ABM_EINVAL, "B=%d must be >= 1", B);
@@ -190,6 +196,7 @@ abm_status abm_plan(abm_ctx* ctx, const abm_problem* probs, int32_t B, abm_plan_
     pl->ctx = ctx;
     pl->B = B;
     pl->shape.assign(probs, probs + B);
+    if (tune) pl->tune = *tune;
     abm_status st = ABM_OK;
 
     // one weight table per distinct alpha, long enough for its longest member

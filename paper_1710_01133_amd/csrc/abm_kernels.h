@@ -68,7 +68,9 @@ struct GroupDev {
     const uint16_t* ah[3];
     double alpha;
     double* F;             // time-major double history [k][ldF]
-    float* F32;            // float copy, column-blocked (colblocked_index)
+    float* F32;            // float copy: column-blocked (colblocked_index), or
+                           // time-major [k][ldF] in a narrow group
+
     uint16_t* Fh[3];       // bf16 split terms of the history, k-blocked (kblocked_index)
     int64_t ldF;           // padded columns
     int64_t rows;          // history rows allocated
@@ -76,20 +78,22 @@ struct GroupDev {
     double* part[2];       // far partials [split][col][2L], by block parity
     const TrajDesc* traj;  // members
     int32_t d;
-    int32_t pad_;
+    int32_t narrow;        // 1: few columns, far field by the blocked convolution,
+                           // ldF = real columns and F32 time-major
 };
 
 // Far field of one group for block m: history k = 1..kfar, kfar = (m-1)L.
 struct FarItem {
     int32_t group;
-    int32_t ncoltiles;     // active columns / tile width
-    int32_t nchunks;       // ceil(kfar / kchunk)
+    int32_t ncoltiles;     // active columns / tile width (narrow: product tiles)
+    int32_t nchunks;       // ceil(kfar / kchunk) (narrow: chunks of shifts)
     int32_t chunks_per_split;
     int32_t nsplit;        // partial slices written
     int32_t pad_;
     int64_t mL;
     int64_t kfar;
-    int64_t ldP;           // column stride of the partial slices (active columns, padded)
+    int64_t ldP;           // column stride of the partial slices (active columns,
+                           // padded to the tile width except in narrow groups)
 };
 
 // Chain of one trajectory (group member) through block m.
@@ -110,14 +114,36 @@ size_t far_lds_bytes(int L, int kchunk, int prec);
 int far_split_plan(int64_t kfar, int kchunk, int max_split, int* nchunks, int* chunks_per_split);
 // Upper bound of far_split_plan's slice count over every kfar <= kfar_max.
 int far_split_bound(int64_t kfar_max, int kchunk, int max_split);
-// One launch over n items (all of precision prec); grid (max_coltiles,
-// max_nsplit, n); workgroups beyond an item's own tiles/splits exit.
+// One launch over n items, all of launch class cls (far_class below);
+// grid (max_coltiles, max_nsplit, n) for the Toeplitz kernels, (1,
+// max_nsplit, n) for the blocked convolution; workgroups beyond an item's
+// own tiles/splits exit.
 hipError_t launch_far(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
-                      int max_nsplit, int kchunk, int L, int prec, hipStream_t st);
+                      int max_nsplit, int kchunk, int L, int cls, hipStream_t st);
 size_t far_lp_lds_bytes(int L, int kchunk, int prec);
 hipError_t launch_far_lp(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
                          int max_nsplit, int kchunk, int L, int prec, hipStream_t st);
 hipError_t allow_lds(const void* fn, size_t bytes);   // dynamic LDS above 64 KiB
+
+// Far-field launch classes: 0..3 the Toeplitz kernels by precision (abm_prec),
+// 4 and 5 the blocked convolution of narrow groups in double and float.
+constexpr int kFarClasses = 6;
+inline int far_class(int prec, bool narrow)
+{
+    return narrow ? (prec == 0 ? 4 : 5) : prec;
+}
+// Blocked convolution (narrow groups, fp64 / fp32 far field): product tiles
+// of a block for cols columns, whether a group qualifies, its split plan over
+// the K + L - 16 rows of shifts and the bound of that plan's slice count.
+constexpr int kHankelMaxCols = 8;
+int hankel_tiles(int64_t cols, int L);
+bool hankel_fits(int prec, int64_t cols, int L);
+int hankel_chunk_rows();
+int hankel_split_plan(int64_t kfar, int L, int max_split, int* nchunks, int* chunks_per_split);
+int hankel_split_bound(int64_t kfar_max, int L, int max_split);
+size_t hankel_lds_bytes(int L, int max_tiles, int prec);
+hipError_t launch_far_hankel(const GroupDev* groups, const FarItem* items, int n, int max_tiles,
+                             int max_nsplit, int L, int prec, hipStream_t st);
 
 // ---- K3: near band + predictor/corrector chain -----------------------------
 // One wave per item; all items of a launch share the right-hand side.

@@ -45,7 +45,8 @@ struct Group {
     std::vector<int> members;     // problem indices, N descending
     std::vector<int32_t> col0;    // first column of each member
     int64_t cols = 0;             // real columns
-    int64_t ldF = 0;              // padded columns
+    int64_t ldF = 0;              // padded columns (narrow groups: real columns)
+    bool narrow = false;          // far field by the blocked convolution
     int64_t rows = 0;             // history rows allocated
     double* F = nullptr;
     float* F32 = nullptr;
@@ -93,6 +94,8 @@ struct abm_plan_s {
     double* part = nullptr;
     uint32_t* flags = nullptr;
     // blocked path: groups and their static tick schedule
+    abm_tuning tune{};            // requested blocking (zero fields: defaults)
+    bool allow_narrow = true;
     int L = 0;
     int kchunk = 0;
     int max_split = 8;
@@ -102,7 +105,7 @@ struct abm_plan_s {
     abm::ChainItem* chain_items_dev = nullptr;
     abm::ChainItem* init_items_dev = nullptr;
     int64_t ticks = 0;
-    std::vector<abm::Span> far_spans;     // [tick][precision]
+    std::vector<abm::Span> far_spans;     // [tick][far launch class]
     std::vector<abm::Span> chain_spans;   // [tick][rhs]
     std::vector<abm::Span> init_spans;    // [rhs]
     int64_t far_macs = 0;

@@ -29,6 +29,9 @@ bool valid_L(int L) { return L == 64 || L == 128 || L == 256 || L == 512; }
 
 }  // namespace
 
+int group_split_plan(const Group& g, int64_t kfar, int L, int kchunk, int max_split, int* nchunks,
+                     int* chunks_per_split);
+
 void free_reduced(WeightTable& t)
 {
     dev_free(t.b32);
@@ -165,6 +168,7 @@ GroupDev group_dev(const Group& g, const WeightTable& W)
     d.part[1] = g.part[1];
     d.traj = g.traj_dev;
     d.d = g.d;
+    d.narrow = g.narrow ? 1 : 0;
     return d;
 }
 
@@ -189,16 +193,22 @@ void block_items(const Group& g, int gi, int64_t m, int L, int kchunk, int max_s
         it.group = gi;
         it.kfar = (mf - 1) * L;
         it.mL = mf * L;
-        it.ldP = round_up((int64_t)active(mf) * g.d, TN);
-        it.ncoltiles = (int32_t)(it.ldP / TN);
-        it.nsplit = far_split_plan(it.kfar, kchunk, max_split, &it.nchunks, &it.chunks_per_split);
+        if (g.narrow) {
+            it.ldP = (int64_t)active(mf) * g.d;
+            it.ncoltiles = hankel_tiles(it.ldP, L);
+        } else {
+            it.ldP = round_up((int64_t)active(mf) * g.d, TN);
+            it.ncoltiles = (int32_t)(it.ldP / TN);
+        }
+        it.nsplit = group_split_plan(g, it.kfar, L, kchunk, max_split, &it.nchunks,
+                                     &it.chunks_per_split);
         far->push_back(it);
     }
     if (chain && m < nblocks) {
         int nsp = 0, nc = 0, cps = 0;
-        if (m >= 2) nsp = far_split_plan((m - 1) * L, kchunk, max_split, &nc, &cps);
+        if (m >= 2) nsp = group_split_plan(g, (m - 1) * L, L, kchunk, max_split, &nc, &cps);
         const int32_t na = active(m);
-        const int64_t ldP = round_up((int64_t)na * g.d, TN);
+        const int64_t ldP = g.narrow ? (int64_t)na * g.d : round_up((int64_t)na * g.d, TN);
         for (int32_t j = 0; j < na; ++j) {
             ChainItem c{};
             c.group = gi;
@@ -211,30 +221,41 @@ void block_items(const Group& g, int gi, int64_t m, int L, int kchunk, int max_s
     }
 }
 
+int group_split_plan(const Group& g, int64_t kfar, int L, int kchunk, int max_split, int* nchunks,
+                     int* chunks_per_split)
+{
+    if (g.narrow) return hankel_split_plan(kfar, L, max_split, nchunks, chunks_per_split);
+    return far_split_plan(kfar, kchunk, max_split, nchunks, chunks_per_split);
+}
+
 int64_t group_far_split_max(const Group& g, int L, int kchunk, int max_split)
 {
     const int64_t nblocks = (g.nmax + L - 1) / L;
     const int64_t kfar_max = nblocks >= 2 ? (nblocks - 2) * L : 0;   // far(m) covers (m-1)L
+    if (g.narrow) return hankel_split_bound(kfar_max, L, max_split);
     return far_split_bound(kfar_max, kchunk, max_split);
 }
 
 abm_status choose_blocking(abm_plan_s* pl, const abm_problem* probs, int B)
 {
-    int L = env_int("ABM_BLOCK_L", pl->L > 0 ? pl->L : 256);
-    if (!valid_L(L)) return fail(ABM_EINVAL, "ABM_BLOCK_L=%d not in {64,128,256,512}", L);
+    const abm_tuning& T = pl->tune;
+    int L = T.block_L ? T.block_L : env_int("ABM_BLOCK_L", 256);
+    if (!valid_L(L)) return fail(ABM_EINVAL, "block length %d not in {64,128,256,512}", L);
     for (int i = 0; i < B; ++i)
         if (probs[i].far_prec != ABM_FAR_FP64 && L < 128)
             return fail(ABM_EINVAL, "problem %d: reduced-precision far field needs block length >= 128", i);
-    int kchunk = env_int("ABM_KCHUNK", 2048);
-    if (kchunk < 512 || kchunk % 512)
-        return fail(ABM_EINVAL, "ABM_KCHUNK=%d must be a positive multiple of 512", kchunk);
+    int kchunk = T.kchunk ? T.kchunk : env_int("ABM_KCHUNK", 2048);
+    if (kchunk < 512 || kchunk % 512 || kchunk > (1 << 20))
+        return fail(ABM_EINVAL, "history chunk %d must be a multiple of 512 (at most 2^20)", kchunk);
     // largest chunk whose LDS footprint fits every precision used
     for (int prec = 0; prec < 4; ++prec)
         while (kchunk > 512 && far_lds_bytes(L, kchunk, prec) > kMaxLds) kchunk -= 512;
     pl->L = L;
     pl->kchunk = kchunk;
-    pl->max_split = env_int("ABM_MAX_SPLIT", 8);
-    if (pl->max_split < 1) return fail(ABM_EINVAL, "ABM_MAX_SPLIT must be >= 1");
+    pl->max_split = T.max_split ? T.max_split : env_int("ABM_MAX_SPLIT", 8);
+    if (pl->max_split < 1 || pl->max_split > 4096)
+        return fail(ABM_EINVAL, "split count %d out of range 1..4096", pl->max_split);
+    pl->allow_narrow = !T.column_tiles_only && env_int("ABM_NARROW", 1) != 0;
     return ABM_OK;
 }
 
@@ -270,7 +291,8 @@ abm_status batch_setup(abm_plan_s* pl)
         const int TN = far_tile_cols(L, g.prec);
         g.nmax = pl->shape[g.members[0]].N;
         g.cols = (int64_t)g.members.size() * g.d;
-        g.ldF = round_up(g.cols, TN);
+        g.narrow = pl->allow_narrow && hankel_fits(g.prec, g.cols, L);
+        g.ldF = g.narrow ? g.cols : round_up(g.cols, TN);
         g.rows = g.nmax + 1 + L;
         g.col0.resize(g.members.size());
         for (size_t j = 0; j < g.members.size(); ++j) g.col0[j] = (int32_t)(j * g.d);
@@ -286,16 +308,16 @@ abm_status batch_setup(abm_plan_s* pl)
     for (int gi = 0; gi < ngroups; ++gi)
         for (int idx : pl->groups[gi].members) memberN[gi].push_back(pl->shape[idx].N);
     pl->ticks = ticks;
-    pl->far_spans.assign((size_t)ticks * 4, Span{});
+    pl->far_spans.assign((size_t)ticks * kFarClasses, Span{});
     pl->chain_spans.assign((size_t)ticks * 5, Span{});
     std::vector<FarItem> far_all;
     std::vector<ChainItem> chain_all, init_all;
     for (int64_t t = 0; t < ticks; ++t) {
-        for (int prec = 0; prec < 4; ++prec) {
-            Span& sp = pl->far_spans[t * 4 + prec];
+        for (int cls = 0; cls < kFarClasses; ++cls) {
+            Span& sp = pl->far_spans[t * kFarClasses + cls];
             sp.offset = (int64_t)far_all.size();
             for (int gi = 0; gi < ngroups; ++gi)
-                if (pl->groups[gi].prec == prec)
+                if (far_class(pl->groups[gi].prec, pl->groups[gi].narrow) == cls)
                     block_items(pl->groups[gi], gi, t, L, kchunk, pl->max_split, memberN[gi],
                                 &far_all, nullptr);
             sp.count = (int32_t)((int64_t)far_all.size() - sp.offset);
@@ -331,9 +353,13 @@ abm_status batch_setup(abm_plan_s* pl)
         sp.count = (int32_t)((int64_t)init_all.size() - sp.offset);
     }
     // every item must fit its group's partial buffers (checked, not assumed)
-    for (const FarItem& it : far_all)
-        if (it.nsplit > pl->groups[it.group].nsplit_cap || it.ldP > pl->groups[it.group].ldF)
+    for (const FarItem& it : far_all) {
+        const Group& g = pl->groups[it.group];
+        if (it.nsplit > g.nsplit_cap || it.ldP > g.ldF)
             return fail(ABM_EDEVICE, "internal: far item exceeds the partial buffer of group %d", it.group);
+        if (g.narrow && !hankel_fits(g.prec, it.ldP, L))
+            return fail(ABM_EDEVICE, "internal: narrow far item of group %d has too many columns", it.group);
+    }
     for (const ChainItem& it : chain_all)
         if (it.nsplit > pl->groups[it.group].nsplit_cap)
             return fail(ABM_EDEVICE, "internal: chain item exceeds the partial buffer of group %d", it.group);
@@ -433,18 +459,18 @@ struct TickEnqueuer {
         hipEvent_t ev_chain_prev = nullptr, ev_far_prev = nullptr;
         for (int64_t t = 0; t < pl->ticks; ++t) {
             bool any_far = false;
-            for (int prec = 0; prec < 4; ++prec)
-                if (pl->far_spans[t * 4 + prec].count) any_far = true;
+            for (int cls = 0; cls < kFarClasses; ++cls)
+                if (pl->far_spans[t * kFarClasses + cls].count) any_far = true;
             hipEvent_t ev_far = nullptr;
             if (any_far) {
                 if (ev_chain_prev && (e = hipStreamWaitEvent(s1, ev_chain_prev, 0)) != hipSuccess)
                     return hip_fail(e, "stream wait");
-                for (int prec = 0; prec < 4; ++prec) {
-                    const Span& sp = pl->far_spans[t * 4 + prec];
+                for (int cls = 0; cls < kFarClasses; ++cls) {
+                    const Span& sp = pl->far_spans[t * kFarClasses + cls];
                     if (!sp.count) continue;
                     e = timed(0, s1, [&]() {
                         return launch_far(pl->groups_dev, pl->far_items_dev + sp.offset, sp.count,
-                                          sp.max_x, sp.max_y, pl->kchunk, L, prec, s1);
+                                          sp.max_x, sp.max_y, pl->kchunk, L, cls, s1);
                     });
                     if (e != hipSuccess) return hip_fail(e, "far-field launch");
                     ++far_launches;
@@ -539,6 +565,7 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
     abm_stats S{};
     S.block_L = pl->L;
     S.n_groups = (int32_t)pl->groups.size();
+    for (const Group& g : pl->groups) S.narrow_groups += g.narrow ? 1 : 0;
     S.far_macs = pl->far_macs;
 
     // per-solve descriptors (x0, p, h, outputs) through the pinned staging copies
@@ -600,6 +627,16 @@ extern "C" abm_status abm_plan_timing(abm_plan_t* pl, int32_t enable)
 {
     if (!pl) return fail(ABM_EINVAL, "plan is NULL");
     pl->timing = enable != 0;
+    return ABM_OK;
+}
+
+extern "C" abm_status abm_plan_config(abm_plan_t* pl, abm_tuning* out)
+{
+    if (!pl || !out) return fail(ABM_EINVAL, "NULL argument");
+    out->block_L = pl->L;
+    out->kchunk = pl->kchunk;
+    out->max_split = pl->max_split;
+    out->column_tiles_only = pl->allow_narrow ? 0 : 1;
     return ABM_OK;
 }
 

@@ -40,6 +40,7 @@ struct ChainArgs {
     uint16_t* Flo;
     int64_t ldF;
     int64_t rows;
+    bool narrow;           // F32 time-major [k][ldF] instead of column-blocked
     const double* part;
     int64_t ldP;
     int64_t mL;
@@ -63,6 +64,7 @@ __device__ __forceinline__ void chain_view(const GroupDev& G, const ChainItem& i
     A.Flo = G.Fh[2];
     A.ldF = G.ldF;
     A.rows = G.rows;
+    A.narrow = G.narrow != 0;
     A.part = G.part[(it.mL / L) & 1];
     A.ldP = it.ldP;
     A.mL = it.mL;
@@ -87,7 +89,10 @@ __device__ __forceinline__ void store_history(const ChainArgs& A, const TrajDesc
     for (int i = 0; i < D; ++i) A.F[row + i] = fs[i];
     if (A.F32) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) A.F32[colblocked_index(s, T.col0 + i, A.rows)] = (float)fs[i];
+        for (int i = 0; i < D; ++i) {
+            const int64_t at = A.narrow ? row + i : colblocked_index(s, T.col0 + i, A.rows);
+            A.F32[at] = (float)fs[i];
+        }
     }
     if (A.Fhi && s >= 1) {
 #pragma unroll

@@ -209,11 +209,14 @@ int far_split_bound(int64_t kfar_max, int kchunk, int max_split)
 }
 
 hipError_t launch_far(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
-                      int max_nsplit, int kchunk, int L, int prec, hipStream_t st)
+                      int max_nsplit, int kchunk, int L, int cls, hipStream_t st)
 {
     if (n < 1 || max_coltiles < 1 || max_nsplit < 1) return hipSuccess;
-    if (prec != ABM_FAR_FP64)
-        return launch_far_lp(groups, items, n, max_coltiles, max_nsplit, kchunk, L, prec, st);
+    if (cls == far_class(ABM_FAR_FP64, true) || cls == far_class(ABM_FAR_FP32, true))
+        return launch_far_hankel(groups, items, n, max_coltiles, max_nsplit, L,
+                                 cls == far_class(ABM_FAR_FP64, true) ? ABM_FAR_FP64 : ABM_FAR_FP32, st);
+    if (cls != ABM_FAR_FP64)
+        return launch_far_lp(groups, items, n, max_coltiles, max_nsplit, kchunk, L, cls, st);
     switch (L) {
     case 64: return launch_t<2, 8>(groups, items, n, max_coltiles, max_nsplit, kchunk, st);
     case 128: return launch_t<4, 4>(groups, items, n, max_coltiles, max_nsplit, kchunk, st);

@@ -71,6 +71,8 @@ struct Request {
 
 }  // namespace
 
+constexpr int kServeMaxSplit = 8;   // far partial slices per request and block
+
 struct ServeState {
     abm_ctx* ctx = nullptr;
     std::mutex mu;
@@ -82,7 +84,7 @@ struct ServeState {
     std::unordered_map<uint64_t, Request*> all;
     uint64_t next_ticket = 1;
     // owned by the server thread
-    int L = 256, kchunk = 2048, max_split = 8;
+    int L = 256, kchunk = 2048, max_split = kServeMaxSplit;
     char* arena = nullptr;
     size_t arena_cap = 0;
     std::map<size_t, size_t> free_list;   // offset -> size
@@ -146,6 +148,7 @@ struct ReqLayout {
     size_t gam, b, a, c, b32, a32, bh[3], ah[3], F, F32, Fh[3], traj, accn, part, total;
     int64_t wn, rows, ldF;
     size_t part_half;
+    bool narrow;
 };
 
 ReqLayout layout_of(const abm_problem& p, int L, int kchunk, int max_split)
@@ -154,7 +157,8 @@ ReqLayout layout_of(const abm_problem& p, int L, int kchunk, int max_split)
     const int TN = far_tile_cols(L, p.far_prec);
     r.wn = p.N + kWeightPad;
     r.rows = p.N + 1 + L;
-    r.ldF = (p.d + TN - 1) / TN * TN;
+    r.narrow = env_int("ABM_NARROW", 1) != 0 && hankel_fits(p.far_prec, p.d, L);
+    r.ldF = r.narrow ? p.d : (p.d + TN - 1) / TN * TN;
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o += align_up(bytes); return at; };
     r.gam = take(2 * sizeof(double));
@@ -184,7 +188,8 @@ ReqLayout layout_of(const abm_problem& p, int L, int kchunk, int max_split)
     r.accn = take((size_t)2 * p.d * L * sizeof(double));
     const int64_t nblocks = (p.N + L - 1) / L;
     const int64_t kfar_max = nblocks >= 2 ? (nblocks - 2) * L : 0;
-    const int nsp = std::max(1, far_split_bound(kfar_max, kchunk, max_split));
+    const int nsp = std::max(1, r.narrow ? hankel_split_bound(kfar_max, L, max_split)
+                                         : far_split_bound(kfar_max, kchunk, max_split));
     r.part_half = (size_t)nsp * r.ldF * 2 * L;
     r.part = take(2 * r.part_half * sizeof(double));
     r.total = o;
@@ -201,17 +206,26 @@ hipEvent_t pooled_event(ServeState* S)
     return ev;
 }
 
+// Block length and history chunk of the serving loop, the same for every
+// request (so a request's sums do not depend on what it is batched with).
+abm_status serve_params(int* L, int* kchunk)
+{
+    *L = env_int("ABM_SERVE_BLOCK_L", 256);
+    if (*L != 128 && *L != 256 && *L != 512)
+        return fail(ABM_EINVAL, "ABM_SERVE_BLOCK_L must be 128, 256 or 512");
+    *kchunk = 2048;
+    for (int prec = 0; prec < 4; ++prec)
+        while (*kchunk > 512 && far_lds_bytes(*L, *kchunk, prec) > kMaxLds) *kchunk -= 512;
+    return ABM_OK;
+}
+
 abm_status server_init(ServeState* S)
 {
     abm_ctx* ctx = S->ctx;
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    S->L = env_int("ABM_SERVE_BLOCK_L", 256);
-    if (S->L != 128 && S->L != 256 && S->L != 512)
-        return fail(ABM_EINVAL, "ABM_SERVE_BLOCK_L must be 128, 256 or 512");
-    S->kchunk = 2048;
-    for (int prec = 0; prec < 4; ++prec)
-        while (S->kchunk > 512 && far_lds_bytes(S->L, S->kchunk, prec) > kMaxLds) S->kchunk -= 512;
+    abm_status ps = serve_params(&S->L, &S->kchunk);
+    if (ps) return ps;
     S->arena_cap = ctx->arena_bytes;
     if ((e = hipMalloc((void**)&S->arena, S->arena_cap)) != hipSuccess) return hip_fail(e, "arena");
     S->free_list[0] = S->arena_cap;
@@ -274,6 +288,7 @@ abm_status admit(ServeState* S, Request* r, size_t off, const ReqLayout& lay)
     g.members = {0};
     g.col0 = {0};
     g.cols = p.d;
+    g.narrow = lay.narrow;
     g.ldF = lay.ldF;
     g.rows = lay.rows;
     g.F = (double*)(base + lay.F);
@@ -339,18 +354,20 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
     FarItem* fh = S->far_host + (size_t)ring * kMaxActive;
     ChainItem* ch = S->chain_host + (size_t)ring * kMaxActive;
     ChainItem* ih = S->init_host + (size_t)ring * kMaxActive;
-    // items grouped by class: far by precision, chain and init by rhs
-    std::vector<FarItem> far[4];
+    // items grouped by class: far by launch class, chain and init by rhs
+    std::vector<FarItem> far[kFarClasses];
     std::vector<ChainItem> chain[5], init[5];
     for (Request* r : S->active) {
         if (r->finishing || r->cancel_seen) continue;
         const std::vector<int64_t> memberN{r->prob.N};
-        const size_t f0 = far[r->g.prec].size(), c0 = chain[r->g.rhs].size();
+        const int cls = far_class(r->g.prec, r->g.narrow);
+        const size_t f0 = far[cls].size(), c0 = chain[r->g.rhs].size();
         block_items(r->g, r->slot, r->m, S->L, S->kchunk, S->max_split, memberN,
-                    &far[r->g.prec], &chain[r->g.rhs]);
+                    &far[cls], &chain[r->g.rhs]);
         // every item must fit the request's partial buffers (checked, not assumed)
-        for (size_t k = f0; k < far[r->g.prec].size(); ++k)
-            if (far[r->g.prec][k].nsplit > r->g.nsplit_cap || far[r->g.prec][k].ldP > r->g.ldF)
+        for (size_t k = f0; k < far[cls].size(); ++k)
+            if (far[cls][k].nsplit > r->g.nsplit_cap || far[cls][k].ldP > r->g.ldF ||
+                (r->g.narrow && !hankel_fits(r->g.prec, far[cls][k].ldP, S->L)))
                 return fail(ABM_EDEVICE, "internal: far item exceeds a request's partial buffer");
         for (size_t k = c0; k < chain[r->g.rhs].size(); ++k)
             if (chain[r->g.rhs][k].nsplit > r->g.nsplit_cap)
@@ -363,8 +380,8 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
         init[r->g.rhs].push_back(c);
     }
     int nf = 0, nc = 0, ni = 0;
-    Span fsp[4], csp[5], isp[5];
-    for (int k = 0; k < 4; ++k) {
+    Span fsp[kFarClasses], csp[5], isp[5];
+    for (int k = 0; k < kFarClasses; ++k) {
         fsp[k].offset = nf;
         fsp[k].count = (int32_t)far[k].size();
         for (const FarItem& it : far[k]) {
@@ -399,7 +416,7 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
         if ((e = hipStreamWaitEvent(S->s1, up, 0)) != hipSuccess) return hip_fail(e, "wait");
         if (S->ev_chain_prev && (e = hipStreamWaitEvent(S->s1, S->ev_chain_prev, 0)) != hipSuccess)
             return hip_fail(e, "wait");
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < kFarClasses; ++k) {
             if (!fsp[k].count) continue;
             e = launch_far(S->groups_dev, fd + fsp[k].offset, fsp[k].count, fsp[k].max_x,
                            fsp[k].max_y, S->kchunk, S->L, k, S->s1);
@@ -603,10 +620,9 @@ abm_status abm_submit(abm_ctx* ctx, const abm_problem* prob, double* y_out, uint
         ctx->serve->ctx = ctx;
     }
     ServeState* S = ctx->serve;
-    const int L = env_int("ABM_SERVE_BLOCK_L", 256);
-    if (prob->far_prec != ABM_FAR_FP64 && L < 128)
-        return fail(ABM_EINVAL, "reduced-precision far field needs block length >= 128");
-    const ReqLayout lay = layout_of(*prob, L, 2048, 8);
+    int L = 0, kchunk = 0;
+    if ((s = serve_params(&L, &kchunk))) return s;
+    const ReqLayout lay = layout_of(*prob, L, kchunk, kServeMaxSplit);
     if (lay.total > ctx->arena_bytes)
         return fail(ABM_ENOMEM, "request needs %zu bytes, the arena has %zu", lay.total,
                     ctx->arena_bytes);
@@ -630,6 +646,17 @@ abm_status abm_submit(abm_ctx* ctx, const abm_problem* prob, double* y_out, uint
     }
     S->cv.notify_all();
     *ticket = r->ticket;
+    return ABM_OK;
+}
+
+abm_status abm_request_bytes(abm_ctx* ctx, const abm_problem* prob, size_t* bytes)
+{
+    if (!ctx || !prob || !bytes) return fail(ABM_EINVAL, "NULL argument");
+    abm_status s = validate(*prob, 0);
+    if (s) return s;
+    int L = 0, kchunk = 0;
+    if ((s = serve_params(&L, &kchunk))) return s;
+    *bytes = layout_of(*prob, L, kchunk, kServeMaxSplit).total;
     return ABM_OK;
 }
 

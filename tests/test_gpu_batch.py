@@ -63,14 +63,23 @@ def test_batch_mixed_groups(ctx):
         assert normerr(y, oracle_run(p, 1)) <= TOL_FP64, p.rhs
 
 
-def test_batch_invariance_and_determinism(ctx):
+def test_batch_invariance_and_determinism(ctx, monkeypatch):
     probs = _sweep([2500, 1700, 2500, 900], seed=3)
     outs1, _ = run_batch(ctx, probs, 1)
     outs2, _ = run_batch(ctx, probs, 1)
     for a, b in zip(outs1, outs2):
         assert np.array_equal(a, b)
     for i in (0, 3):
-        alone, _ = run_batch(ctx, [probs[i]], 1)
+        # alone, a trajectory is a narrow group (blocked convolution): the
+        # same sums in another order
+        alone, st = run_batch(ctx, [probs[i]], 1)
+        assert st["narrow_groups"] == 1
+        assert normerr(alone[0], outs1[i]) <= 1e-13
+    # with the same far-field kernel the batch does not change a trajectory's bits
+    monkeypatch.setenv("ABM_NARROW", "0")
+    for i in (0, 3):
+        alone, st = run_batch(ctx, [probs[i]], 1)
+        assert st["narrow_groups"] == 0
         assert np.array_equal(alone[0], outs1[i])
 
 
@@ -80,7 +89,7 @@ def test_batch_single_trajectory_long(ctx):
     assert normerr(outs[0], oracle_run(p, 1)) <= TOL_FP64
 
 
-def test_sweep_full_size_fp64(ctx):
+def test_sweep_full_size_fp64(ctx, monkeypatch):
     """B = 1024, N = 65536 forcing sweep at the benchmark's launch shape:
     sampled members against stored oracle runs, the rest finite and bounded,
     and one member alone equal bit for bit to its column in the full batch."""
@@ -92,6 +101,9 @@ def test_sweep_full_size_fp64(ctx):
         assert normerr(outs[idx], ref) <= TOL_FP64, idx
     allv = np.stack(outs)
     assert np.all(np.isfinite(allv)) and np.max(np.abs(allv)) < 10
+    alone, _ = run_batch(ctx, [probs[511]], 1024)           # narrow group: other sum order
+    assert normerr(alone[0], outs[511]) <= 1e-13
+    monkeypatch.setenv("ABM_NARROW", "0")                    # same kernel: same bits
     alone, _ = run_batch(ctx, [probs[511]], 1024)
     assert np.array_equal(alone[0], outs[511])
 

@@ -88,7 +88,10 @@ def test_fifo_admission_under_small_arena(torch_ready):
     p0 = inputs.duffing_single(N=20000, h=2 ** -8)
     probs = [inputs.Problem("DUFFING", 0.9 + 0.01 * i, 2 ** -8, 20000, (0.1, 0.0),
                             (0.1, 0.3, 1.2)) for i in range(6)]
-    ctx = abm.Context(0, arena_bytes=24 << 20)
+    probe = abm.Context(0)
+    need = max(abm.request_bytes(probe, p) for p in probs)
+    probe.close()
+    ctx = abm.Context(0, arena_bytes=int(2.5 * need))
     ys = [abm.alloc_out(p, 0) for p in probs]
     tickets = [abm.submit(ctx, p, y, out_stride=0) for p, y in zip(probs, ys)]
     res = _wait(ctx, tickets)
@@ -103,8 +106,13 @@ def test_fifo_admission_under_small_arena(torch_ready):
 
 
 def test_error_paths(torch_ready):
-    ctx = abm.Context(0, arena_bytes=8 << 20)
+    p = inputs.duffing_single(N=15000, h=2 ** -8)
+    probe = abm.Context(0)
+    one = abm.request_bytes(probe, p)
+    probe.close()
+    ctx = abm.Context(0, arena_bytes=int(1.5 * one))     # holds one such request at a time
     big = inputs.duffing_single(N=200000)
+    assert abm.request_bytes(ctx, big) > int(1.5 * one)
     y = abm.alloc_out(big, 0)
     with pytest.raises(abm.AbmError) as e:
         abm.submit(ctx, big, y)
@@ -117,7 +125,6 @@ def test_error_paths(torch_ready):
         abm.poll(ctx, 987654)
     assert e.value.code == abm.ABM_ENOENT
     # cancel a request queued behind one that fills the arena
-    p = inputs.duffing_single(N=15000, h=2 ** -8)
     y1, y2 = abm.alloc_out(p, 0), abm.alloc_out(p, 0)
     t1 = abm.submit(ctx, p, y1)
     t2 = abm.submit(ctx, p, y2)

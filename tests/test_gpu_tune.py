@@ -1,0 +1,76 @@
+"""Explicit blocking (abm_plan_tuned / abm_plan_config) and the measuring
+autotuner (abm_autotune): the blockings it tries all give the method's
+results, the best one is a valid plan, and invalid blockings are refused."""
+import numpy as np
+import pytest
+
+from paper_1710_01133_amd import abm, inputs
+from gpu_common import normerr, oracle_run
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.init()
+    c = abm.Context(0)
+    yield c
+    c.close()
+
+
+def _mix():
+    amps = np.random.default_rng(3).uniform(0.1, 0.6, 12)
+    probs = [inputs.Problem("DUFFING", 0.95, 2 ** -7, 2600, (0.1, 0.0), (0.1, float(A), 1.2),
+                            far_prec="fp32") for A in amps]
+    probs.append(inputs.Problem("LORENZ", 0.97, 2 ** -8, 2000, (1.0, 1.0, 1.0),
+                                (10.0, 28.0, 8 / 3), far_prec="fp32"))
+    return probs
+
+
+def _solve(ctx, probs, tuning, stride=5):
+    plan = abm.Plan(ctx, probs, out_stride=stride, tuning=tuning)
+    cfg = plan.config()
+    ys = [abm.alloc_out(p, stride) for p in probs]
+    st = abm.solve_batch(plan, probs, ys)
+    plan.check()
+    plan.close()
+    return [y.cpu().numpy() for y in ys], cfg, st
+
+
+def test_explicit_blocking_is_used_and_correct(ctx):
+    probs = _mix()
+    for t in [dict(block_L=128, kchunk=1024, max_split=3, column_tiles_only=0),
+              dict(block_L=512, kchunk=512, max_split=1, column_tiles_only=1)]:
+        outs, cfg, st = _solve(ctx, probs, t)
+        assert cfg == t and st["block_L"] == t["block_L"]
+        assert st["narrow_groups"] == (0 if t["column_tiles_only"] else 1)
+        for p, y in zip(probs, outs):
+            assert normerr(y, oracle_run(p, 5)) <= 1e-6, t
+
+
+def test_invalid_blockings_refused(ctx):
+    probs = _mix()
+    for t in [dict(block_L=96, kchunk=0, max_split=0, column_tiles_only=0),
+              dict(block_L=64, kchunk=0, max_split=0, column_tiles_only=0),   # float far field
+              dict(block_L=256, kchunk=700, max_split=0, column_tiles_only=0),
+              dict(block_L=256, kchunk=0, max_split=-2, column_tiles_only=0)]:
+        with pytest.raises(abm.AbmError) as e:
+            abm.Plan(ctx, probs, out_stride=0, tuning=t)
+        assert e.value.code == abm.ABM_EINVAL, t
+
+
+def test_autotune_measures_and_picks_a_valid_blocking(ctx):
+    probs = _mix()
+    best, trials = abm.autotune(ctx, probs, out_stride=5, budget_s=30.0)
+    ok = [t for t in trials if t["status"] == abm.ABM_OK]
+    assert {t["cfg"]["block_L"] for t in ok} >= {128, 256, 512}
+    assert all(t["ms"] > 0 for t in ok)
+    assert best == min(ok, key=lambda t: t["ms"])["cfg"]
+    # the narrow Lorenz group makes the tuner also try column tiles only
+    assert any(t["cfg"]["column_tiles_only"] == 1 for t in ok)
+    outs, cfg, _ = _solve(ctx, probs, best)
+    assert cfg == best
+    for p, y in zip(probs, outs):
+        assert normerr(y, oracle_run(p, 5)) <= 1e-6
