@@ -11,6 +11,20 @@ namespace abm {
 
 constexpr int kWave = 64;
 
+// Pointers into device memory that the kernels read from descriptors are
+// generic to the compiler, which then emits flat memory instructions; flat
+// loads also count against the LDS wait counter, so every wait for an LDS
+// operand would wait for the HBM prefetch in flight as well.  Kernels
+// therefore access such memory through global-address-space pointers.
+#define ABM_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+using gptr = ABM_GLOBAL T*;
+template <typename T>
+__device__ __forceinline__ gptr<T> as_global(T* p)
+{
+    return (gptr<T>)p;
+}
+
 // f(t, y) for the right-hand side R (enum abm_rhs) of dimension D.
 template <int R, int D>
 __device__ __forceinline__ void rhs_eval(const double* __restrict__ p, double t, const double* y,

@@ -28,48 +28,48 @@ namespace {
 
 // Per-wave view of one chain work item.
 struct ChainArgs {
-    const double* b;
-    const double* a;
-    const double* c;
-    const double* gam;
+    gptr<const double> b;
+    gptr<const double> a;
+    gptr<const double> c;
+    gptr<const double> gam;
     double alpha;
-    double* F;
-    float* F32;
-    uint16_t* Fhi;
-    uint16_t* Fmid;
-    uint16_t* Flo;
+    gptr<double> F;
+    gptr<float> F32;
+    gptr<uint16_t> Fhi;
+    gptr<uint16_t> Fmid;
+    gptr<uint16_t> Flo;
     int64_t ldF;
     int64_t rows;
     bool narrow;           // F32 time-major [k][ldF] instead of column-blocked
-    const double* part;
+    gptr<const double> part;
     int64_t ldP;
     int64_t mL;
     int32_t nchunks;
-    double* accn;          // this member's carried sums [2][d][L]
+    gptr<double> accn;     // this member's carried sums [2][d][L]
 };
 
 template <int L>
 __device__ __forceinline__ void chain_view(const GroupDev& G, const ChainItem& it, int D,
                                            ChainArgs& A)
 {
-    A.b = G.b;
-    A.a = G.a;
-    A.c = G.c;
-    A.gam = G.gam;
+    A.b = as_global(G.b);
+    A.a = as_global(G.a);
+    A.c = as_global(G.c);
+    A.gam = as_global(G.gam);
     A.alpha = G.alpha;
-    A.F = G.F;
-    A.F32 = G.F32;
-    A.Fhi = G.Fh[0];
-    A.Fmid = G.Fh[1];
-    A.Flo = G.Fh[2];
+    A.F = as_global(G.F);
+    A.F32 = as_global(G.F32);
+    A.Fhi = as_global(G.Fh[0]);
+    A.Fmid = as_global(G.Fh[1]);
+    A.Flo = as_global(G.Fh[2]);
     A.ldF = G.ldF;
     A.rows = G.rows;
     A.narrow = G.narrow != 0;
-    A.part = G.part[(it.mL / L) & 1];
+    A.part = as_global((const double*)G.part[(it.mL / L) & 1]);
     A.ldP = it.ldP;
     A.mL = it.mL;
     A.nchunks = it.nsplit;
-    A.accn = G.accn + (size_t)it.member * 2 * D * L;
+    A.accn = as_global(G.accn) + (size_t)it.member * 2 * D * L;
 }
 
 __device__ __forceinline__ double readlane_d(double v, int l)
@@ -120,7 +120,7 @@ __device__ __forceinline__ void store_output(const TrajDesc& T, int64_t s, const
     }
     if (w >= 0) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) T.y_out[w * D + i] = y[i];
+        for (int i = 0; i < D; ++i) as_global(T.y_out)[w * D + i] = y[i];
     }
 }
 
@@ -165,7 +165,7 @@ __global__ __launch_bounds__(256) void k_chain(const GroupDev* __restrict__ grou
 
     const int r0 = Q * lane;                  // first row of this lane
     // carried sums of block m (written by the previous block's chain)
-    double* accn = A.accn;
+    const gptr<double> accn = A.accn;
     double accP[Q][D], accC[Q][D], nxtP[Q][D], nxtC[Q][D];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -175,7 +175,7 @@ __global__ __launch_bounds__(256) void k_chain(const GroupDev* __restrict__ grou
         for (int i = 0; i < D; ++i) {
             double sp = 0.0, sc = 0.0;
             for (int ch = 0; ch < A.nchunks; ++ch) {
-                const double* pc = A.part + ((size_t)ch * A.ldP + T.col0 + i) * (2 * L);
+                const gptr<const double> pc = A.part + ((size_t)ch * A.ldP + T.col0 + i) * (2 * L);
                 sp += pc[r];
                 sc += pc[L + r];
             }
@@ -340,7 +340,7 @@ __global__ void k_chain_init(const GroupDev* groups, const ChainItem* items, int
     store_history<D>(A, T, 0, f0);
     if (T.out_stride > 0) {
 #pragma unroll
-        for (int i = 0; i < D; ++i) T.y_out[i] = x0[i];
+        for (int i = 0; i < D; ++i) as_global(T.y_out)[i] = x0[i];
     }
 }
 

@@ -61,7 +61,7 @@ __global__ __launch_bounds__(256) void k_far_f64(const GroupDev* groups, const F
     // stage loader: kKS x TN doubles, coalesced along columns
     constexpr int kStageElems = kKS * TN;
     constexpr int kPerThread = (kStageElems + 255) / 256;
-    const double* Fg = A.F;
+    const gptr<const double> Fg = A.F;
     const int64_t ldF = A.ldF;
     double pre[kPerThread];
     auto load_stage = [&](int64_t k0) {
@@ -129,14 +129,14 @@ __global__ __launch_bounds__(256) void k_far_f64(const GroupDev* groups, const F
 
     // FFpart[split][col][2L].  The double 16x16x4 product returns row
     // lk + 4v of column li of the tile in register v of lane (li, lk).
-    double* out = A.part + (size_t)blockIdx.y * A.ldP * (2 * L);
+    const gptr<double> out = A.part + (size_t)blockIdx.y * A.ldP * (2 * L);
     const int prow = (corr ? L : 0) + rbase;
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
             const int col = col0 + j * 16 + li;
-            double* o = out + (size_t)col * (2 * L) + prow + i * 16 + lk;
+            const gptr<double> o = out + (size_t)col * (2 * L) + prow + i * 16 + lk;
 #pragma unroll
             for (int v = 0; v < 4; ++v) o[4 * v] = acc[i][j][v];
         }

@@ -6,15 +6,15 @@
 namespace abm {
 
 struct FarArgs {
-    const double* b;
-    const double* a;
-    const float* b32;
-    const float* a32;
-    const uint16_t* bh[3];
-    const uint16_t* ah[3];
-    const double* F;
-    const float* F32;
-    const uint16_t* Fh[3];
+    gptr<const double> b;
+    gptr<const double> a;
+    gptr<const float> b32;
+    gptr<const float> a32;
+    gptr<const uint16_t> bh[3];
+    gptr<const uint16_t> ah[3];
+    gptr<const double> F;
+    gptr<const float> F32;
+    gptr<const uint16_t> Fh[3];
     int64_t ldF;
     int64_t rows;
     int64_t mL;
@@ -22,7 +22,7 @@ struct FarArgs {
     int32_t kchunk;
     int32_t nchunks;
     int32_t chunks_per_split;
-    double* part;
+    gptr<double> part;
     int64_t ldP;
 };
 
@@ -36,18 +36,18 @@ __device__ __forceinline__ bool far_view(const GroupDev* __restrict__ groups,
     const FarItem it = items[blockIdx.z];
     if ((int)blockIdx.x >= it.ncoltiles || (int)blockIdx.y >= it.nsplit) return false;
     const GroupDev& G = groups[it.group];
-    A.b = G.b;
-    A.a = G.a;
-    A.b32 = G.b32;
-    A.a32 = G.a32;
+    A.b = as_global(G.b);
+    A.a = as_global(G.a);
+    A.b32 = as_global(G.b32);
+    A.a32 = as_global(G.a32);
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        A.bh[i] = G.bh[i];
-        A.ah[i] = G.ah[i];
-        A.Fh[i] = G.Fh[i];
+        A.bh[i] = as_global(G.bh[i]);
+        A.ah[i] = as_global(G.ah[i]);
+        A.Fh[i] = as_global((const uint16_t*)G.Fh[i]);
     }
-    A.F = G.F;
-    A.F32 = G.F32;
+    A.F = as_global((const double*)G.F);
+    A.F32 = as_global((const float*)G.F32);
     A.ldF = G.ldF;
     A.rows = G.rows;
     A.mL = it.mL;
@@ -55,7 +55,7 @@ __device__ __forceinline__ bool far_view(const GroupDev* __restrict__ groups,
     A.kchunk = kchunk;
     A.nchunks = it.nchunks;
     A.chunks_per_split = it.chunks_per_split;
-    A.part = G.part[(it.mL / L) & 1];
+    A.part = as_global(G.part[(it.mL / L) & 1]);
     A.ldP = it.ldP;
     return true;
 }

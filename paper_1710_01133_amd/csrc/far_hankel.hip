@@ -100,9 +100,9 @@ __device__ __forceinline__ void hankel_body(const GroupDev& G, const FarItem& it
     const int64_t K = it.kfar, mL = it.mL;
     const int64_t dmin = 1 - K / 16;
     const int64_t ndelta = K / 16 + R - 1;
-    const T* __restrict__ wbg = hk_weights<T>(G, false);
-    const T* __restrict__ wag = hk_weights<T>(G, true);
-    const T* __restrict__ hist = hk_history<T>(G);
+    const gptr<const T> wbg = as_global(hk_weights<T>(G, false));
+    const gptr<const T> wag = as_global(hk_weights<T>(G, true));
+    const gptr<const T> hist = as_global(hk_history<T>(G));
     const int64_t ldF = G.ldF;
 
     T* sw = reinterpret_cast<T*>(hk_smem);    // [2][kWlen] predictor, corrector weights
@@ -201,7 +201,7 @@ __device__ __forceinline__ void hankel_body(const GroupDev& G, const FarItem& it
     // reduce the four waves' sums (wave order 0..3) and store: tile q is the
     // predictor tile q (q < TMAX) or the corrector tile q - TMAX
     double* red = reinterpret_cast<double*>(hk_smem);   // [kRedSlots][kHWaves][64][4]
-    double* out = G.part[(mL / L) & 1] + (size_t)blockIdx.y * it.ldP * (2 * L);
+    const gptr<double> out = as_global(G.part[(mL / L) & 1]) + (size_t)blockIdx.y * it.ldP * (2 * L);
 #pragma unroll
     for (int q0 = 0; q0 < 2 * TMAX; q0 += kRedSlots) {
         __syncthreads();   // LDS free (staging or the previous round)
@@ -230,7 +230,7 @@ __device__ __forceinline__ void hankel_body(const GroupDev& G, const FarItem& it
             const int idx = tau * 16 + li;
             const int c = idx / R, rho = idx % R;
             if (c < ncols) {
-                double* o = out + (size_t)c * (2 * L) + (q < TMAX ? 0 : L) + 16 * rho;
+                const gptr<double> o = out + (size_t)c * (2 * L) + (q < TMAX ? 0 : L) + 16 * rho;
 #pragma unroll
                 for (int v = 0; v < 4; ++v) o[hk_row<T>(g, v)] = s[v];
             }

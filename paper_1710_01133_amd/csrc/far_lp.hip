@@ -75,12 +75,12 @@ template <int MT, int NT>
 __device__ __forceinline__ void store_part(const FarArgs& A, const d4 (&acc64)[MT][NT], int col0,
                                            int prow, int li, int g, int L)
 {
-    double* out = A.part + (size_t)blockIdx.y * A.ldP * (2 * L);
+    const gptr<double> out = A.part + (size_t)blockIdx.y * A.ldP * (2 * L);
 #pragma unroll
     for (int i = 0; i < MT; ++i)
 #pragma unroll
         for (int j = 0; j < NT; ++j) {
-            double* o = out + (size_t)(col0 + j * 16 + li) * (2 * L) + prow + i * 16 + 4 * g;
+            const gptr<double> o = out + (size_t)(col0 + j * 16 + li) * (2 * L) + prow + i * 16 + 4 * g;
 #pragma unroll
             for (int v = 0; v < 4; ++v) o[v] = acc64[i][j][v];
         }
@@ -122,7 +122,7 @@ __global__ __launch_bounds__(512, 1) void k_far_f32(const GroupDev* groups, cons
     constexpr int kStageElems = KS * TN;        // 512: one element per thread
     float pre = 0.f;
     // column-blocked float history: this workgroup's 16 columns are contiguous
-    const float* Fblk = A.F32 + (int64_t)(col0 >> 4) * A.rows * 16;
+    const gptr<const float> Fblk = A.F32 + (int64_t)(col0 >> 4) * A.rows * 16;
     auto load_stage = [&](int64_t k0) { pre = Fblk[k0 * 16 + t]; };
     auto store_stage = [&](int buf) { Ft[buf * kStageElems + t] = pre; };
 
@@ -200,16 +200,26 @@ __global__ __launch_bounds__(512, 1) void k_far_bf16(const GroupDev* groups, con
 
     constexpr int kPerThread = (kStageU4 + 511) / 512;
     u4 pre[kPerThread];
+    // split term of each staged element, chosen without indexing A.Fh by a
+    // per-thread value (which would move the descriptor to scratch memory)
+    gptr<const uint16_t> fsrc[kPerThread];
+    int64_t foff[kPerThread];
+#pragma unroll
+    for (int e = 0; e < kPerThread; ++e) {
+        const int idx = t + e * 512;
+        const int tt = idx / (NB8 * TN);
+        const int rem = idx % (NB8 * TN);
+        const int b = rem / TN, c = rem % TN;
+        fsrc[e] = tt == 0 ? A.Fh[0] : (tt == 1 ? A.Fh[1] : A.Fh[TERMS - 1]);
+        foff[e] = (int64_t)b * A.ldF + col0 + c;
+    }
     auto load_stage = [&](int64_t kb8, int st) {
 #pragma unroll
         for (int e = 0; e < kPerThread; ++e) {
             const int idx = t + e * 512;
             if (idx < kStageU4) {
-                const int tt = idx / (NB8 * TN);
-                const int rem = idx % (NB8 * TN);
-                const int b = rem / TN, c = rem % TN;
-                const int64_t blk = kb8 + (int64_t)st * NB8 + b;
-                pre[e] = *reinterpret_cast<const u4*>(A.Fh[tt] + (blk * A.ldF + col0 + c) * 8);
+                const int64_t blk0 = kb8 + (int64_t)st * NB8;
+                pre[e] = *reinterpret_cast<const ABM_GLOBAL u4*>(fsrc[e] + (blk0 * A.ldF + foff[e]) * 8);
             }
         }
     };
