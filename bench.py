@@ -103,11 +103,18 @@ def serving(abm, torch, inputs, n_req, arena_bytes, prec):
     queue = np.array([done[j]["t_start"] - done[j]["t_submit"] for j in range(n_req)])
     ok = sum(1 for j in range(n_req) if done[j]["status"] == 0)
     macs = sum(r.problem.history_macs() for r in reqs)
+    # requests running at once (admitted, not yet done), sampled at every admission
+    starts = np.array([done[j]["t_start"] for j in range(n_req)])
+    ends = np.array([done[j]["t_done"] for j in range(n_req)])
+    conc = [int(np.sum((starts <= t) & (ends > t))) for t in starts]
     ctx.close()
     return {"requests": n_req, "ok": ok, "rate_per_s": 200.0, "arena_bytes": arena_bytes,
             "far_prec": prec, "p50_s": float(np.percentile(lat, 50)),
             "p99_s": float(np.percentile(lat, 99)), "max_s": float(lat.max()),
-            "p50_queue_s": float(np.percentile(queue, 50)), "wall_s": wall,
+            "p50_queue_s": float(np.percentile(queue, 50)),
+            "p99_queue_s": float(np.percentile(queue, 99)),
+            "mean_concurrent": float(np.mean(conc)), "max_concurrent": int(max(conc)),
+            "wall_s": wall,
             "throughput_req_per_s": n_req / wall, "history_macs_per_s": macs / wall,
             "workload": "Poisson 200/s, half Duffing (d=2) half Lorenz (d=3), alpha~U[0.90,0.99], "
                         "N log-uniform [4096, 262144], h=2^-8, seed 1710"}
@@ -198,9 +205,12 @@ def main():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--plain-only", action="store_true",
                     help="only the plain per-step path on the 200000-step oscillator")
-    ap.add_argument("--serve-requests", type=int, default=400,
+    ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving stream (0 skips the serving leg)")
-    ap.add_argument("--serve-arena-mib", type=int, default=1024)
+    ap.add_argument("--serve-arena-mib", type=int, nargs="+", default=[64, 8192],
+                    help="arena sizes to serve the stream with (the first binds admission)")
+    ap.add_argument("--no-precisions", action="store_true",
+                    help="skip the sweep at the other far-field precisions")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--eager", action="store_true",
                     help="launch the batched solve eagerly instead of replaying its captured graph")
@@ -274,8 +284,30 @@ def main():
 
     serve = None
     if args.serve_requests > 0:
-        serve = serving(abm, torch, inputs, args.serve_requests, args.serve_arena_mib << 20,
-                        "fp32")
+        serve = {"arena_%dMiB" % mib: serving(abm, torch, inputs, args.serve_requests, mib << 20,
+                                              "fp32")
+                 for mib in args.serve_arena_mib}
+
+    # the same sweep at the other far-field precisions (error against the same oracle runs)
+    others = None
+    if not args.no_precisions:
+        others = {}
+        for pr in ("fp64", "bf16x6", "bf16x3"):
+            if pr == args.prec:
+                continue
+            pp = inputs.duffing_sweep(far_prec=pr)
+            pl2 = abm.Plan(ctx, pp, out_stride=stride)
+            pl2.graph(not args.eager)
+            dt2, st2 = time_batch(abm, torch, pl2, pp, ys, 2, 1)
+            e2 = {}
+            if os.path.exists(gold_path):
+                for i in (0, 1, 511, 1023):
+                    key = "duffing_sweep_%d" % i
+                    if key in g:
+                        e2[i] = normerr(ys[i].cpu().numpy(), np.array(g[key]["y"]))
+            others[pr] = {"value": st2["history_macs"] / dt2, "ms_per_step": dt2 * 1e3,
+                          "max_rel_err_vs_oracle": max(e2.values()) if e2 else None}
+            pl2.close()
 
     cpu = None if args.no_cpu else cpu_baseline(inputs)
 
@@ -305,6 +337,7 @@ def main():
         "plain": plain,
         "batched_over_plain": (value / plain["history_macs_per_s"]) if plain else None,
         "serving": serve,
+        "other_precisions": others,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))
