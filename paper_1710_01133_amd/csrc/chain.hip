@@ -124,15 +124,18 @@ __device__ __forceinline__ void store_output(const TrajDesc& T, int64_t s, const
     }
 }
 
-template <int R, int D, int L>
-__global__ __launch_bounds__(256) void k_chain(const GroupDev* __restrict__ groups,
+// W waves per workgroup: chains are latency-bound and register-heavy, so they
+// are packed two waves per SIMD on as few CUs as possible, which leaves whole
+// CUs to the far-field kernel running beside them.
+template <int R, int D, int L, int W>
+__global__ __launch_bounds__(64 * W) void k_chain(const GroupDev* __restrict__ groups,
                                                const ChainItem* __restrict__ items, int nitems,
                                                uint32_t* status)
 {
     constexpr int Q = L / 64;
     extern __shared__ double smc[];           // per wave: b[0..2L), a[0..2L)
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int j = blockIdx.x * 4 + wid;
+    const int j = blockIdx.x * W + wid;
     if (j >= nitems) return;                  // whole wave: no barrier below
     const ChainItem it = items[j];
     const GroupDev& G = groups[it.group];
@@ -299,28 +302,32 @@ __global__ __launch_bounds__(256) void k_chain(const GroupDev* __restrict__ grou
     if (bad) raise_status(status, kStatusNonFinite);
 }
 
+template <int R, int D, int L, int W>
+hipError_t launch_rdl(const GroupDev* groups, const ChainItem* items, int n, uint32_t* status,
+                      hipStream_t st)
+{
+    const dim3 grid((unsigned)((n + W - 1) / W));
+    const size_t shmem = (size_t)W * 4 * L * sizeof(double);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_chain<R, D, L, W>), shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_chain<R, D, L, W>), grid, dim3(64 * W), shmem, st, groups, items, n, status);
+    return hipGetLastError();
+}
+
 template <int R, int D>
 hipError_t launch_rd(const GroupDev* groups, const ChainItem* items, int n, int L, uint32_t* status,
                      hipStream_t st)
 {
-    const dim3 grid((unsigned)((n + 3) / 4));
-    const size_t shmem = 4 * 4 * (size_t)L * sizeof(double);
-    hipError_t e = hipSuccess;
     switch (L) {
-    case 64: hipLaunchKernelGGL((k_chain<R, D, 64>), grid, dim3(256), shmem, st, groups, items, n, status); break;
-    case 128: hipLaunchKernelGGL((k_chain<R, D, 128>), grid, dim3(256), shmem, st, groups, items, n, status); break;
-    case 256: hipLaunchKernelGGL((k_chain<R, D, 256>), grid, dim3(256), shmem, st, groups, items, n, status); break;
-    case 512:
-        e = allow_lds(reinterpret_cast<const void*>(&k_chain<R, D, 512>), shmem);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_chain<R, D, 512>), grid, dim3(256), shmem, st, groups, items, n, status);
-        break;
+    case 64: return launch_rdl<R, D, 64, 8>(groups, items, n, status, st);
+    case 128: return launch_rdl<R, D, 128, 8>(groups, items, n, status, st);
+    // three components at L = 256 need more than half a SIMD's registers
+    case 256: return launch_rdl<R, D, 256, (D <= 2 ? 8 : 4)>(groups, items, n, status, st);
+    case 512: return launch_rdl<R, D, 512, 4>(groups, items, n, status, st);   // one wave per SIMD fits
     default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
-// Solve start: f_0 = f(0, x0) into history row 0 (and reduced copies), y_0 = x0.
 template <int R, int D>
 __global__ void k_chain_init(const GroupDev* groups, const ChainItem* items, int n)
 {

@@ -15,10 +15,14 @@
 //   bf16x6: the above + w1 F1 + w0 F2 + w2 F0
 // so the dropped products are below 2^-16 (x3) and 2^-24 (x6) of w F.
 //
-// Tiling: a workgroup of 8 waves computes all 2L rows of the block for 16
-// columns; waves 0-3 hold L/4 predictor rows each, waves 4-7 the corrector
-// rows, so every SIMD runs two waves and one wave's double flushes run under
-// the other's matrix work.  Reduced precision needs L >= 128.
+// Tiling: a workgroup computes all 2L rows of the block for 16 columns.  In
+// float, 8 waves: waves 0-3 hold L/4 predictor rows each, waves 4-7 the
+// corrector rows.  In bf16, each wave holds 8 row tiles (128 rows) when
+// L <= 256, so a workgroup is 2L/128 waves, one per SIMD with the whole
+// register file: the history fragment of a product step is then read from
+// LDS once per 8 tiles instead of once per 4, which halves the LDS traffic
+// that otherwise limits these products (L = 512 keeps 4 tiles per wave).
+// Reduced precision needs L >= 128.
 //
 // Operand layout of the bf16 16x16x32 product: lane (li = lane%16, g = lane/16)
 // supplies row li, history rows 8g..8g+7 of the A fragment and column li,
@@ -164,11 +168,13 @@ __global__ __launch_bounds__(512, 1) void k_far_f32(const GroupDev* groups, cons
 }
 
 // ------------------------------------------------------------------ bf16 split
-template <int MT, int TERMS>
-__global__ __launch_bounds__(512, 1) void k_far_bf16(const GroupDev* groups, const FarItem* items,
-                                                     int kchunk)
+// MT row tiles per wave, WPR waves per row kind (predictor, corrector).
+template <int MT, int TERMS, int WPR>
+__global__ __launch_bounds__(128 * WPR, 1) void k_far_bf16(const GroupDev* groups,
+                                                           const FarItem* items, int kchunk)
 {
-    constexpr int L = 64 * MT, TN = 16;
+    constexpr int L = 16 * MT * WPR, TN = 16;
+    constexpr int NTH = 128 * WPR;              // threads
     FarArgs A;
     if (!far_view(groups, items, kchunk, L, A)) return;
     constexpr int QS = 4;                       // K-steps (32 rows) per stage
@@ -184,8 +190,8 @@ __global__ __launch_bounds__(512, 1) void k_far_bf16(const GroupDev* groups, con
 
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int col0 = blockIdx.x * TN;
-    const bool corr = wid >= 4;
-    const int rbase = (wid & 3) * (L / 4);
+    const bool corr = wid >= WPR;
+    const int rbase = (wid % WPR) * (L / WPR);
     const uint16_t* wr = corr ? wra : wrb;
     const int li = lane & 15, g = lane >> 4;
     const int abase = L - 1 - rbase - li + 8 * g;   // fragment v starts at abase + 16 v
@@ -198,7 +204,7 @@ __global__ __launch_bounds__(512, 1) void k_far_bf16(const GroupDev* groups, con
         acc64[i][0] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
-    constexpr int kPerThread = (kStageU4 + 511) / 512;
+    constexpr int kPerThread = (kStageU4 + NTH - 1) / NTH;
     u4 pre[kPerThread];
     // split term of each staged element, chosen without indexing A.Fh by a
     // per-thread value (which would move the descriptor to scratch memory)
@@ -206,7 +212,7 @@ __global__ __launch_bounds__(512, 1) void k_far_bf16(const GroupDev* groups, con
     int64_t foff[kPerThread];
 #pragma unroll
     for (int e = 0; e < kPerThread; ++e) {
-        const int idx = t + e * 512;
+        const int idx = t + e * NTH;
         const int tt = idx / (NB8 * TN);
         const int rem = idx % (NB8 * TN);
         const int b = rem / TN, c = rem % TN;
@@ -216,7 +222,7 @@ __global__ __launch_bounds__(512, 1) void k_far_bf16(const GroupDev* groups, con
     auto load_stage = [&](int64_t kb8, int st) {
 #pragma unroll
         for (int e = 0; e < kPerThread; ++e) {
-            const int idx = t + e * 512;
+            const int idx = t + e * NTH;
             if (idx < kStageU4) {
                 const int64_t blk0 = kb8 + (int64_t)st * NB8;
                 pre[e] = *reinterpret_cast<const ABM_GLOBAL u4*>(fsrc[e] + (blk0 * A.ldF + foff[e]) * 8);
@@ -226,7 +232,7 @@ __global__ __launch_bounds__(512, 1) void k_far_bf16(const GroupDev* groups, con
     auto store_stage = [&](int buf) {
 #pragma unroll
         for (int e = 0; e < kPerThread; ++e) {
-            const int idx = t + e * 512;
+            const int idx = t + e * NTH;
             if (idx < kStageU4) Bst[buf * kStageU4 + idx] = pre[e];
         }
     };
@@ -244,7 +250,7 @@ __global__ __launch_bounds__(512, 1) void k_far_bf16(const GroupDev* groups, con
         const int64_t kb8 = (cb.k_lo - 1) >> 3;
         __syncthreads();   // previous chunk's readers are done with the LDS
         // reversed windows: wr[x] = w[jb + wlen - 1 - x]
-        for (int x = t; x < cb.wlen; x += 512) {
+        for (int x = t; x < cb.wlen; x += NTH) {
             const int64_t j = cb.jb + cb.wlen - 1 - x;
 #pragma unroll
             for (int tt = 0; tt < TERMS; ++tt) {
@@ -323,17 +329,20 @@ hipError_t launch_f32_t(const LpLaunch& P, hipStream_t st)
     return hipGetLastError();
 }
 
-template <int MT, int TERMS>
+// Row tiles per wave: 8 where one wave per SIMD can hold them (L <= 256:
+// the history fragment is then read once per 8 tiles), else L/64.
+template <int L, int TERMS>
 hipError_t launch_bf16_t(const LpLaunch& P, hipStream_t st)
 {
-    constexpr int L = 64 * MT;
+    constexpr int MT = L <= 256 ? (L / 32 < 8 ? L / 32 : 8) : L / 64;
+    constexpr int WPR = L / (16 * MT);
     const size_t shmem =
         far_lp_lds_bytes(L, P.kchunk, TERMS == 2 ? ABM_FAR_BF16X3 : ABM_FAR_BF16X6);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_bf16<MT, TERMS>), shmem);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_bf16<MT, TERMS, WPR>), shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_far_bf16<MT, TERMS>),
+    hipLaunchKernelGGL((k_far_bf16<MT, TERMS, WPR>),
                        dim3((unsigned)P.max_coltiles, (unsigned)P.max_nsplit, (unsigned)P.n),
-                       dim3(512), shmem, st, P.groups, P.items, P.kchunk);
+                       dim3(128 * WPR), shmem, st, P.groups, P.items, P.kchunk);
     return hipGetLastError();
 }
 
@@ -362,17 +371,17 @@ hipError_t launch_far_lp(const GroupDev* groups, const FarItem* items, int n, in
     }
     if (prec == ABM_FAR_BF16X3) {
         switch (L) {
-        case 128: return launch_bf16_t<2, 2>(A, st);
-        case 256: return launch_bf16_t<4, 2>(A, st);
-        case 512: return launch_bf16_t<8, 2>(A, st);
+        case 128: return launch_bf16_t<128, 2>(A, st);
+        case 256: return launch_bf16_t<256, 2>(A, st);
+        case 512: return launch_bf16_t<512, 2>(A, st);
         default: return hipErrorInvalidValue;
         }
     }
     if (prec == ABM_FAR_BF16X6) {
         switch (L) {
-        case 128: return launch_bf16_t<2, 3>(A, st);
-        case 256: return launch_bf16_t<4, 3>(A, st);
-        case 512: return launch_bf16_t<8, 3>(A, st);
+        case 128: return launch_bf16_t<128, 3>(A, st);
+        case 256: return launch_bf16_t<256, 3>(A, st);
+        case 512: return launch_bf16_t<512, 3>(A, st);
         default: return hipErrorInvalidValue;
         }
     }
