@@ -168,9 +168,10 @@ __global__ __launch_bounds__(512, 1) void k_far_f32(const GroupDev* groups, cons
 }
 
 // ------------------------------------------------------------------ bf16 split
-// MT row tiles per wave, WPR waves per row kind (predictor, corrector).
+// MT row tiles per wave, WPR waves per row kind (predictor, corrector); with
+// 4 waves two workgroups share a CU, so each SIMD runs two waves.
 template <int MT, int TERMS, int WPR>
-__global__ __launch_bounds__(128 * WPR, 1) void k_far_bf16(const GroupDev* groups,
+__global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const GroupDev* groups,
                                                            const FarItem* items, int kchunk)
 {
     constexpr int L = 16 * MT * WPR, TN = 16;
@@ -288,6 +289,17 @@ __global__ __launch_bounds__(128 * WPR, 1) void k_far_bf16(const GroupDev* group
 #pragma unroll
                 for (int tt = 0; tt < TERMS; ++tt)
                     bfr[tt] = __builtin_bit_cast(bf8, Bs[(tt * NB8 + 4 * qq + g) * TN + li]);
+                // Ordering fence (no instruction): this step's products take their
+                // history operands only after the previous step's double flush, so a
+                // single set of float accumulators is live.  Left alone, the compiler
+                // keeps every step's accumulators of a stage and flushes them
+                // together, which needs a second register set and halves occupancy.
+#pragma unroll
+                for (int i = 0; i < MT; ++i)
+#pragma unroll
+                    for (int tt = 0; tt < TERMS; ++tt)
+                        asm volatile("" : "+v"(bfr[tt]) : "v"(acc64[i][0][0]), "v"(acc64[i][0][1]),
+                                     "v"(acc64[i][0][2]), "v"(acc64[i][0][3]));
                 // small products first, the leading w0 F0 last
                 constexpr int NP = (TERMS == 2) ? 3 : 6;
                 constexpr int pa[6] = {2, 0, 1, 1, 0, 0};
