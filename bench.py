@@ -208,7 +208,7 @@ def main():
                     help="only the plain per-step path on the 200000-step oscillator")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving stream (0 skips the serving leg)")
-    ap.add_argument("--serve-arena-mib", type=int, nargs="+", default=[64, 8192],
+    ap.add_argument("--serve-arena-mib", type=int, nargs="+", default=[192, 8192],
                     help="arena sizes to serve the stream with (the first binds admission)")
     ap.add_argument("--no-precisions", action="store_true",
                     help="skip the sweep at the other far-field precisions")
@@ -293,7 +293,7 @@ def main():
     others = None
     if not args.no_precisions:
         others = {}
-        for pr in ("fp64", "bf16x6", "bf16x3"):
+        for pr in ("fp64", "fp32", "bf16x6", "bf16x3"):
             if pr == args.prec:
                 continue
             pp = inputs.duffing_sweep(far_prec=pr)

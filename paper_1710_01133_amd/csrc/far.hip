@@ -94,9 +94,23 @@ __global__ __launch_bounds__(256) void k_far_f64(const GroupDev* groups, const F
         const int64_t jb = mL - k_hi + 1;                     // lowest weight index used (>= 0)
         const int wlen = L + nk - 1;
         __syncthreads();   // previous chunk's readers are done with the LDS
-        for (int x = t; x < wlen; x += 256) {
-            wb[x] = A.b[jb + x];
-            wa[x] = A.a[jb + x];
+        // weight window: the loads of a batch are all issued before its stores
+        for (int x0 = t; x0 < wlen; x0 += 256 * 4) {
+            double vb[4], va[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int x = x0 + 256 * u;
+                vb[u] = x < wlen ? A.b[jb + x] : 0.0;
+                va[u] = x < wlen ? A.a[jb + x] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int x = x0 + 256 * u;
+                if (x < wlen) {
+                    wb[x] = vb[u];
+                    wa[x] = va[u];
+                }
+            }
         }
         load_stage(k_lo);
         store_stage(0);

@@ -97,6 +97,9 @@ __device__ __forceinline__ void hankel_body(const GroupDev& G, const FarItem& it
     typedef typename std::conditional<kFloat, f4, d4>::type acc_t;
 
     const int ncols = (int)it.ldP;
+    // floor(e / ncols) = (e * inv_cols) >> 20 for every staged e (e < 2^17,
+    // ncols <= 8; checked exhaustively)
+    const unsigned inv_cols = (1u << 20) / (unsigned)ncols + 1u;
     const int64_t K = it.kfar, mL = it.mL;
     const int64_t dmin = 1 - K / 16;
     const int64_t ndelta = K / 16 + R - 1;
@@ -143,22 +146,51 @@ __device__ __forceinline__ void hankel_body(const GroupDev& G, const FarItem& it
         const int nd = (int)((ndelta - i0) < kDch ? (ndelta - i0) : kDch);
         const int64_t d0 = dmin + i0, d1 = d0 + nd;
         __syncthreads();   // the previous chunk's readers are done with the LDS
+        // Staging: every load of a batch is issued before its first LDS store
+        // (a load-then-store loop waits on each load in turn, which made the
+        // staging, not the products, the cost of a chunk).
         // weights w_{mL - 16 + 16 d0 + x}, x < 16 nd + 15
         const int64_t wlo = mL - 16 + 16 * d0;
         const int nW = 16 * nd + 15;
-        for (int x = t; x < nW; x += 256) {
-            sw[x] = wbg[wlo + x];
-            sw[kWlen + x] = wag[wlo + x];
+        {
+            constexpr int kWPer = (kWlen + 255) / 256;
+            T vb[kWPer], va[kWPer];
+#pragma unroll
+            for (int u = 0; u < kWPer; ++u) {
+                const int x = t + 256 * u;
+                vb[u] = x < nW ? wbg[wlo + x] : T(0);
+                va[u] = x < nW ? wag[wlo + x] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kWPer; ++u) {
+                const int x = t + 256 * u;
+                if (x < nW) {
+                    sw[x] = vb[u];
+                    sw[kWlen + x] = va[u];
+                }
+            }
         }
-        // history rows klo .. klo + nH - 1, zero outside 1..K
+        // history rows klo .. klo + nH - 1, zero outside 1..K; element e is row
+        // e / ncols (by a reciprocal exact for these sizes), column e % ncols
         const int64_t klo = 17 - 16 * d1;
         const int nH = 16 * (nd + R - 1);
-        for (int e = t; e < nH * ncols; e += 256) {
-            const int x = e / ncols, c = e - (e / ncols) * ncols;
-            const int64_t k = klo + x;
-            T v = 0;
-            if (k >= 1 && k <= K) v = hist[k * ldF + c];
-            sh[c * HST + pad16(x)] = v;
+        const int nE = nH * ncols;
+        constexpr int kBatch = 8;
+        for (int e0 = t; e0 < nE; e0 += 256 * kBatch) {
+            T v[kBatch];
+            int at[kBatch];
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u) {
+                const int e = e0 + 256 * u;
+                const int x = (int)(((unsigned)e * inv_cols) >> 20);
+                const int c = e - x * ncols;
+                const int64_t k = klo + x;
+                at[u] = e < nE ? c * HST + pad16(x) : -1;
+                v[u] = (e < nE && k >= 1 && k <= K) ? hist[k * ldF + c] : T(0);
+            }
+#pragma unroll
+            for (int u = 0; u < kBatch; ++u)
+                if (at[u] >= 0) sh[at[u]] = v[u];
         }
         __syncthreads();
         for (int dd = wid; dd < nd; dd += kHWaves) {

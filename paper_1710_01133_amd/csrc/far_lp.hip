@@ -136,9 +136,23 @@ __global__ __launch_bounds__(512, 1) void k_far_f32(const GroupDev* groups, cons
     for (int chunk = c_begin; chunk < c_end; ++chunk) {
         const ChunkBounds cb = chunk_bounds(A, L, chunk);
         __syncthreads();   // previous chunk's readers are done with the LDS
-        for (int x = t; x < cb.wlen; x += 512) {
-            wb[x] = A.b32[cb.jb + x];
-            wa[x] = A.a32[cb.jb + x];
+        // weight window: the loads of a batch are all issued before its stores
+        for (int x0 = t; x0 < cb.wlen; x0 += 512 * 4) {
+            float vb[4], va[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int x = x0 + 512 * u;
+                vb[u] = x < cb.wlen ? A.b32[cb.jb + x] : 0.f;
+                va[u] = x < cb.wlen ? A.a32[cb.jb + x] : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int x = x0 + 512 * u;
+                if (x < cb.wlen) {
+                    wb[x] = vb[u];
+                    wa[x] = va[u];
+                }
+            }
         }
         load_stage(cb.k_lo);
         store_stage(0);
