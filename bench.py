@@ -213,6 +213,8 @@ def main():
     ap.add_argument("--no-precisions", action="store_true",
                     help="skip the sweep at the other far-field precisions")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--tune-budget", type=float, default=20.0,
+                    help="seconds for the autotuner to choose the blocking (0: library defaults)")
     ap.add_argument("--eager", action="store_true",
                     help="launch the batched solve eagerly instead of replaying its captured graph")
     args = ap.parse_args()
@@ -236,8 +238,18 @@ def main():
 
     stride = 1024
     probs = inputs.duffing_sweep(far_prec=args.prec)
+    # blocking chosen by the library's autotuner (whole solves of this sweep)
+    tuning = None
+    tune_report = None
+    if args.tune_budget > 0:
+        t0 = time.perf_counter()
+        best, trials = abm.autotune(ctx, probs, out_stride=stride, budget_s=args.tune_budget)
+        tuning = best
+        tune_report = {"best": best, "seconds": time.perf_counter() - t0,
+                       "trials": [{"cfg": t["cfg"], "ms": round(t["ms"], 2), "status": t["status"]}
+                                  for t in trials]}
     t0 = time.perf_counter()
-    plan = abm.Plan(ctx, probs, out_stride=stride)
+    plan = abm.Plan(ctx, probs, out_stride=stride, tuning=tuning)
     torch.cuda.synchronize()
     plan_s = time.perf_counter() - t0
     ys = [abm.alloc_out(p, stride) for p in probs]
@@ -328,12 +340,14 @@ def main():
         "config": {"workload": "forcing sweep: B=1024 forced Duffing, alpha=0.95, h=2^-8, "
                                "N=65536, d=2, far field %s" % args.prec,
                    "B": 1024, "N": 65536, "d": 2, "block_L": st["block_L"],
+                   "blocking": plan.config(),
                    "far_prec": args.prec, "launch": "eager" if args.eager else "graph"},
         "eager_ms_per_step": None if eager_dt is None else eager_dt * 1e3,
         "launch_bound_batch": small,
         "max_rel_err_vs_oracle": max_err,
         "err_members": errs,
         "plan_seconds": plan_s,
+        "autotune": tune_report,
         "roofline": roof,
         "plain": plain,
         "batched_over_plain": (value / plain["history_macs_per_s"]) if plain else None,
