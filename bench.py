@@ -208,7 +208,7 @@ def main():
                     help="only the plain per-step path on the 200000-step oscillator")
     ap.add_argument("--serve-requests", type=int, default=2000,
                     help="requests of the serving stream (0 skips the serving leg)")
-    ap.add_argument("--serve-arena-mib", type=int, nargs="+", default=[192, 8192],
+    ap.add_argument("--serve-arena-mib", type=int, nargs="+", default=[96, 8192],
                     help="arena sizes to serve the stream with (the first binds admission)")
     ap.add_argument("--no-precisions", action="store_true",
                     help="skip the sweep at the other far-field precisions")

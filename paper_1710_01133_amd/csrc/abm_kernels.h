@@ -101,7 +101,7 @@ struct ChainItem {
     int32_t group;
     int32_t member;
     int32_t nsplit;        // far partial slices of this block (0 when m < 2)
-    int32_t pad_;
+    int32_t rhs;           // right-hand side (abm_rhs) of the group
     int64_t mL;
     int64_t ldP;
 };
@@ -149,6 +149,9 @@ hipError_t launch_far_hankel(const GroupDev* groups, const FarItem* items, int n
 // One wave per item; all items of a launch share the right-hand side.
 hipError_t launch_chain(const GroupDev* groups, const ChainItem* items, int n, int rhs, int L,
                         uint32_t* status, hipStream_t st);
+// Items of any right-hand sides in one launch (one kernel for all systems).
+hipError_t launch_chain_mixed(const GroupDev* groups, const ChainItem* items, int n, int L,
+                              uint32_t* status, hipStream_t st);
 // f_0 into history row 0 and y_0 = x0 for every member of the listed groups.
 hipError_t launch_chain_init(const GroupDev* groups, const ChainItem* items, int n, int rhs,
                              hipStream_t st);

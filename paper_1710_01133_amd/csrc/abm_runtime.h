@@ -112,7 +112,6 @@ struct abm_plan_s {
     // far field on its own stream, overlapping the chain
     bool overlap = true;
     hipStream_t far_stream = nullptr;
-    hipStream_t rhs_streams[5] = {};     // chains per right-hand side when several are planned
     std::vector<hipEvent_t> sync_events;
     // optional per-launch timing
     bool timing = false;

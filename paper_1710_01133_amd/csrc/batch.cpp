@@ -81,10 +81,7 @@ void batch_teardown(abm_plan_s* pl)
     pl->sync_events.clear();
     if (pl->far_stream) (void)hipStreamDestroy(pl->far_stream);
     pl->far_stream = nullptr;
-    for (auto& c : pl->rhs_streams) {
-        if (c) (void)hipStreamDestroy(c);
-        c = nullptr;
-    }
+
 }
 
 // Reduced copies of a weight table for far precision prec (once per table).
@@ -217,6 +214,7 @@ void block_items(const Group& g, int gi, int64_t m, int L, int kchunk, int max_s
             ChainItem c{};
             c.group = gi;
             c.member = j;
+            c.rhs = g.rhs;
             c.nsplit = nsp;
             c.mL = m * L;
             c.ldP = ldP;
@@ -392,17 +390,6 @@ abm_status batch_setup(abm_plan_s* pl)
         e = hipStreamCreateWithFlags(&pl->far_stream, hipStreamNonBlocking);
         if (e != hipSuccess) return hip_fail(e, "far stream");
     }
-    bool rhs_used[5] = {};
-    int nrhs = 0;
-    for (const Group& g : pl->groups)
-        if (!rhs_used[g.rhs]) {
-            rhs_used[g.rhs] = true;
-            ++nrhs;
-        }
-    if (nrhs > 1)
-        for (int r = 0; r < 5; ++r)
-            if (rhs_used[r] && (e = hipStreamCreateWithFlags(&pl->rhs_streams[r], hipStreamNonBlocking)) != hipSuccess)
-                return hip_fail(e, "chain stream");
     return ABM_OK;
 }
 
@@ -496,33 +483,34 @@ struct TickEnqueuer {
             }
             if (ev_far_prev && (e = hipStreamWaitEvent(st, ev_far_prev, 0)) != hipSuccess)
                 return hip_fail(e, "stream wait");
-            // chains of different right-hand sides are independent: with more
-            // than one, each runs on its own stream, forked from and joined into st
-            int nrhs = 0;
-            for (int rhs = 0; rhs < 5; ++rhs) nrhs += pl->chain_spans[t * 5 + rhs].count ? 1 : 0;
-            hipEvent_t fork_c = nullptr;
-            if (nrhs > 1) {
-                fork_c = sync_event();
-                if (!fork_c || (e = hipEventRecord(fork_c, st)) != hipSuccess)
-                    return fail(ABM_EDEVICE, "chain fork");
-            }
+            // chains of every right-hand side: one launch (one kernel switching
+            // per wave when the tick mixes systems), so they run side by side
+            int nrhs = 0, nch = 0;
+            int64_t off0 = -1;
             for (int rhs = 0; rhs < 5; ++rhs) {
                 const Span& sp = pl->chain_spans[t * 5 + rhs];
                 if (!sp.count) continue;
-                hipStream_t sc = nrhs > 1 ? pl->rhs_streams[rhs] : st;
-                if (nrhs > 1 && (e = hipStreamWaitEvent(sc, fork_c, 0)) != hipSuccess)
-                    return hip_fail(e, "stream wait");
-                e = timed(1, sc, [&]() {
-                    return launch_chain(pl->groups_dev, pl->chain_items_dev + sp.offset, sp.count,
-                                        rhs, L, pl->status, sc);
+                ++nrhs;
+                if (off0 < 0) off0 = sp.offset;
+                nch += sp.count;
+            }
+            if (nrhs > 1) {
+                e = timed(1, st, [&]() {
+                    return launch_chain_mixed(pl->groups_dev, pl->chain_items_dev + off0, nch, L,
+                                              pl->status, st);
                 });
                 if (e != hipSuccess) return hip_fail(e, "chain launch");
                 ++chain_launches;
-                if (nrhs > 1) {
-                    hipEvent_t join_c = sync_event();
-                    if (!join_c || (e = hipEventRecord(join_c, sc)) != hipSuccess ||
-                        (e = hipStreamWaitEvent(st, join_c, 0)) != hipSuccess)
-                        return fail(ABM_EDEVICE, "chain join");
+            } else {
+                for (int rhs = 0; rhs < 5; ++rhs) {
+                    const Span& sp = pl->chain_spans[t * 5 + rhs];
+                    if (!sp.count) continue;
+                    e = timed(1, st, [&]() {
+                        return launch_chain(pl->groups_dev, pl->chain_items_dev + sp.offset, sp.count,
+                                            rhs, L, pl->status, st);
+                    });
+                    if (e != hipSuccess) return hip_fail(e, "chain launch");
+                    ++chain_launches;
                 }
             }
             ev_chain_prev = sync_event();

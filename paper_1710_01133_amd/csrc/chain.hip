@@ -127,22 +127,17 @@ __device__ __forceinline__ void store_output(const TrajDesc& T, int64_t s, const
 // W waves per workgroup: chains are latency-bound and register-heavy, so they
 // are packed two waves per SIMD on as few CUs as possible, which leaves whole
 // CUs to the far-field kernel running beside them.
-template <int R, int D, int L, int W>
-__global__ __launch_bounds__(64 * W) void k_chain(const GroupDev* __restrict__ groups,
-                                               const ChainItem* __restrict__ items, int nitems,
-                                               uint32_t* status)
+// The block of one chain item, run by one wave (smw: that wave's 4L doubles
+// of LDS).
+template <int R, int D, int L>
+__device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& it, double* smw,
+                                            int lane, uint32_t* status)
 {
     constexpr int Q = L / 64;
-    extern __shared__ double smc[];           // per wave: b[0..2L), a[0..2L)
-    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    const int j = blockIdx.x * W + wid;
-    if (j >= nitems) return;                  // whole wave: no barrier below
-    const ChainItem it = items[j];
-    const GroupDev& G = groups[it.group];
     ChainArgs A;
     chain_view<L>(G, it, D, A);
     const TrajDesc T = G.traj[it.member];
-    double* swb = smc + (size_t)wid * 4 * L;
+    double* swb = smw;
     double* swa = swb + 2 * L;
     for (int x = lane; x < 2 * L; x += 64) {
         swb[x] = A.b[x];
@@ -303,6 +298,55 @@ __global__ __launch_bounds__(64 * W) void k_chain(const GroupDev* __restrict__ g
 }
 
 template <int R, int D, int L, int W>
+__global__ __launch_bounds__(64 * W) void k_chain(const GroupDev* __restrict__ groups,
+                                               const ChainItem* __restrict__ items, int nitems,
+                                               uint32_t* status)
+{
+    extern __shared__ double smc[];           // per wave: b[0..2L), a[0..2L)
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int j = blockIdx.x * W + wid;
+    if (j >= nitems) return;                  // whole wave: no barrier below
+    const ChainItem it = items[j];
+    chain_block<R, D, L>(groups[it.group], it, smc + (size_t)wid * 4 * L, lane, status);
+}
+
+// Items of several right-hand sides in one launch (each wave switches on its
+// item's): chains of different systems then run side by side in one kernel.
+template <int L, int W>
+__global__ __launch_bounds__(64 * W) void k_chain_mixed(const GroupDev* __restrict__ groups,
+                                                     const ChainItem* __restrict__ items,
+                                                     int nitems, uint32_t* status)
+{
+    extern __shared__ double smc[];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    const int j = blockIdx.x * W + wid;
+    if (j >= nitems) return;
+    const ChainItem it = items[j];
+    const GroupDev& G = groups[it.group];
+    double* smw = smc + (size_t)wid * 4 * L;
+    switch (it.rhs) {
+    case ABM_RHS_LINEAR: chain_block<ABM_RHS_LINEAR, 1, L>(G, it, smw, lane, status); break;
+    case ABM_RHS_DUFFING: chain_block<ABM_RHS_DUFFING, 2, L>(G, it, smw, lane, status); break;
+    case ABM_RHS_LORENZ: chain_block<ABM_RHS_LORENZ, 3, L>(G, it, smw, lane, status); break;
+    case ABM_RHS_POLY: chain_block<ABM_RHS_POLY, 1, L>(G, it, smw, lane, status); break;
+    case ABM_RHS_LCR: chain_block<ABM_RHS_LCR, 2, L>(G, it, smw, lane, status); break;
+    default: break;   // validated on the host
+    }
+}
+
+template <int L, int W>
+hipError_t launch_mixed_l(const GroupDev* groups, const ChainItem* items, int n, uint32_t* status,
+                          hipStream_t st)
+{
+    const dim3 grid((unsigned)((n + W - 1) / W));
+    const size_t shmem = (size_t)W * 4 * L * sizeof(double);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_chain_mixed<L, W>), shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_chain_mixed<L, W>), grid, dim3(64 * W), shmem, st, groups, items, n, status);
+    return hipGetLastError();
+}
+
+template <int R, int D, int L, int W>
 hipError_t launch_rdl(const GroupDev* groups, const ChainItem* items, int n, uint32_t* status,
                       hipStream_t st)
 {
@@ -360,6 +404,20 @@ hipError_t launch_init_rd(const GroupDev* groups, const ChainItem* items, int n,
 }
 
 }  // namespace
+
+hipError_t launch_chain_mixed(const GroupDev* groups, const ChainItem* items, int n, int L,
+                              uint32_t* status, hipStream_t st)
+{
+    if (n <= 0) return hipSuccess;
+    // register demand is the largest system's (three components)
+    switch (L) {
+    case 64: return launch_mixed_l<64, 8>(groups, items, n, status, st);
+    case 128: return launch_mixed_l<128, 8>(groups, items, n, status, st);
+    case 256: return launch_mixed_l<256, 4>(groups, items, n, status, st);
+    case 512: return launch_mixed_l<512, 4>(groups, items, n, status, st);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_chain(const GroupDev* groups, const ChainItem* items, int n, int rhs, int L,
                         uint32_t* status, hipStream_t st)

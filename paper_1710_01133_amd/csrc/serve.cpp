@@ -91,7 +91,6 @@ struct ServeState {
     std::vector<Request*> active;
     std::vector<int> free_slots;
     hipStream_t s0 = nullptr, s1 = nullptr;
-    hipStream_t cs[5] = {};       // chains of each right-hand side, beside one another
     GroupDev* groups_dev = nullptr;
     GroupDev* groups_host = nullptr;      // pinned staging, one entry per slot
     FarItem* far_dev = nullptr;           // [kRing][kMaxActive]
@@ -233,9 +232,7 @@ abm_status server_init(ServeState* S)
     if ((e = hipStreamCreateWithFlags(&S->s0, hipStreamNonBlocking)) != hipSuccess ||
         (e = hipStreamCreateWithFlags(&S->s1, hipStreamNonBlocking)) != hipSuccess)
         return hip_fail(e, "server streams");
-    for (auto& c : S->cs)
-        if ((e = hipStreamCreateWithFlags(&c, hipStreamNonBlocking)) != hipSuccess)
-            return hip_fail(e, "server streams");
+
     abm_status s;
     if ((s = dev_alloc((void**)&S->groups_dev, kMaxActive * sizeof(GroupDev), "group slots")) ||
         (s = dev_alloc((void**)&S->far_dev, (size_t)kRing * kMaxActive * sizeof(FarItem), "far ring")) ||
@@ -436,27 +433,19 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
             (e = launch_chain_init(S->groups_dev, id + isp[k].offset, isp[k].count, k, S->s0)) != hipSuccess)
             return hip_fail(e, "init launch");
     }
-    // chains of different right-hand sides are independent: with more than
-    // one, each runs on its own stream, forked from and joined back into s0
+    // chains of every right-hand side: one launch (one kernel switching per
+    // wave when the tick mixes systems), so they run side by side
     int nrhs = 0;
     for (int k = 0; k < 5; ++k) nrhs += csp[k].count ? 1 : 0;
-    hipEvent_t fork = nullptr;
     if (nrhs > 1) {
-        fork = pooled_event(S);
-        if ((e = hipEventRecord(fork, S->s0)) != hipSuccess) return hip_fail(e, "event");
-    }
-    for (int k = 0; k < 5; ++k) {
-        if (!csp[k].count) continue;
-        hipStream_t sk = nrhs > 1 ? S->cs[k] : S->s0;
-        if (nrhs > 1 && (e = hipStreamWaitEvent(sk, fork, 0)) != hipSuccess) return hip_fail(e, "wait");
-        if ((e = launch_chain(S->groups_dev, cd + csp[k].offset, csp[k].count, k, S->L, S->status,
-                              sk)) != hipSuccess)
+        if ((e = launch_chain_mixed(S->groups_dev, cd, nc, S->L, S->status, S->s0)) != hipSuccess)
             return hip_fail(e, "chain launch");
-        if (nrhs > 1) {
-            hipEvent_t join = pooled_event(S);
-            if ((e = hipEventRecord(join, sk)) != hipSuccess ||
-                (e = hipStreamWaitEvent(S->s0, join, 0)) != hipSuccess)
-                return hip_fail(e, "join");
+    } else {
+        for (int k = 0; k < 5; ++k) {
+            if (csp[k].count &&
+                (e = launch_chain(S->groups_dev, cd + csp[k].offset, csp[k].count, k, S->L, S->status,
+                                  S->s0)) != hipSuccess)
+                return hip_fail(e, "chain launch");
         }
     }
     // requests whose last block ran in this tick: copy the last state, mark done
@@ -582,8 +571,7 @@ void server_loop(ServeState* S)
     }
     (void)hipStreamSynchronize(S->s0);
     (void)hipStreamSynchronize(S->s1);
-    for (auto c : S->cs)
-        if (c) (void)hipStreamSynchronize(c);
+
 }
 
 }  // namespace
@@ -623,8 +611,7 @@ void serve_shutdown(abm_ctx* ctx)
     for (auto ev : S->ev_pool) (void)hipEventDestroy(ev);
     if (S->s0) (void)hipStreamDestroy(S->s0);
     if (S->s1) (void)hipStreamDestroy(S->s1);
-    for (auto c : S->cs)
-        if (c) (void)hipStreamDestroy(c);
+
     delete S;
     ctx->serve = nullptr;
 }
