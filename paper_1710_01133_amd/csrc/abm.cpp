@@ -342,10 +342,8 @@ abm_status plain_setup(abm_plan_s* pl)
     const int ch = plain_chunk();
     const int64_t nchunks = std::max<int64_t>(1, (p.N + ch - 1) / ch);   // indices 0..N-1
     const int nloc_max = plain_max_local_chunks(p.d);
-    int occ = 0;
     // co-residency bound: one workgroup per CU is always possible for this kernel
-    int gcap = std::min(pl->ctx->n_cu, 256);
-    (void)occ;
+    const int gcap = std::min(pl->ctx->n_cu, 256);
     const int gmin = (int)((nchunks + nloc_max - 1) / nloc_max);
     if (gmin > gcap)
         return fail(ABM_EINVAL, "N=%lld too long for the plain path (history does not fit the LDS of %d workgroups)",
