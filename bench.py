@@ -215,6 +215,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--tune-budget", type=float, default=20.0,
                     help="seconds for the autotuner to choose the blocking (0: library defaults)")
+    ap.add_argument("--blocking", default=None,
+                    help="L,kchunk,max_split: use this blocking instead of autotuning")
     ap.add_argument("--eager", action="store_true",
                     help="launch the batched solve eagerly instead of replaying its captured graph")
     args = ap.parse_args()
@@ -241,7 +243,10 @@ def main():
     # blocking chosen by the library's autotuner (whole solves of this sweep)
     tuning = None
     tune_report = None
-    if args.tune_budget > 0:
+    if args.blocking:
+        Lb, kb, sb = (int(x) for x in args.blocking.split(","))
+        tuning = {"block_L": Lb, "kchunk": kb, "max_split": sb, "column_tiles_only": 0}
+    elif args.tune_budget > 0:
         t0 = time.perf_counter()
         best, trials = abm.autotune(ctx, probs, out_stride=stride, budget_s=args.tune_budget)
         tuning = best
