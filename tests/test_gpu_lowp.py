@@ -90,3 +90,23 @@ def test_lowp_sweep_full_size(ctx, prec):
     assert max(errs.values()) <= BOUND[prec]
     allv = np.stack(outs)
     assert np.all(np.isfinite(allv)) and np.max(np.abs(allv)) < 10
+
+
+@pytest.mark.parametrize("blocking", [(256, 2048, 4), (512, 2048, 4), (128, 1024, 16)])
+def test_bf16x6_sweep_full_size_at_tuned_blockings(ctx, blocking):
+    """The full sweep in the default far precision at blockings the autotuner
+    chooses between (the first is the one the benchmark has been timing):
+    sampled members against the stored double oracle runs."""
+    L, kchunk, split = blocking
+    probs = inputs.duffing_sweep(far_prec="bf16x6")
+    tuning = dict(block_L=L, kchunk=kchunk, max_split=split, column_tiles_only=0)
+    plan = abm.Plan(ctx, probs, out_stride=1024, tuning=tuning)
+    assert plan.config() == tuning
+    ys = [abm.alloc_out(p, 1024) for p in probs]
+    abm.solve_batch(plan, probs, ys)
+    plan.check()
+    plan.close()
+    g = golden()
+    for i in (0, 1, 511, 1023):
+        err = normerr(ys[i].cpu().numpy(), np.array(g["duffing_sweep_%d" % i]["y"]))
+        assert err <= BOUND["bf16x6"], (blocking, i, err)
