@@ -190,9 +190,32 @@ def plain_leg(abm, torch, inputs, ctx):
     dt1 = time.perf_counter() - t1
     pp.check()
     pp.close()
-    return {"workload": "forced Duffing, alpha=0.9, h=1e-3, N=200000, d=2, one trajectory",
-            "seconds": dt1, "history_macs_per_s": p1.history_macs() / dt1,
-            "us_per_step": dt1 / p1.N * 1e6}
+    res = {"workload": "forced Duffing, alpha=0.9, h=1e-3, N=200000, d=2, one trajectory",
+           "seconds": dt1, "history_macs_per_s": p1.history_macs() / dt1,
+           "us_per_step": dt1 / p1.N * 1e6}
+    # the scalar linear test (D^0.8 y = -y, N = 8192): plain path and the
+    # blocked path on the same single trajectory (a narrow group)
+    p0 = inputs.linear_c()
+    pp = abm.Plan(ctx, [p0], out_stride=0)
+    y0 = abm.alloc_out(p0, 0)
+    times = {}
+    for mode in ("plain", "blocked"):
+        run = (lambda: abm.solve(pp, p0, y0)) if mode == "plain" else \
+              (lambda: abm.solve_batch(pp, [p0], [y0]))
+        run()
+        pp.check()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for _ in range(5):
+            run()
+        torch.cuda.synchronize()
+        times[mode] = (time.perf_counter() - t1) / 5
+        pp.check()
+    pp.close()
+    res["linear_test"] = {"workload": "D^0.8 y = -y, y0 = 1, h = 2^-10, N = 8192, one trajectory",
+                          "plain_us_per_step": times["plain"] / p0.N * 1e6,
+                          "blocked_us_per_step": times["blocked"] / p0.N * 1e6}
+    return res
 
 
 def main():

@@ -71,7 +71,8 @@ struct Request {
 
 }  // namespace
 
-constexpr int kServeMaxSplit = 16;  // far partial slices per request and block
+// far partial slices per request and block (ABM_SERVE_MAX_SPLIT overrides)
+int serve_max_split() { return std::max(1, std::min(256, env_int("ABM_SERVE_MAX_SPLIT", 16))); }
 
 struct ServeState {
     abm_ctx* ctx = nullptr;
@@ -84,7 +85,7 @@ struct ServeState {
     std::unordered_map<uint64_t, Request*> all;
     uint64_t next_ticket = 1;
     // owned by the server thread
-    int L = 256, kchunk = 2048, max_split = kServeMaxSplit;
+    int L = 256, kchunk = 2048, max_split = serve_max_split();
     char* arena = nullptr;
     size_t arena_cap = 0;
     std::map<size_t, size_t> free_list;   // offset -> size
@@ -634,7 +635,7 @@ abm_status abm_submit(abm_ctx* ctx, const abm_problem* prob, double* y_out, uint
     ServeState* S = ctx->serve;
     int L = 0, kchunk = 0;
     if ((s = serve_params(&L, &kchunk))) return s;
-    const ReqLayout lay = layout_of(*prob, L, kchunk, kServeMaxSplit);
+    const ReqLayout lay = layout_of(*prob, L, kchunk, S->max_split);
     if (lay.total > ctx->arena_bytes)
         return fail(ABM_ENOMEM, "request needs %zu bytes, the arena has %zu", lay.total,
                     ctx->arena_bytes);
@@ -668,7 +669,7 @@ abm_status abm_request_bytes(abm_ctx* ctx, const abm_problem* prob, size_t* byte
     if (s) return s;
     int L = 0, kchunk = 0;
     if ((s = serve_params(&L, &kchunk))) return s;
-    *bytes = layout_of(*prob, L, kchunk, kServeMaxSplit).total;
+    *bytes = layout_of(*prob, L, kchunk, ctx->serve ? ctx->serve->max_split : serve_max_split()).total;
     return ABM_OK;
 }
 
