@@ -218,6 +218,29 @@ def plain_leg(abm, torch, inputs, ctx):
     return res
 
 
+def long_leg(abm, torch, inputs, ctx):
+    """The paper's step counts (Table 1: 1e6 and 3e6 steps of one trajectory):
+    the forced fractional LCR circuit (alpha = 0.9, h = 0.01, f = 0.117) by the
+    blocked path, double far field."""
+    res = {"workload": "forced fractional LCR circuit, alpha=0.9, h=0.01, f=0.117, d=2, "
+                       "one trajectory, far field fp64",
+           "paper_bgp_seconds": {"1000000": 69.06, "3000000": 304.17}}
+    for N in (1000000, 3000000):
+        p = inputs.Problem("LCR", 0.9, 0.01, N, (0.1, 0.0), inputs.LCR_P + (0.117,))
+        plan = abm.Plan(ctx, [p], out_stride=0)
+        y = abm.alloc_out(p, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        abm.solve_batch(plan, [p], [y])
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        plan.check()
+        plan.close()
+        res[str(N)] = {"seconds": dt, "history_macs_per_s": p.history_macs() / dt,
+                       "us_per_step": dt / N * 1e6}
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,6 +259,8 @@ def main():
     ap.add_argument("--no-precisions", action="store_true",
                     help="skip the sweep at the other far-field precisions")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-long", action="store_true",
+                    help="skip the 1e6 / 3e6-step single-trajectory runs")
     ap.add_argument("--tune-budget", type=float, default=20.0,
                     help="seconds for the autotuner to choose the blocking (0: library defaults)")
     ap.add_argument("--blocking", default=None,
@@ -321,6 +346,7 @@ def main():
             "chain_ms_total": stt["chain_ms"], "far_ms_total": stt["far_ms"]}
 
     plain = None if args.no_plain else plain_leg(abm, torch, inputs, ctx)
+    longrun = None if args.no_long else long_leg(abm, torch, inputs, ctx)
     small = small_batch_leg(abm, torch, inputs, ctx)
 
     serve = None
@@ -372,6 +398,7 @@ def main():
                    "far_prec": args.prec, "launch": "eager" if args.eager else "graph"},
         "eager_ms_per_step": None if eager_dt is None else eager_dt * 1e3,
         "launch_bound_batch": small,
+        "long_trajectory": longrun,
         "max_rel_err_vs_oracle": max_err,
         "err_members": errs,
         "plan_seconds": plan_s,

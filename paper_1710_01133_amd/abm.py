@@ -6,7 +6,10 @@ binding refuses to work without the built library: there is no fallback.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import sys
+import weakref
 import os
 from typing import List, Optional, Sequence
 
@@ -59,6 +62,25 @@ class AbmTuneTrial(ctypes.Structure):
 
 def _tuning_dict(t: AbmTuning) -> dict:
     return {f: getattr(t, f) for f, _ in AbmTuning._fields_}
+
+
+# Handles still open when the interpreter exits are released before the HIP
+# runtime goes away (plans before their contexts); a finalizer running during
+# interpreter shutdown would call into a runtime that no longer exists.
+_live_plans = weakref.WeakSet()
+_live_contexts = weakref.WeakSet()
+
+
+def _close_all():
+    for group in (_live_plans, _live_contexts):
+        for obj in list(group):
+            try:
+                obj.close()
+            except Exception:
+                pass
+
+
+atexit.register(_close_all)
 
 
 class AbmError(RuntimeError):
@@ -158,6 +180,7 @@ class Context:
             stream = _current_stream_handle()
         _check(lib.abm_ctx_create(device, ctypes.c_void_p(stream), arena_bytes,
                                   ctypes.byref(self._h)), "abm_ctx_create")
+        _live_contexts.add(self)
 
     @property
     def handle(self):
@@ -169,6 +192,8 @@ class Context:
             self._h = ctypes.c_void_p()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:
@@ -192,6 +217,7 @@ class Plan:
             t = AbmTuning(**tuning)
             _check(lib.abm_plan_tuned(ctx.handle, arr, len(self.problems), ctypes.byref(t),
                                       ctypes.byref(self._h)), "abm_plan_tuned")
+        _live_plans.add(self)
 
     def config(self) -> dict:
         """The blocking the plan uses (block_L, kchunk, max_split, column_tiles_only)."""
@@ -231,6 +257,8 @@ class Plan:
             self._h = ctypes.c_void_p()
 
     def __del__(self):
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -47,6 +47,7 @@ struct Group {
     int64_t cols = 0;             // real columns
     int64_t ldF = 0;              // padded columns (narrow groups: real columns)
     bool narrow = false;          // far field by the blocked convolution
+    int split_cap = 0;            // narrow groups: most partial slices per block (0: the plan's)
     int64_t rows = 0;             // history rows allocated
     double* F = nullptr;
     float* F32 = nullptr;

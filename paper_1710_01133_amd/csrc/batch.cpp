@@ -226,7 +226,9 @@ void block_items(const Group& g, int gi, int64_t m, int L, int kchunk, int max_s
 int group_split_plan(const Group& g, int64_t kfar, int L, int kchunk, int max_split, int* nchunks,
                      int* chunks_per_split)
 {
-    if (g.narrow) return hankel_split_plan(kfar, L, max_split, nchunks, chunks_per_split);
+    if (g.narrow)
+        return hankel_split_plan(kfar, L, g.split_cap > 0 ? g.split_cap : max_split, nchunks,
+                                 chunks_per_split);
     return far_split_plan(kfar, kchunk, max_split, nchunks, chunks_per_split);
 }
 
@@ -234,7 +236,7 @@ int64_t group_far_split_max(const Group& g, int L, int kchunk, int max_split)
 {
     const int64_t nblocks = (g.nmax + L - 1) / L;
     const int64_t kfar_max = nblocks >= 2 ? (nblocks - 2) * L : 0;   // far(m) covers (m-1)L
-    if (g.narrow) return hankel_split_bound(kfar_max, L, max_split);
+    if (g.narrow) return hankel_split_bound(kfar_max, L, g.split_cap > 0 ? g.split_cap : max_split);
     return far_split_bound(kfar_max, kchunk, max_split);
 }
 
@@ -287,13 +289,23 @@ abm_status batch_setup(abm_plan_s* pl)
     }
     std::vector<GroupDev> gdev;
     int64_t ticks = 0;
+    int n_narrow = 0;
+    for (auto& g : pl->groups) {
+        g.cols = (int64_t)g.members.size() * g.d;
+        g.narrow = pl->allow_narrow && hankel_fits(g.prec, g.cols, L);
+        n_narrow += g.narrow ? 1 : 0;
+    }
+    // A narrow group's convolution is a few tiles wide, so its history is
+    // split over more workgroups: about 1024 in total over the narrow groups
+    // (a single long trajectory gets 256), never fewer than the plan's count.
+    const int narrow_split =
+        n_narrow ? std::max(pl->max_split, std::min(256, 1024 / n_narrow)) : pl->max_split;
     for (auto& g : pl->groups) {
         std::stable_sort(g.members.begin(), g.members.end(),
                          [&](int x, int y) { return pl->shape[x].N > pl->shape[y].N; });
         const int TN = far_tile_cols(L, g.prec);
         g.nmax = pl->shape[g.members[0]].N;
-        g.cols = (int64_t)g.members.size() * g.d;
-        g.narrow = pl->allow_narrow && hankel_fits(g.prec, g.cols, L);
+        if (g.narrow) g.split_cap = narrow_split;
         g.ldF = g.narrow ? g.cols : round_up(g.cols, TN);
         g.rows = g.nmax + 1 + L;
         g.col0.resize(g.members.size());

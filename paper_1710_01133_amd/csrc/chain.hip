@@ -171,11 +171,28 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
         const int64_t n = mL + r;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
+            // partial slices added in slice order; loaded 8 at a time so the
+            // loads are in flight together instead of waiting one by one
             double sp = 0.0, sc = 0.0;
-            for (int ch = 0; ch < A.nchunks; ++ch) {
-                const gptr<const double> pc = A.part + ((size_t)ch * A.ldP + T.col0 + i) * (2 * L);
-                sp += pc[r];
-                sc += pc[L + r];
+            const gptr<const double> pc0 = A.part + (size_t)(T.col0 + i) * (2 * L) + r;
+            const size_t sstride = (size_t)A.ldP * (2 * L);
+            int ch = 0;
+            for (; ch + 8 <= A.nchunks; ch += 8) {
+                double vp[8], vc[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    vp[u] = pc0[(ch + u) * sstride];
+                    vc[u] = pc0[(ch + u) * sstride + L];
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    sp += vp[u];
+                    sc += vc[u];
+                }
+            }
+            for (; ch < A.nchunks; ++ch) {
+                sp += pc0[ch * sstride];
+                sc += pc0[ch * sstride + L];
             }
             sp += A.b[n] * F0[i];
             sc += A.c[n] * F0[i];

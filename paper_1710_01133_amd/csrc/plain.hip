@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kCh = 256;          // history indices per chunk (= threads per workgroup)
 constexpr int kPartStride = 8;    // doubles per partial slot (2d <= 6 used)
+constexpr size_t kPlainLds = 160 * 1024 - 256;   // LDS of one gfx950 CU, less the static flag
 
 template <int R, int D>
 __global__ __launch_bounds__(256) void k_plain(PlainArgs A)
@@ -165,6 +166,8 @@ template <int R, int D>
 hipError_t launch_plain_t(const PlainArgs& A, hipStream_t st)
 {
     const size_t shmem = ((size_t)A.nloc * kCh * D + 4 * 2 * D) * sizeof(double);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_plain<R, D>), shmem);
+    if (e != hipSuccess) return e;
     PlainArgs a = A;
     void* args[] = {&a};
     return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plain<R, D>), dim3(A.G),
@@ -175,8 +178,8 @@ hipError_t launch_plain_t(const PlainArgs& A, hipStream_t st)
 
 int plain_max_local_chunks(int d)
 {
-    // dynamic LDS kept at or below 64 KiB
-    return (int)((65536 - 4 * 2 * d * sizeof(double)) / ((size_t)kCh * d * sizeof(double)));
+    // the CU's whole LDS (one workgroup per CU): history slice + wave partials
+    return (int)((kPlainLds - 4 * 2 * d * sizeof(double)) / ((size_t)kCh * d * sizeof(double)));
 }
 
 int plain_chunk() { return kCh; }
