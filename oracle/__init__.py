@@ -19,8 +19,8 @@ _SRC = os.path.join(_HERE, "abm_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 # right-hand side ids used by the oracle (its own numbering)
-RHS_LINEAR, RHS_DUFFING, RHS_LORENZ, RHS_POLY, RHS_LCR = 0, 1, 2, 3, 4
-RHS_DIM = {RHS_LINEAR: 1, RHS_DUFFING: 2, RHS_LORENZ: 3, RHS_POLY: 1, RHS_LCR: 2}
+RHS_LINEAR, RHS_DUFFING, RHS_LORENZ, RHS_POLY, RHS_LCR, RHS_DIAG = 0, 1, 2, 3, 4, 5
+RHS_DIM = {RHS_LINEAR: 1, RHS_DUFFING: 2, RHS_LORENZ: 3, RHS_POLY: 1, RHS_LCR: 2, RHS_DIAG: 2}
 
 _lib = None
 
@@ -54,16 +54,21 @@ def _load():
     lib.oracle_solve.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                  ctypes.c_int64, c_dp, c_dp, ctypes.c_int64, c_dp, ctypes.c_int]
     lib.oracle_solve.restype = ctypes.c_int
-    lib.oracle_steps_from_states.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                             ctypes.c_double, c_dp, c_dp, c_dp,
-                                             ctypes.POINTER(ctypes.c_int64), ctypes.c_int32, c_dp]
-    lib.oracle_steps_from_states.restype = ctypes.c_int
-    lib.oracle_solve_batch.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
-                                       ctypes.POINTER(ctypes.c_int32), c_dp, c_dp,
-                                       ctypes.POINTER(ctypes.c_int64), c_dp, c_dp, ctypes.c_int64,
-                                       ctypes.POINTER(c_dp), ctypes.POINTER(ctypes.c_int32),
-                                       ctypes.c_int]
-    lib.oracle_solve_batch.restype = ctypes.c_int
+    lib.oracle_solve_gen.argtypes = [ctypes.c_int, ctypes.c_int, c_dp, ctypes.c_double,
+                                     ctypes.c_int64, c_dp, c_dp, c_dp, ctypes.c_int64, c_dp,
+                                     ctypes.c_int]
+    lib.oracle_solve_gen.restype = ctypes.c_int
+    lib.oracle_steps_from_states_gen.argtypes = [ctypes.c_int, ctypes.c_int, c_dp,
+                                                 ctypes.c_double, c_dp, c_dp, c_dp, c_dp,
+                                                 ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                                 c_dp]
+    lib.oracle_steps_from_states_gen.restype = ctypes.c_int
+    lib.oracle_solve_batch_gen.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
+                                           ctypes.POINTER(ctypes.c_int32), c_dp, c_dp,
+                                           ctypes.POINTER(ctypes.c_int64), c_dp, c_dp, c_dp,
+                                           ctypes.c_int64, ctypes.POINTER(c_dp),
+                                           ctypes.POINTER(ctypes.c_int32), ctypes.c_int]
+    lib.oracle_solve_batch_gen.restype = ctypes.c_int
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -105,61 +110,91 @@ def _params(rhs, d, x0, p):
     return x, pp
 
 
-def solve(rhs: int, alpha: float, h: float, N: int, x0, p, out_stride: int = 1,
-          compensated: bool = False) -> np.ndarray:
-    """One trajectory; returns the written states as an (n_out, d) array."""
+def _orders(alpha, d, x1):
+    """Per-component orders (a scalar means one order for all components)
+    and the initial first derivative (zeros when not given)."""
+    al = np.zeros(4, np.float64)
+    a = np.asarray(alpha, np.float64).ravel()
+    if a.size == 1:
+        al[:d] = a[0]
+    elif a.size == d:
+        al[:d] = a
+    else:
+        raise ValueError("alpha must be a scalar or one value per component")
+    v = np.zeros(4, np.float64)
+    if x1 is not None:
+        x1 = np.asarray(x1, np.float64).ravel()
+        if x1.size != d:
+            raise ValueError("bad x1 size")
+        v[:d] = x1
+    return al, v
+
+
+def solve(rhs: int, alpha, h: float, N: int, x0, p, out_stride: int = 1,
+          compensated: bool = False, x1=None) -> np.ndarray:
+    """One trajectory; returns the written states as an (n_out, d) array.
+    alpha: one order, or one per component (incommensurate system), each in
+    (0, 2]; x1: y'(0), used by components of order above 1."""
     lib = _load()
     d = RHS_DIM[rhs]
     x, pp = _params(rhs, d, x0, p)
+    al, v = _orders(alpha, d, x1)
     y = np.zeros((n_out(N, out_stride), d), np.float64)
-    rc = lib.oracle_solve(rhs, d, float(alpha), float(h), int(N), _dp(x), _dp(pp),
-                          int(out_stride), _dp(y), 1 if compensated else 0)
+    rc = lib.oracle_solve_gen(rhs, d, _dp(al), float(h), int(N), _dp(x), _dp(v), _dp(pp),
+                              int(out_stride), _dp(y), 1 if compensated else 0)
     if rc != 0:
         raise ValueError("oracle_solve failed: %d" % rc)
     return y
 
 
-def steps_from_states(rhs: int, alpha: float, h: float, x0, p, y_hist: np.ndarray,
-                      s_list) -> np.ndarray:
+def steps_from_states(rhs: int, alpha, h: float, x0, p, y_hist: np.ndarray,
+                      s_list, x1=None) -> np.ndarray:
     """y_s recomputed for each s in s_list from the given states y_0..y_{s-1}."""
     lib = _load()
     d = RHS_DIM[rhs]
     x, pp = _params(rhs, d, x0, p)
+    al, v = _orders(alpha, d, x1)
     s_arr = np.ascontiguousarray(np.asarray(s_list, np.int64))
     yh = np.ascontiguousarray(np.asarray(y_hist, np.float64).reshape(-1, d))
     if s_arr.size and (s_arr.min() < 1 or s_arr.max() > yh.shape[0]):
         raise ValueError("s out of range of the given history")
     out = np.zeros((s_arr.size, d), np.float64)
-    rc = lib.oracle_steps_from_states(rhs, d, float(alpha), float(h), _dp(x), _dp(pp), _dp(yh),
-                                      s_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                      int(s_arr.size), _dp(out))
+    rc = lib.oracle_steps_from_states_gen(rhs, d, _dp(al), float(h), _dp(x), _dp(v), _dp(pp),
+                                          _dp(yh),
+                                          s_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                          int(s_arr.size), _dp(out))
     if rc != 0:
         raise ValueError("oracle_steps_from_states failed: %d" % rc)
     return out
 
 
-def solve_batch(rhs, alpha, h, N, x0, p, out_stride: int = 0, compensated: bool = False):
+def solve_batch(rhs, alpha, h, N, x0, p, out_stride: int = 0, compensated: bool = False,
+                x1=None):
     """Many independent trajectories (OpenMP over trajectories).  Every argument
-    is per trajectory (sequence of length B); returns a list of (n_out, d) arrays."""
+    is per trajectory (sequence of length B; alpha[i] a scalar or one order per
+    component, x1[i] or None); returns a list of (n_out, d) arrays."""
     lib = _load()
     B = len(rhs)
     rhs_a = np.asarray(rhs, np.int32)
     d_a = np.asarray([RHS_DIM[int(r)] for r in rhs_a], np.int32)
-    al = np.asarray(alpha, np.float64)
     hh = np.asarray(h, np.float64)
     NN = np.asarray(N, np.int64)
     xs = np.zeros((B, 4), np.float64)
+    vs = np.zeros((B, 4), np.float64)
+    als = np.zeros((B, 4), np.float64)
     ps = np.zeros((B, 8), np.float64)
     for i in range(B):
         xs[i], ps[i] = _params(int(rhs_a[i]), int(d_a[i]), x0[i], p[i])
+        als[i], vs[i] = _orders(alpha[i], int(d_a[i]), None if x1 is None else x1[i])
     outs = [np.zeros((n_out(int(NN[i]), out_stride), int(d_a[i])), np.float64) for i in range(B)]
     ptrs = (ctypes.POINTER(ctypes.c_double) * max(B, 1))(*[_dp(o) for o in outs])
     st = np.zeros(B, np.int32)
     i32 = ctypes.POINTER(ctypes.c_int32)
-    rc = lib.oracle_solve_batch(B, rhs_a.ctypes.data_as(i32), d_a.ctypes.data_as(i32), _dp(al),
-                                _dp(hh), NN.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                _dp(xs), _dp(ps), int(out_stride), ptrs, st.ctypes.data_as(i32),
-                                1 if compensated else 0)
+    rc = lib.oracle_solve_batch_gen(B, rhs_a.ctypes.data_as(i32), d_a.ctypes.data_as(i32),
+                                    _dp(als), _dp(hh),
+                                    NN.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _dp(xs),
+                                    _dp(vs), _dp(ps), int(out_stride), ptrs,
+                                    st.ctypes.data_as(i32), 1 if compensated else 0)
     if rc != 0:
         raise ValueError("oracle_solve_batch failed: %s" % st)
     return outs

@@ -10,10 +10,13 @@
  * shares no code, header, table or constant with the GPU library.
  *
  * What it computes (Section 2, "Preliminaries"):
- *   problem      D^alpha y = f(t, y), y(0) = x0, 0 < alpha <= 1   (eq. fde)
+ *   problem      D^alpha y = f(t, y), y(0) = x0, and y'(0) = x1 when
+ *                1 < alpha <= 2 (the ceil(alpha) initial values of eq. fde)
  *   grid         t_n = n h, f_n = f(t_n, y_n) with the corrected y_n
- *   predictor    yP_{n+1} = x0 + h^alpha * sum_{k=0..n} b_{n-k} f_k      (eq. abm)
- *   corrector    y_{n+1}  = x0 + h^alpha * ( c_n f_0 + sum_{k=1..n} a_{n-k} f_k
+ *   start term   T(t) = x0 (alpha <= 1),  x0 + t x1 (1 < alpha <= 2): the
+ *                Taylor sum over k < ceil(alpha) in eq. abm
+ *   predictor    yP_{n+1} = T(t_{n+1}) + h^alpha * sum_{k=0..n} b_{n-k} f_k      (eq. abm)
+ *   corrector    y_{n+1}  = T(t_{n+1}) + h^alpha * ( c_n f_0 + sum_{k=1..n} a_{n-k} f_k
  *                                            + f(t_{n+1}, yP_{n+1}) / Gamma(alpha+2) )
  *   weights      b_n = ((n+1)^alpha - n^alpha) / Gamma(alpha+1)
  *                a_n = ((n+2)^(alpha+1) - 2 (n+1)^(alpha+1) + n^(alpha+1)) / Gamma(alpha+2)
@@ -23,7 +26,10 @@
  *     rule it comes from needs "-" (the tests pin this by quadrature and by
  *     the telescoping sum of b).
  *   - exactly one corrector evaluation per step (PECE), f_n uses corrected y_n.
- *   - systems are treated component-wise with one alpha for all components.
+ *   - systems are treated component by component; an incommensurate system
+ *     (eq. sys.LRC with alpha_1 != alpha_2) applies to component i the
+ *     scalar scheme of order alpha_i: its own weights, h^alpha_i,
+ *     Gamma(alpha_i + 2) and start term, with f evaluated on the whole state.
  *
  * Arithmetic: the weights are evaluated from the literal formulas in
  * __float128 (113-bit significand), so the cancellation inside the
@@ -37,9 +43,11 @@
  *   1 DUFFING  f = (y2, -delta y2 - y1 - y1^3 + A cos(omega t))   p = {delta, A, omega}
  *   2 LORENZ   f = (s(y2-y1), y1(r-y3)-y2, y1 y2 - b y3)          p = {s, r, b}
  *   3 POLY     f = c0 + c1 t (each component)            p = {c0, c1}
- *   4 LCR      f = (y2 - g(y1), -sigma y2 - y1 + F sin(omega t))  (eq. sys.LRC,
- *              one common order)   p = {sigma, omega, a, b, F}
+ *   4 LCR      f = (y2 - g(y1), -sigma y2 - y1 + F sin(omega t))  (eq. sys.LRC)
+ *              p = {sigma, omega, a, b, F}
  *              g(x) = b x - a + b (x <= -1), a x (|x| < 1), b x + a - b (x >= 1)
+ *   5 DIAG     f = (-l1 y1 + m1, -l2 y2 + m2): two uncoupled scalar equations,
+ *              a test system for per-component orders   p = {l1, l2, m1, m2}
  */
 #include <math.h>
 #include <quadmath.h>
@@ -59,6 +67,7 @@ static int rhs_dim(int rhs)
     case 2: return 3;
     case 3: return 1;
     case 4: return 2;
+    case 5: return 2;
     default: return -1;
     }
 }
@@ -94,7 +103,17 @@ static void rhs_eval(int rhs, const double *p, double t, const double *y, double
         f[1] = -p[0] * y[1] - y[0] + p[4] * sin(p[1] * t);
         break;
     }
+    case 5:
+        f[0] = -p[0] * y[0] + p[2];
+        f[1] = -p[1] * y[1] + p[3];
+        break;
     }
+}
+
+/* Orders accepted: 0 < alpha <= 2 (at most one initial derivative). */
+static int order_ok(double alpha)
+{
+    return alpha > 0.0 && alpha <= 2.0;
 }
 
 /*
@@ -105,7 +124,7 @@ static void rhs_eval(int rhs, const double *p, double t, const double *y, double
  */
 int oracle_weights_at(double alpha, int64_t k0, int64_t n, double *b, double *a, double *c)
 {
-    if (!(alpha > 0.0 && alpha <= 1.0) || n < 0 || k0 < 0)
+    if (!order_ok(alpha) || n < 0 || k0 < 0)
         return ORC_EINVAL;
     const __float128 al = (__float128)alpha;
     const __float128 g1 = (__float128)tgamma(alpha + 1.0);
@@ -154,39 +173,94 @@ static double hist_sum(const double *w, const double *F, int d, int comp_idx,
     return s + e;
 }
 
+/* Weight tables and scalar factors of one component of order alpha. */
+struct comp_tables {
+    double *b, *a, *c;
+    double ha, g2;
+};
+
+static void free_tables(struct comp_tables *T, int d)
+{
+    for (int i = 0; i < d; ++i) {
+        free(T[i].b);
+        free(T[i].a);
+        free(T[i].c);
+        T[i].b = T[i].a = T[i].c = NULL;
+    }
+}
+
+/* Tables for n indices of every component (orders alphas[0..d-1]). */
+static int make_tables(struct comp_tables *T, int d, const double *alphas, double h, int64_t n)
+{
+    for (int i = 0; i < d; ++i)
+        T[i].b = T[i].a = T[i].c = NULL;
+    for (int i = 0; i < d; ++i) {
+        T[i].b = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        T[i].a = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        T[i].c = malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+        if (!T[i].b || !T[i].a || !T[i].c) {
+            free_tables(T, d);
+            return ORC_ENOMEM;
+        }
+        int rc = oracle_weights(alphas[i], n, T[i].b, T[i].a, T[i].c);
+        if (rc != ORC_OK) {
+            free_tables(T, d);
+            return rc;
+        }
+        T[i].ha = pow(h, alphas[i]);
+        T[i].g2 = tgamma(alphas[i] + 2.0);
+    }
+    return ORC_OK;
+}
+
+/* Start term of component i at time t (the Taylor sum of eq. abm). */
+static double start_term(double alpha, double x0, const double *x1, int i, double t)
+{
+    return alpha > 1.0 ? x0 + t * x1[i] : x0;
+}
+
+static int orders_ok(int d, const double *alphas)
+{
+    for (int i = 0; i < d; ++i)
+        if (!order_ok(alphas[i]))
+            return 0;
+    return 1;
+}
+
 /*
- * One trajectory of the fractional ABM scheme.
+ * One trajectory of the fractional ABM scheme, general form.
  *   rhs, p      right-hand side and its parameters (table above)
  *   d           state dimension (must equal the dimension of rhs)
- *   alpha, h, N order, step size, number of steps
+ *   alphas      order of each component (d values, each in (0, 2]); equal
+ *               values give the commensurate scheme
+ *   h, N        step size, number of steps
  *   x0          initial state, d doubles
+ *   x1          initial first derivative, d doubles, read only for components
+ *               of order above 1 (may be NULL when there are none)
  *   out_stride  0: write only y_N;  k>0: write y_s for s = 0, k, 2k, ... and y_N
  *   y_out       d doubles per written state, in that order
  *   comp        0: plain ascending sums; 1: Neumaier-compensated sums
  * Returns 0, or a negative code for invalid arguments / allocation failure.
  */
-int oracle_solve(int rhs, int d, double alpha, double h, int64_t N,
-                 const double *x0, const double *p, int64_t out_stride,
-                 double *y_out, int comp)
+int oracle_solve_gen(int rhs, int d, const double *alphas, double h, int64_t N,
+                     const double *x0, const double *x1, const double *p, int64_t out_stride,
+                     double *y_out, int comp)
 {
-    if (rhs_dim(rhs) != d || !(alpha > 0.0 && alpha <= 1.0) || !(h > 0.0) ||
+    if (rhs_dim(rhs) != d || !alphas || !orders_ok(d, alphas) || !(h > 0.0) ||
         !isfinite(h) || N < 1 || out_stride < 0 || !x0 || !p || !y_out)
         return ORC_EINVAL;
-    double *b = malloc(sizeof(double) * (size_t)N);
-    double *a = malloc(sizeof(double) * (size_t)N);
-    double *c = malloc(sizeof(double) * (size_t)N);
+    for (int i = 0; i < d; ++i)
+        if (alphas[i] > 1.0 && !x1)
+            return ORC_EINVAL;
+    struct comp_tables T[8];
     double *F = malloc(sizeof(double) * (size_t)(N + 1) * (size_t)d);
-    if (!b || !a || !c || !F) {
-        free(b); free(a); free(c); free(F);
+    if (!F)
         return ORC_ENOMEM;
-    }
-    int rc = oracle_weights(alpha, N, b, a, c);
+    int rc = make_tables(T, d, alphas, h, N);
     if (rc != ORC_OK) {
-        free(b); free(a); free(c); free(F);
+        free(F);
         return rc;
     }
-    const double ha = pow(h, alpha);
-    const double g2 = tgamma(alpha + 2.0);
     double y[8], yp[8], fp[8], P[8], C[8];
 
     rhs_eval(rhs, p, 0.0, x0, F);   /* F_0 = f(t_0, y_0) */
@@ -199,15 +273,15 @@ int oracle_solve(int rhs, int d, double alpha, double h, int64_t N,
         const int64_t n = s - 1;
         const double t = (double)s * h;
         for (int i = 0; i < d; ++i)
-            P[i] = hist_sum(b, F, d, i, 0, n, comp);
+            P[i] = hist_sum(T[i].b, F, d, i, 0, n, comp);
         for (int i = 0; i < d; ++i)
-            yp[i] = x0[i] + ha * P[i];
+            yp[i] = start_term(alphas[i], x0[i], x1, i, t) + T[i].ha * P[i];
         rhs_eval(rhs, p, t, yp, fp);
         for (int i = 0; i < d; ++i) {
             /* c_n f_0 first, then the a-weighted sum over k = 1..n */
-            double hs = hist_sum(a, F, d, i, 1, n, comp);
-            C[i] = c[n] * F[i] + hs;
-            y[i] = x0[i] + ha * (C[i] + fp[i] / g2);
+            double hs = hist_sum(T[i].a, F, d, i, 1, n, comp);
+            C[i] = T[i].c[n] * F[i] + hs;
+            y[i] = start_term(alphas[i], x0[i], x1, i, t) + T[i].ha * (C[i] + fp[i] / T[i].g2);
         }
         rhs_eval(rhs, p, t, y, F + s * d);
         if (out_stride > 0 && (s % out_stride == 0 || s == N)) {
@@ -217,8 +291,23 @@ int oracle_solve(int rhs, int d, double alpha, double h, int64_t N,
     }
     if (out_stride == 0)
         memcpy(y_out, y, sizeof(double) * (size_t)d);
-    free(b); free(a); free(c); free(F);
+    free_tables(T, d);
+    free(F);
     return ORC_OK;
+}
+
+/* One trajectory with one order for every component and no initial
+ * derivative (0 < alpha <= 1, or alpha <= 2 with y'(0) = 0). */
+int oracle_solve(int rhs, int d, double alpha, double h, int64_t N,
+                 const double *x0, const double *p, int64_t out_stride,
+                 double *y_out, int comp)
+{
+    if (rhs_dim(rhs) != d || !(alpha > 0.0 && alpha <= 1.0))
+        return ORC_EINVAL;
+    double al[8];
+    for (int i = 0; i < d; ++i)
+        al[i] = alpha;
+    return oracle_solve_gen(rhs, d, al, h, N, x0, NULL, p, out_stride, y_out, comp);
 }
 
 /*
@@ -226,14 +315,18 @@ int oracle_solve(int rhs, int d, double alpha, double h, int64_t N,
  * a long run one by one.  y_hist holds y_0 .. y_{smax-1} (d doubles each,
  * smax = max over s_list); for every s in s_list the oracle forms
  * F_k = f(t_k, y_hist_k) for k < s and applies one predictor-corrector step
- * (the same formulas as oracle_solve), writing y_s to y_out + i*d.
+ * (the same formulas as oracle_solve_gen), writing y_s to y_out + i*d.
  */
-int oracle_steps_from_states(int rhs, int d, double alpha, double h, const double *x0,
-                             const double *p, const double *y_hist, const int64_t *s_list,
-                             int32_t ns, double *y_out)
+int oracle_steps_from_states_gen(int rhs, int d, const double *alphas, double h,
+                                 const double *x0, const double *x1, const double *p,
+                                 const double *y_hist, const int64_t *s_list, int32_t ns,
+                                 double *y_out)
 {
-    if (rhs_dim(rhs) != d || !(alpha > 0.0 && alpha <= 1.0) || !(h > 0.0) || ns < 0)
+    if (rhs_dim(rhs) != d || !alphas || !orders_ok(d, alphas) || !(h > 0.0) || ns < 0)
         return ORC_EINVAL;
+    for (int i = 0; i < d; ++i)
+        if (alphas[i] > 1.0 && !x1)
+            return ORC_EINVAL;
     int64_t smax = 0;
     for (int32_t i = 0; i < ns; ++i) {
         if (s_list[i] < 1)
@@ -243,54 +336,69 @@ int oracle_steps_from_states(int rhs, int d, double alpha, double h, const doubl
     }
     if (smax == 0)
         return ORC_OK;
-    double *b = malloc(sizeof(double) * (size_t)smax);
-    double *a = malloc(sizeof(double) * (size_t)smax);
-    double *c = malloc(sizeof(double) * (size_t)smax);
+    struct comp_tables T[8];
     double *F = malloc(sizeof(double) * (size_t)smax * (size_t)d);
-    if (!b || !a || !c || !F) {
-        free(b); free(a); free(c); free(F);
+    if (!F)
         return ORC_ENOMEM;
+    int rc = make_tables(T, d, alphas, h, smax);
+    if (rc != ORC_OK) {
+        free(F);
+        return rc;
     }
-    oracle_weights(alpha, smax, b, a, c);
     for (int64_t k = 0; k < smax; ++k)
         rhs_eval(rhs, p, (double)k * h, y_hist + k * d, F + k * d);
-    const double ha = pow(h, alpha);
-    const double g2 = tgamma(alpha + 2.0);
     double yp[8], fp[8];
     for (int32_t j = 0; j < ns; ++j) {
         const int64_t s = s_list[j], n = s - 1;
         const double t = (double)s * h;
         for (int i = 0; i < d; ++i)
-            yp[i] = x0[i] + ha * hist_sum(b, F, d, i, 0, n, 0);
+            yp[i] = start_term(alphas[i], x0[i], x1, i, t) +
+                    T[i].ha * hist_sum(T[i].b, F, d, i, 0, n, 0);
         rhs_eval(rhs, p, t, yp, fp);
         for (int i = 0; i < d; ++i) {
-            double hs = hist_sum(a, F, d, i, 1, n, 0);
-            y_out[j * d + i] = x0[i] + ha * ((c[n] * F[i] + hs) + fp[i] / g2);
+            double hs = hist_sum(T[i].a, F, d, i, 1, n, 0);
+            y_out[j * d + i] = start_term(alphas[i], x0[i], x1, i, t) +
+                               T[i].ha * ((T[i].c[n] * F[i] + hs) + fp[i] / T[i].g2);
         }
     }
-    free(b); free(a); free(c); free(F);
+    free_tables(T, d);
+    free(F);
     return ORC_OK;
+}
+
+int oracle_steps_from_states(int rhs, int d, double alpha, double h, const double *x0,
+                             const double *p, const double *y_hist, const int64_t *s_list,
+                             int32_t ns, double *y_out)
+{
+    if (rhs_dim(rhs) != d || !(alpha > 0.0 && alpha <= 1.0))
+        return ORC_EINVAL;
+    double al[8];
+    for (int i = 0; i < d; ++i)
+        al[i] = alpha;
+    return oracle_steps_from_states_gen(rhs, d, al, h, x0, NULL, p, y_hist, s_list, ns, y_out);
 }
 
 /*
  * A batch of independent trajectories, one per entry, run in parallel over
  * trajectories with OpenMP (each trajectory is the single-trajectory scheme
- * above, unchanged).  Arrays are per trajectory: rhs[i], d[i], alpha[i], h[i],
- * N[i], x0[i*4 ...], p[i*8 ...]; y_out[i] points at that trajectory's output.
- * status[i] receives each trajectory's return code.
+ * above, unchanged).  Arrays are per trajectory: rhs[i], d[i], h[i], N[i],
+ * alphas[i*4 ...] (order of each component), x0[i*4 ...], x1[i*4 ...],
+ * p[i*8 ...]; y_out[i] points at that trajectory's output.  status[i]
+ * receives each trajectory's return code.
  */
-int oracle_solve_batch(int32_t B, const int32_t *rhs, const int32_t *d,
-                       const double *alpha, const double *h, const int64_t *N,
-                       const double *x0, const double *p, int64_t out_stride,
-                       double *const *y_out, int32_t *status, int comp)
+int oracle_solve_batch_gen(int32_t B, const int32_t *rhs, const int32_t *d,
+                           const double *alphas, const double *h, const int64_t *N,
+                           const double *x0, const double *x1, const double *p,
+                           int64_t out_stride, double *const *y_out, int32_t *status, int comp)
 {
     if (B < 0)
         return ORC_EINVAL;
     int bad = 0;
 #pragma omp parallel for schedule(dynamic, 1) reduction(| : bad)
     for (int32_t i = 0; i < B; ++i) {
-        status[i] = oracle_solve(rhs[i], d[i], alpha[i], h[i], N[i], x0 + 4 * (size_t)i,
-                                 p + 8 * (size_t)i, out_stride, y_out[i], comp);
+        status[i] = oracle_solve_gen(rhs[i], d[i], alphas + 4 * (size_t)i, h[i], N[i],
+                                     x0 + 4 * (size_t)i, x1 + 4 * (size_t)i, p + 8 * (size_t)i,
+                                     out_stride, y_out[i], comp);
         bad |= (status[i] != ORC_OK);
     }
     return bad ? ORC_EINVAL : ORC_OK;

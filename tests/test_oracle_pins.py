@@ -9,6 +9,11 @@ Each test would fail under a plausible slip in the oracle:
   * alpha = 1 two-term recurrence                             (predictor/corrector coupling)
   * 50-digit brute force on tiny N, weights by quadrature     (every step, every rhs)
   * equilibrium invariance                                     (rhs formulas, spurious history terms)
+  * per-component orders: uncoupled components equal scalar runs, closed
+    forms per component, brute force with one order per component
+                                                               (order / weight table of the wrong component)
+  * orders in (1, 2]: the start term x0 + t x1 of eq. abm by closed forms,
+    Mittag-Leffler / harmonic-oscillator convergence, alpha = 2 weights exact
 """
 import math
 
@@ -57,7 +62,7 @@ def _kq(al, g, v0, v1):
     return mp.quad(lambda w: g(w ** inv), [mp.mpf(v0) ** al, mp.mpf(v1) ** al]) / al
 
 
-@pytest.mark.parametrize("alpha", [0.3, 0.8, 0.95, 1.0])
+@pytest.mark.parametrize("alpha", [0.3, 0.8, 0.95, 1.0, 1.4, 2.0])
 def test_weights_match_quadrature(alpha):
     nmax = 4
     b, a, c = O.weights(alpha, nmax + 1)
@@ -85,7 +90,7 @@ def test_printed_plus_sign_of_b_is_not_the_rule():
 
 
 @pytest.mark.parametrize("alpha,k0", [(0.8, 65536), (0.9, 262144), (0.95, 3_000_000),
-                                      (0.5, 1_000_000)])
+                                      (0.5, 1_000_000), (1.5, 1_000_000), (1.9, 65536)])
 def test_weights_large_index_50_digits(alpha, k0):
     """Cancellation in the differences of powers grows like k^2; the oracle's
     quad evaluation must still be within a few ulp of a 50-digit value."""
@@ -105,7 +110,7 @@ def test_weights_large_index_50_digits(alpha, k0):
             assert c[i] == pytest.approx(float(cc), rel=8e-16)
 
 
-@pytest.mark.parametrize("alpha", [0.2, 0.55, 0.8, 0.9, 0.99, 1.0])
+@pytest.mark.parametrize("alpha", [0.2, 0.55, 0.8, 0.9, 0.99, 1.0, 1.3, 1.75, 2.0])
 def test_weight_sums_telescope(alpha):
     """Both quadrature rules integrate f == 1 exactly:
        sum_{k=0..n} b_k                        = (n+1)^alpha / Gamma(alpha+1)
@@ -128,6 +133,17 @@ def test_alpha_one_weights_exact():
     assert np.all(a == 1.0)
     assert np.all(c[1:] == 0.5)
     assert c[0] == 0.5  # c_0 = alpha / Gamma(alpha+2) = 1/2
+
+
+def test_alpha_two_weights_exact():
+    """At alpha = 2 the differences of powers are polynomials in k:
+    b_k = (2k+1)/2, a_k = (6k+6)/6 = k+1, c_k = (3k+2)/6 (c_0 = 2/6)."""
+    n = 4000
+    b, a, c = O.weights(2.0, n)
+    k = np.arange(n, dtype=np.float64)
+    assert np.array_equal(b, (2 * k + 1) / 2)
+    assert np.array_equal(a, k + 1)
+    assert np.max(np.abs(c - (3 * k + 2) / 6) / ((3 * k + 2) / 6)) <= 2.3e-16
 
 
 # ---------------------------------------------------------------- whole scheme
@@ -251,39 +267,58 @@ def _rhs_mp(name, p):
                 return p[3] * x + p[2] - p[3]
             return p[2] * x
         return lambda t, y: [y[1] - g(y[0]), -p[0] * y[1] - y[0] + p[4] * mp.sin(p[1] * t)]
+    if name == "DIAG":
+        return lambda t, y: [-p[0] * y[0] + p[2], -p[1] * y[1] + p[3]]
     raise KeyError(name)
 
 
-def _brute_force(name, alpha, h, N, x0, p):
+def _quad_rules(al, n):
+    """Product-rectangle and product-trapezoid weights of step n+1 for order
+    al by quadrature (v = t_{n+1}/h - u, kernel v^(al-1), node j at v = n+1-j)."""
+    ga = mp.gamma(al)
+    pw = [_kq(al, lambda v: 1, n - j, n + 1 - j) / ga for j in range(n + 1)]
+    cw = []
+    for j in range(n + 2):
+        vj = n + 1 - j
+        tot = mp.mpf(0)
+        if j >= 1:
+            tot += _kq(al, lambda v: vj + 1 - v, vj, vj + 1)
+        if j <= n:
+            tot += _kq(al, lambda v: v - (vj - 1), vj - 1, vj)
+        cw.append(tot / ga)
+    return pw, cw
+
+
+def _brute_force(name, alpha, h, N, x0, p, x1=None):
     """50-digit ABM for tiny N with weights from quadrature of the
-    product-integration rules (no closed-form weight is used)."""
+    product-integration rules (no closed-form weight is used).  alpha is one
+    order or one per component; components of order above 1 start from
+    x0 + t x1 (the Taylor sum over the ceil(alpha) initial values)."""
+    d = len(x0)
+    alphas = list(alpha) if np.ndim(alpha) else [alpha] * d
     with mp.workdps(50):
-        al = mp.mpf(alpha)
+        als = [mp.mpf(a) for a in alphas]
         hh = mp.mpf(h)
         fn = _rhs_mp(name, [mp.mpf(v) for v in p])
         x0m = [mp.mpf(v) for v in x0]
-        d = len(x0)
-        ha = hh ** al
-        ga = mp.gamma(al)
+        x1m = [mp.mpf(v) for v in (x1 if x1 is not None else [0.0] * d)]
+        ha = [hh ** al for al in als]
         F = [fn(mp.mpf(0), x0m)]
         ys = [x0m]
         for n in range(N):
-            # v = t_{n+1}/h - u, kernel v^(alpha-1), node j at v = n+1-j
-            pw = [_kq(al, lambda v: 1, n - j, n + 1 - j) / ga for j in range(n + 1)]
-            cw = []
-            for j in range(n + 2):
-                vj = n + 1 - j
-                tot = mp.mpf(0)
-                if j >= 1:
-                    tot += _kq(al, lambda v: vj + 1 - v, vj, vj + 1)
-                if j <= n:
-                    tot += _kq(al, lambda v: v - (vj - 1), vj - 1, vj)
-                cw.append(tot / ga)
+            rules = {}
+            for al in set(als):
+                rules[al] = _quad_rules(al, n)
             t1 = (n + 1) * hh
-            yP = [x0m[i] + ha * mp.fsum(pw[j] * F[j][i] for j in range(n + 1)) for i in range(d)]
-            fP = fn(t1, yP)
-            y1 = [x0m[i] + ha * (mp.fsum(cw[j] * F[j][i] for j in range(n + 1)) + cw[n + 1] * fP[i])
+            T = [x0m[i] + (t1 * x1m[i] if alphas[i] > 1 else 0) for i in range(d)]
+            yP = [T[i] + ha[i] * mp.fsum(rules[als[i]][0][j] * F[j][i] for j in range(n + 1))
                   for i in range(d)]
+            fP = fn(t1, yP)
+            y1 = []
+            for i in range(d):
+                cw = rules[als[i]][1]
+                y1.append(T[i] + ha[i] * (mp.fsum(cw[j] * F[j][i] for j in range(n + 1))
+                                          + cw[n + 1] * fP[i]))
             ys.append(y1)
             F.append(fn(t1, y1))
         return np.array([[float(v) for v in y] for y in ys])
@@ -304,6 +339,101 @@ def test_tiny_n_brute_force(name, alpha, h, x0, p):
     assert np.max(np.abs(y - ref)) <= 2e-15 * max(1.0, np.max(np.abs(ref)))
 
 
+_RID = {"LINEAR": O.RHS_LINEAR, "DUFFING": O.RHS_DUFFING, "LORENZ": O.RHS_LORENZ,
+        "LCR": O.RHS_LCR, "DIAG": O.RHS_DIAG}
+
+
+@pytest.mark.parametrize("name,alpha,h,x0,x1,p", [
+    # incommensurate orders (eq. sys.LRC with alpha_1 != alpha_2)
+    ("LCR", (0.9, 0.8), 0.25, [1.2, -0.4], None, [1.015, 0.55, -1.02, -0.58, 0.117]),
+    ("LORENZ", (0.95, 0.9, 0.85), 0.01, [1.0, 1.0, 1.0], None, [10.0, 28.0, 8.0 / 3.0]),
+    ("DIAG", (0.6, 0.95), 0.1, [1.0, -0.5], None, [1.3, 0.7, 0.2, -0.1]),
+    # orders above 1: start term x0 + t x1
+    ("LINEAR", 1.5, 0.125, [1.0], [0.5], [1.3]),
+    ("DUFFING", (1.3, 0.9), 0.05, [0.1, 0.0], [0.4, 0.0], [0.1, 0.3, 1.2]),
+    ("DIAG", (2.0, 1.7), 0.1, [1.0, 0.0], [0.0, 1.0], [1.0, 2.0, 0.0, 0.3]),
+])
+def test_tiny_n_brute_force_general_orders(name, alpha, h, x0, x1, p):
+    N = 8
+    y = O.solve(_RID[name], alpha, h, N, x0, p, out_stride=1, x1=x1)
+    ref = _brute_force(name, alpha, h, N, x0, p, x1=x1)
+    assert np.max(np.abs(y - ref)) <= 4e-15 * max(1.0, np.max(np.abs(ref)))
+
+
+# ---------------------------------------------------------------- general orders
+def test_uncoupled_components_equal_scalar_runs():
+    """DIAG with m = 0 is two scalar problems D^(a_i) y_i = -l_i y_i; with
+    different orders each component must be, bit for bit, the scalar LINEAR
+    run of its own order (a component reading the other's weights, h^a or
+    Gamma factor fails this)."""
+    h, N = 2.0 ** -6, 700
+    al, lam, x0 = (0.55, 0.9), (1.3, 0.4), (1.0, -2.0)
+    y = O.solve(O.RHS_DIAG, al, h, N, x0, [lam[0], lam[1], 0.0, 0.0], out_stride=1)
+    for i in range(2):
+        yi = O.solve(O.RHS_LINEAR, al[i], h, N, [x0[i]], [lam[i]], out_stride=1)[:, 0]
+        assert np.array_equal(y[:, i], yi), i
+
+
+@pytest.mark.parametrize("alphas", [(0.6, 1.7), (1.0, 0.35), (2.0, 1.25)])
+def test_constant_forcing_closed_form_per_component(alphas):
+    """f = m (no dependence on y): both product rules integrate a constant
+    exactly, so component i is y_i(t) = x0_i + [a_i > 1] x1_i t
+    + m_i t^(a_i) / Gamma(a_i + 1) at every node, each with its own order."""
+    h, N = 1.0 / 64, 400
+    x0, x1, m = (0.25, -1.0), (0.5, 2.0), (0.7, -0.3)
+    y = O.solve(O.RHS_DIAG, alphas, h, N, x0, [0.0, 0.0, m[0], m[1]], out_stride=1, x1=x1)
+    t = np.arange(N + 1) * h
+    for i in range(2):
+        exact = x0[i] + m[i] * t ** alphas[i] / math.gamma(alphas[i] + 1)
+        if alphas[i] > 1:
+            exact = exact + x1[i] * t
+        assert np.max(np.abs(y[:, i] - exact)) <= 2e-14 * np.max(np.abs(exact)), i
+
+
+@pytest.mark.parametrize("alpha", [1.25, 1.6, 2.0])
+def test_linear_in_t_forcing_exact_above_one(alpha):
+    """D^a y = c0 + c1 t, y(0) = y0, y'(0) = y1 (1 < a <= 2):
+    y = y0 + y1 t + c0 t^a/Gamma(a+1) + c1 t^(a+1)/Gamma(a+2), reproduced at
+    every node (the start term of eq. abm plus exact product integration)."""
+    c0, c1, y0, y1, h, N = 0.7, -0.3, 0.25, -0.8, 1.0 / 64, 300
+    y = O.solve(O.RHS_POLY, alpha, h, N, [y0], [c0, c1], out_stride=1, x1=[y1])[:, 0]
+    t = np.arange(N + 1) * h
+    exact = (y0 + y1 * t + c0 * t ** alpha / math.gamma(alpha + 1)
+             + c1 * t ** (alpha + 1) / math.gamma(alpha + 2))
+    assert np.max(np.abs(y - exact)) <= 2e-14 * np.max(np.abs(exact))
+
+
+def test_mittag_leffler_above_one_converges_at_order_two():
+    """D^1.5 y = -y, y(0) = 1, y'(0) = 0 has y = E_1.5(-t^1.5); the scheme's
+    error at fixed T falls like h^2 (order min(2, 1 + a))."""
+    alpha, T = 1.5, 4.0
+    exact = _mittag_leffler(alpha, -T ** alpha)
+    errs = []
+    for k in (5, 6, 7, 8):
+        h = 2.0 ** -k
+        y = O.solve(O.RHS_LINEAR, alpha, h, int(round(T / h)), [1.0], [1.0], out_stride=0,
+                    x1=[0.0])[0, 0]
+        errs.append(abs(y - exact))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert abs(orders[-1] - 2.0) < 0.1, orders
+
+
+def test_alpha_two_is_the_harmonic_oscillator():
+    """At a = 2, D^2 y = -w^2 y with y(0) = 0, y'(0) = 1 is sin(w t)/w; the
+    error at T = 5 falls like h^2."""
+    w, T = 1.7, 5.0
+    errs = []
+    for k in (5, 6, 7, 8):
+        h = 2.0 ** -k
+        N = int(round(T / h))
+        y = O.solve(O.RHS_LINEAR, 2.0, h, N, [0.0], [w * w], out_stride=1, x1=[1.0])[:, 0]
+        t = np.arange(N + 1) * h
+        errs.append(np.max(np.abs(y - np.sin(w * t) / w)))
+    assert errs[0] < 5e-3
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
+    assert all(abs(o - 2.0) < 0.1 for o in orders), orders
+
+
 # ---------------------------------------------------------------- invariants
 def _lcr_equilibria(sigma, a, b):
     """Equilibria of the unforced LCR system (f = 0), as given in the
@@ -315,9 +445,11 @@ def _lcr_equilibria(sigma, a, b):
 
 
 @pytest.mark.parametrize("case", ["lorenz0", "lorenz+", "lorenz-", "duffing0", "lcr0", "lcr+",
-                                  "lcr-"])
+                                  "lcr-", "lcr+ incommensurate", "lcr- incommensurate"])
 def test_equilibrium_is_invariant(case):
     alpha, h, N = 0.9, 1.0 / 256, 512
+    if case.endswith("incommensurate"):
+        alpha = (0.9, 0.75)
     if case.startswith("lorenz"):
         s, r, bb = 10.0, 28.0, 8.0 / 3.0
         q = math.sqrt(bb * (r - 1))
@@ -328,7 +460,7 @@ def test_equilibrium_is_invariant(case):
         y = O.solve(O.RHS_DUFFING, alpha, h, N, x0, (0.1, 0.0, 1.2), out_stride=1)
     else:
         E = _lcr_equilibria(1.015, -1.02, -0.58)
-        x0 = E[{"lcr0": 0, "lcr+": 1, "lcr-": 2}[case]]
+        x0 = E[{"lcr0": 0, "lcr+": 1, "lcr-": 2}[case.split()[0]]]
         y = O.solve(O.RHS_LCR, alpha, h, N, x0, (1.015, 0.55, -1.02, -0.58, 0.0), out_stride=1)
     dev = np.max(np.abs(y - np.asarray(x0)[None, :]))
     assert dev <= 1e-12 * max(1.0, np.max(np.abs(x0))), dev
@@ -368,7 +500,11 @@ def test_batch_equals_single(orc):
 
 def test_invalid_arguments_rejected():
     with pytest.raises(ValueError):
-        O.solve(O.RHS_LINEAR, 1.5, 0.1, 10, [1.0], [1.0])
+        O.solve(O.RHS_LINEAR, 2.5, 0.1, 10, [1.0], [1.0])
+    with pytest.raises(ValueError):
+        O.solve(O.RHS_DIAG, (0.5, 0.0), 0.1, 10, [1.0, 1.0], [1.0])
+    with pytest.raises(ValueError):
+        O.solve(O.RHS_DIAG, (0.5, 0.6, 0.7), 0.1, 10, [1.0, 1.0], [1.0])
     with pytest.raises(ValueError):
         O.solve(O.RHS_LINEAR, 0.5, -0.1, 10, [1.0], [1.0])
     with pytest.raises(ValueError):
