@@ -3,16 +3,19 @@
  * history-sum library (libabm.so).
  *
  * The method (Bonchis, Kaslik, Rosu, arXiv 1710.01133, Section 2): for a
- * Caputo system D^alpha y = f(t, y), y(0) = x0, 0 < alpha <= 1, on the grid
+ * Caputo system D^alpha y = f(t, y), y(0) = x0 (and y'(0) = x1 when
+ * 1 < alpha <= 2: the ceil(alpha) initial values of eq. fde), on the grid
  * t_n = n h, step s = n+1 computes
- *   predictor  yP_s = x0 + h^alpha * sum_{k=0..n} b_{n-k} f_k                    (eq. abm)
- *   corrector  y_s  = x0 + h^alpha * ( c_n f_0 + sum_{k=1..n} a_{n-k} f_k
- *                                      + f(t_s, yP_s) / Gamma(alpha+2) )
- * with f_k = f(t_k, y_k), b, a, c the product-rectangle / product-trapezoid
- * weights given right after eq. abm (b with a minus sign between its two
- * powers), one corrector evaluation per step, and systems handled component
- * by component with one alpha for all components.  The O(N^2) history sums
- * are the work this library does on the GPU.
+ *   predictor  yP_s = T(t_s) + h^alpha * sum_{k=0..n} b_{n-k} f_k                (eq. abm)
+ *   corrector  y_s  = T(t_s) + h^alpha * ( c_n f_0 + sum_{k=1..n} a_{n-k} f_k
+ *                                        + f(t_s, yP_s) / Gamma(alpha+2) )
+ * with T(t) = x0 (alpha <= 1) or x0 + t x1 (alpha > 1) the Taylor sum of
+ * eq. abm, f_k = f(t_k, y_k), b, a, c the product-rectangle /
+ * product-trapezoid weights given right after eq. abm (b with a minus sign
+ * between its two powers) and one corrector evaluation per step.  Systems are
+ * handled component by component; an incommensurate system (eq. sys.LRC with
+ * alpha_1 != alpha_2) gives each component the scheme of its own order.  The
+ * O(N^2) history sums are the work this library does on the GPU.
  *
  * Conventions for every entry point:
  *  - Return value is an abm_status: 0 on success, a negative code otherwise.
@@ -51,10 +54,12 @@ enum abm_rhs {
     ABM_RHS_DUFFING = 1, /* d=2: f = (y2, -delta y2 - y1 - y1^3 + A cos(omega t)); p = {delta, A, omega} */
     ABM_RHS_LORENZ = 2,  /* d=3: f = (s(y2-y1), y1(r-y3)-y2, y1 y2 - b y3);   p = {s, r, b} */
     ABM_RHS_POLY = 3,    /* d=1: f = c0 + c1 t;                          p = {c0, c1} */
-    ABM_RHS_LCR = 4      /* d=2: forced LCR circuit of eq. sys.LRC with one common order:
+    ABM_RHS_LCR = 4,     /* d=2: forced LCR circuit of eq. sys.LRC:
                             f = (y2 - g(y1), -sigma y2 - y1 + F sin(omega t)),
                             g(x) = b x - a + b (x <= -1), a x (|x| < 1), b x + a - b (x >= 1);
                             p = {sigma, omega, a, b, F} */
+    ABM_RHS_DIAG = 5     /* d=2: two uncoupled equations, a test system for per-component
+                            orders: f = (-l1 y1 + m1, -l2 y2 + m2);  p = {l1, l2, m1, m2} */
 };
 
 /* Precision of the far-field history products of abm_solve_batch.  The near
@@ -71,13 +76,16 @@ enum abm_prec {
 typedef struct abm_problem {
     int32_t rhs;        /* enum abm_rhs */
     int32_t d;          /* state dimension; must equal the rhs dimension */
-    double alpha;       /* order, 0 < alpha <= 1 */
+    double alpha;       /* order of every component, 0 < alpha <= 2 (unless alphas[0] > 0) */
     double h;           /* step, > 0 and finite; t_s = (double)s * h */
     int64_t N;          /* number of steps, >= 1 */
     double x0[4];       /* y(0) (first d entries used) */
     double p[8];        /* rhs parameters, see enum abm_rhs */
     int32_t far_prec;   /* enum abm_prec (abm_solve_batch only) */
     int32_t out_stride; /* 0: write y_N only; k>0: write y_s for s = 0, k, 2k, ... and y_N */
+    double alphas[4];   /* incommensurate orders: if alphas[0] > 0, component i has order
+                           alphas[i] (first d entries, each in (0, 2]) and alpha is not read */
+    double x1[4];       /* y'(0) (first d entries), read for components of order above 1 */
 } abm_problem;
 
 typedef struct abm_stats {
@@ -129,13 +137,19 @@ typedef struct abm_plan_s abm_plan_t;
  * memory pool of the serving loop (abm_submit); 0 means 1 GiB.
  * Errors: ABM_EINVAL (bad device), ABM_ENOMEM, ABM_EDEVICE. */
 abm_status abm_ctx_create(int device, void *hip_stream, size_t arena_bytes, abm_ctx **out);
+/* Stops the context's server (cancelling queued requests) and frees it.
+ * Every plan made on the context must be destroyed before: a plan keeps a
+ * pointer to its context. */
 void abm_ctx_destroy(abm_ctx *ctx);
 
 /* Validate and size B problems, allocate their device state, generate their
  * weight tables on the device (Section 2 weights, cancellation-free double
  * evaluation) and choose the block length and tiles.  The plan fixes, per
- * trajectory, rhs, d, alpha, N, far_prec and out_stride; later solves may
- * change x0, p and h.  Trajectories with equal alpha share one weight table.
+ * trajectory, rhs, d, the orders, N, far_prec and out_stride; later solves
+ * may change x0, x1, p and h.  Components of equal order share one weight
+ * table.  Trajectories whose components have different orders are grouped
+ * by their order tuple; their far field runs once per component with that
+ * component's table. 
  * Errors: ABM_EINVAL (any invalid problem; the message names its index),
  * ABM_ENOMEM, ABM_EDEVICE. */
 abm_status abm_plan(abm_ctx *ctx, const abm_problem *probs, int32_t B, abm_plan_t **out);
@@ -211,9 +225,10 @@ abm_status abm_plan_timing(abm_plan_t *plan, int32_t enable);
 abm_status abm_plan_graph(abm_plan_t *plan, int32_t enable);
 
 /* Copy the first n entries of the weight tables b_k, a_k, c_k (Section 2,
- * generated on the device by abm_plan) used by problem idx of the plan into
- * host arrays of n doubles each (any of them may be NULL).  Synchronises the
- * context's stream.  Errors: ABM_EINVAL (idx or n out of range), ABM_EDEVICE. */
+ * generated on the device by abm_plan) used by component 0 of problem idx of
+ * the plan into host arrays of n doubles each (any of them may be NULL).
+ * Synchronises the context's stream.  Errors: ABM_EINVAL (idx or n out of
+ * range), ABM_EDEVICE. */
 abm_status abm_plan_weights(abm_plan_t *plan, int32_t idx, int64_t n, double *b, double *a,
                             double *c);
 

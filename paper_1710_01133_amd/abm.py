@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libabm.so")
 
 ABM_OK, ABM_EINVAL, ABM_ENOMEM, ABM_EDEVICE, ABM_EAGAIN, ABM_ENOENT, ABM_ECANCELED = \
     0, -1, -2, -3, -4, -5, -6
-RHS_ID = {"LINEAR": 0, "DUFFING": 1, "LORENZ": 2, "POLY": 3, "LCR": 4}
+RHS_ID = {"LINEAR": 0, "DUFFING": 1, "LORENZ": 2, "POLY": 3, "LCR": 4, "DIAG": 5}
 PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3}
 
 EXPORTED = ("abm_ctx_create", "abm_ctx_destroy", "abm_plan", "abm_plan_destroy", "abm_plan_check",
@@ -33,7 +33,8 @@ class AbmProblem(ctypes.Structure):
     _fields_ = [("rhs", ctypes.c_int32), ("d", ctypes.c_int32), ("alpha", ctypes.c_double),
                 ("h", ctypes.c_double), ("N", ctypes.c_int64), ("x0", ctypes.c_double * 4),
                 ("p", ctypes.c_double * 8), ("far_prec", ctypes.c_int32),
-                ("out_stride", ctypes.c_int32)]
+                ("out_stride", ctypes.c_int32), ("alphas", ctypes.c_double * 4),
+                ("x1", ctypes.c_double * 4)]
 
 
 class AbmStats(ctypes.Structure):
@@ -147,7 +148,18 @@ def c_problem(p: Problem, out_stride: int = 0) -> AbmProblem:
     c = AbmProblem()
     c.rhs = RHS_ID[p.rhs]
     c.d = RHS_DIM[p.rhs]
-    c.alpha = float(p.alpha)
+    if isinstance(p.alpha, (tuple, list)):
+        # incommensurate orders: one per component
+        if len(p.alpha) != c.d:
+            raise ValueError("alpha needs one order per component (%d)" % c.d)
+        c.alpha = 0.0
+        for i, v in enumerate(p.alpha):
+            c.alphas[i] = float(v)
+    else:
+        c.alpha = float(p.alpha)
+    if p.x1 is not None:
+        for i, v in enumerate(p.x1):
+            c.x1[i] = float(v)
     c.h = float(p.h)
     c.N = int(p.N)
     for i, v in enumerate(p.x0):
@@ -180,6 +192,7 @@ class Context:
             stream = _current_stream_handle()
         _check(lib.abm_ctx_create(device, ctypes.c_void_p(stream), arena_bytes,
                                   ctypes.byref(self._h)), "abm_ctx_create")
+        self._plans = weakref.WeakSet()   # plans made on this context
         _live_contexts.add(self)
 
     @property
@@ -187,7 +200,11 @@ class Context:
         return self._h
 
     def close(self):
+        """Destroy the context; plans still open on it are destroyed first
+        (a plan must not outlive its context)."""
         if self._h:
+            for plan in list(self._plans):
+                plan.close()
             load().abm_ctx_destroy(self._h)
             self._h = ctypes.c_void_p()
 
@@ -217,6 +234,7 @@ class Plan:
             t = AbmTuning(**tuning)
             _check(lib.abm_plan_tuned(ctx.handle, arr, len(self.problems), ctypes.byref(t),
                                       ctypes.byref(self._h)), "abm_plan_tuned")
+        ctx._plans.add(self)
         _live_plans.add(self)
 
     def config(self) -> dict:

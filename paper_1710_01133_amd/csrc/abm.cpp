@@ -46,8 +46,37 @@ int rhs_dim(int rhs)
     case ABM_RHS_LORENZ: return 3;
     case ABM_RHS_POLY: return 1;
     case ABM_RHS_LCR: return 2;
+    case ABM_RHS_DIAG: return 2;
     default: return -1;
     }
+}
+
+double order_of(const abm_problem& p, int comp)
+{
+    return p.alphas[0] > 0.0 ? p.alphas[comp] : p.alpha;
+}
+
+bool orders_differ(const abm_problem& p)
+{
+    for (int i = 1; i < p.d; ++i)
+        if (order_of(p, i) != order_of(p, 0)) return true;
+    return false;
+}
+
+int deriv_mask(const abm_problem& p)
+{
+    int m = 0;
+    for (int i = 0; i < p.d; ++i)
+        if (order_of(p, i) > 1.0) m |= 1 << i;
+    return m;
+}
+
+bool same_orders(const abm_problem& a, const abm_problem& b)
+{
+    if (a.d != b.d) return false;
+    for (int i = 0; i < a.d; ++i)
+        if (order_of(a, i) != order_of(b, i)) return false;
+    return true;
 }
 
 int64_t n_out(int64_t N, int64_t stride)
@@ -61,8 +90,13 @@ abm_status validate(const abm_problem& p, int idx)
     const int d = rhs_dim(p.rhs);
     if (d < 0) return fail(ABM_EINVAL, "problem %d: unknown rhs %d", idx, p.rhs);
     if (p.d != d) return fail(ABM_EINVAL, "problem %d: d=%d but rhs %d has dimension %d", idx, p.d, p.rhs, d);
-    if (!(p.alpha > 0.0 && p.alpha <= 1.0))
-        return fail(ABM_EINVAL, "problem %d: alpha=%g outside (0, 1]", idx, p.alpha);
+    for (int i = 0; i < d; ++i) {
+        const double al = order_of(p, i);
+        if (!(al > 0.0 && al <= 2.0))
+            return fail(ABM_EINVAL, "problem %d: order %g of component %d outside (0, 2]", idx, al, i);
+        if (al > 1.0 && !std::isfinite(p.x1[i]))
+            return fail(ABM_EINVAL, "problem %d: x1 not finite", idx);
+    }
     if (!(p.h > 0.0) || !std::isfinite(p.h))
         return fail(ABM_EINVAL, "problem %d: h=%g must be positive and finite", idx, p.h);
     if (p.N < 1 || p.N > kMaxSteps)
@@ -81,7 +115,7 @@ abm_status validate(const abm_problem& p, int idx)
 // Shape fields a plan fixes; x0, p and h may change between solves.
 static bool same_shape(const abm_problem& a, const abm_problem& b)
 {
-    return a.rhs == b.rhs && a.d == b.d && a.alpha == b.alpha && a.N == b.N &&
+    return a.rhs == b.rhs && a.d == b.d && same_orders(a, b) && a.N == b.N &&
            a.far_prec == b.far_prec && a.out_stride == b.out_stride;
 }
 
@@ -199,20 +233,24 @@ abm_status abm_plan_tuned(abm_ctx* ctx, const abm_problem* probs, int32_t B,
     if (tune) pl->tune = *tune;
     abm_status st = ABM_OK;
 
-    // one weight table per distinct alpha, long enough for its longest member
-    pl->table_of.resize(B);
+    // one weight table per distinct order, long enough for its longest user
+    pl->table_of.assign((size_t)B * 4, 0);
     for (int i = 0; i < B; ++i) {
-        int found = -1;
-        for (size_t j = 0; j < pl->tables.size(); ++j)
-            if (pl->tables[j].alpha == probs[i].alpha) found = (int)j;
-        if (found < 0) {
-            WeightTable t{};
-            t.alpha = probs[i].alpha;
-            pl->tables.push_back(t);
-            found = (int)pl->tables.size() - 1;
+        for (int c = 0; c < probs[i].d; ++c) {
+            const double al = order_of(probs[i], c);
+            int found = -1;
+            for (size_t j = 0; j < pl->tables.size(); ++j)
+                if (pl->tables[j].alpha == al) found = (int)j;
+            if (found < 0) {
+                WeightTable t{};
+                t.alpha = al;
+                pl->tables.push_back(t);
+                found = (int)pl->tables.size() - 1;
+            }
+            pl->tables[found].n = std::max<int64_t>(pl->tables[found].n, probs[i].N);
+            pl->table_of[(size_t)i * 4 + c] = found;
         }
-        pl->tables[found].n = std::max<int64_t>(pl->tables[found].n, probs[i].N);
-        pl->table_of[i] = found;
+        for (int c = probs[i].d; c < 4; ++c) pl->table_of[(size_t)i * 4 + c] = pl->table_of[(size_t)i * 4];
     }
     for (auto& t : pl->tables) {
         // padded so that block kernels may read a full tile past N
@@ -283,7 +321,7 @@ abm_status abm_plan_weights(abm_plan_t* pl, int32_t idx, int64_t n, double* b, d
 {
     if (!pl) return fail(ABM_EINVAL, "plan is NULL");
     if (idx < 0 || idx >= pl->B) return fail(ABM_EINVAL, "idx %d outside [0, %d)", idx, pl->B);
-    const WeightTable& t = pl->tables[pl->table_of[idx]];
+    const WeightTable& t = pl->tables[pl->table_of[(size_t)idx * 4]];
     if (n < 0 || n > t.n + kWeightPad)
         return fail(ABM_EINVAL, "n=%lld outside [0, %lld]", (long long)n, (long long)(t.n + kWeightPad));
     hipError_t e = hipSetDevice(pl->ctx->device);
@@ -303,18 +341,21 @@ abm_status abm_solve(abm_plan_t* pl, const abm_problem* prob, double* y_out)
     abm_status s = validate(*prob, 0);
     if (s != ABM_OK) return s;
     if (!same_shape(*prob, pl->shape[0]))
-        return fail(ABM_EINVAL, "problem does not match the plan (rhs, d, alpha, N, far_prec, out_stride)");
+        return fail(ABM_EINVAL, "problem does not match the plan (rhs, d, orders, N, far_prec, out_stride)");
     hipError_t e = hipSetDevice(pl->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    const WeightTable& t = pl->tables[pl->table_of[0]];
     PlainArgs A{};
-    A.b = t.b;
-    A.a = t.a;
-    A.c = t.c;
-    A.gam = t.gam;
-    A.alpha = prob->alpha;
+    for (int i = 0; i < 4; ++i) {
+        const WeightTable& t = pl->tables[pl->table_of[i]];
+        A.b[i] = t.b;
+        A.a[i] = t.a;
+        A.c[i] = t.c;
+        A.gam[i] = t.gam;
+        A.alpha[i] = t.alpha;
+        A.x0[i] = prob->x0[i];
+        A.x1[i] = prob->x1[i];
+    }
     A.h = prob->h;
-    for (int i = 0; i < 4; ++i) A.x0[i] = prob->x0[i];
     for (int i = 0; i < 8; ++i) A.p[i] = prob->p[i];
     A.N = prob->N;
     A.G = pl->plain_G;
@@ -327,7 +368,7 @@ abm_status abm_solve(abm_plan_t* pl, const abm_problem* prob, double* y_out)
     A.spin_limit = kSpinLimit;
     e = launch_fill_u32(pl->flags, 0, pl->plain_G, pl->ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "flag reset");
-    e = launch_plain(A, prob->rhs, pl->ctx->stream);
+    e = launch_plain(A, chain_kind(prob->rhs, orders_differ(*prob)), pl->ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
     return ABM_OK;
 }

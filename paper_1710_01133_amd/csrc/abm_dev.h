@@ -52,6 +52,9 @@ __device__ __forceinline__ void rhs_eval(const double* __restrict__ p, double t,
             g = p[2] * x;
         f[0] = y[1] - g;
         f[1] = -p[0] * y[1] - y[0] + p[4] * sin(p[1] * t);
+    } else if constexpr (R == ABM_RHS_DIAG) {
+        f[0] = -p[0] * y[0] + p[2];
+        f[1] = -p[1] * y[1] + p[3];
     }
 }
 
@@ -93,6 +96,9 @@ __device__ __forceinline__ void rhs_eval_forced(const double* __restrict__ p, co
             g = p[2] * x;
         f[0] = y[1] - g;
         f[1] = -p[0] * y[1] - y[0] + force;
+    } else if constexpr (R == ABM_RHS_DIAG) {
+        f[0] = -p[0] * y[0] + p[2];
+        f[1] = -p[1] * y[1] + p[3];
     }
 }
 

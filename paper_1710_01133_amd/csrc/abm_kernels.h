@@ -16,14 +16,23 @@ hipError_t launch_weights(double alpha, int64_t n, double* gam, double* b, doubl
 hipError_t launch_weights_lowp(int64_t n, const double* b, const double* a, float* b32, float* a32,
                                uint16_t* const* bh, uint16_t* const* ah, hipStream_t st);
 
+// Number of right-hand sides (enum abm_rhs) and the chain kernels' kinds:
+// a right-hand side, plus kRhsCount when the group's components have orders
+// of their own (a weight table per component).
+constexpr int kRhsCount = 6;
+constexpr int kChainKinds = 2 * kRhsCount;
+inline int chain_kind(int rhs, bool per_comp) { return rhs + (per_comp ? kRhsCount : 0); }
+
 // ---- K1: plain per-step persistent kernel --------------------------------
 struct PlainArgs {
-    const double* b;     // weights b_k, k < N
-    const double* a;     // weights a_k
-    const double* c;     // weights c_k
-    const double* gam;   // Gamma(alpha+1), Gamma(alpha+2)
-    double alpha, h;
+    const double* b[4];  // weights b_k, k < N, of each component's order
+    const double* a[4];  // weights a_k
+    const double* c[4];  // weights c_k
+    const double* gam[4];  // Gamma(alpha+1), Gamma(alpha+2)
+    double alpha[4];
+    double h;
     double x0[4];
+    double x1[4];        // y'(0), used by components of order above 1
     double p[8];
     int64_t N;
     int32_t G;           // workgroups (all co-resident)
@@ -38,27 +47,32 @@ struct PlainArgs {
 int plain_max_local_chunks(int d);
 int plain_chunk();
 int plain_part_doubles(int G);
-hipError_t launch_plain(const PlainArgs& A, int rhs, hipStream_t st);
+// kind: chain_kind(rhs, components have their own orders)
+hipError_t launch_plain(const PlainArgs& A, int kind, hipStream_t st);
 
 // ---- blocked method: groups and work items --------------------------------
-// A group is a set of trajectories sharing one weight table (one alpha), one
-// right-hand side and one far-field precision; their components are the
-// columns of one time-major history.  Launches take lists of work items that
-// point at group descriptors in device memory, so one launch can advance
-// groups that are at different blocks (differing N, alpha, start time).
+// A group is a set of trajectories sharing their orders (one weight table, or
+// one per component), one right-hand side and one far-field precision; their
+// components are the columns of one time-major history.  Launches take lists
+// of work items that point at group descriptors in device memory, so one
+// launch can advance groups that are at different blocks (differing N,
+// alpha, start time).
 struct TrajDesc {
     double x0[4];
+    double x1[4];          // y'(0), used by components of order above 1
     double p[8];
     double h;
     int64_t N;
     int64_t out_stride;
     double* y_out;
-    int32_t col0;          // first column of this trajectory in its group's history
-    int32_t pad_;
+    int32_t col0;          // column of component 0 of this trajectory in its group's history
+    int32_t cstride;       // column distance between its components (1, or the
+                           // component block width when columns are component-major)
 };
 
-struct GroupDev {
-    const double* b;       // weight tables (padded past N by at least 2L)
+// The weight tables of one order (padded past N by at least 2L).
+struct CompWeights {
+    const double* b;
     const double* a;
     const double* c;
     const double* gam;     // Gamma(alpha+1), Gamma(alpha+2)
@@ -67,6 +81,10 @@ struct GroupDev {
     const uint16_t* bh[3]; // bf16 split terms (far_prec bf16x3 / bf16x6)
     const uint16_t* ah[3];
     double alpha;
+};
+
+struct GroupDev {
+    CompWeights w[4];      // component i's tables (all equal unless per_comp)
     double* F;             // time-major double history [k][ldF]
     float* F32;            // float copy: column-blocked (colblocked_index), or
                            // time-major [k][ldF] in a narrow group
@@ -80,20 +98,28 @@ struct GroupDev {
     int32_t d;
     int32_t narrow;        // 1: few columns, far field by the blocked convolution,
                            // ldF = real columns and F32 time-major
+    int32_t per_comp;      // 1: components have orders of their own; columns are
+                           // component-major (component i of member j at i*cstride + j)
+    int32_t deriv;         // bit i: component i has order above 1 (start term x0 + t x1)
 };
 
-// Far field of one group for block m: history k = 1..kfar, kfar = (m-1)L.
+// Far field of one group (or of one component of a group whose components
+// have their own orders) for block m: history k = 1..kfar, kfar = (m-1)L.
 struct FarItem {
     int32_t group;
     int32_t ncoltiles;     // active columns / tile width (narrow: product tiles)
     int32_t nchunks;       // ceil(kfar / kchunk) (narrow: chunks of shifts)
     int32_t chunks_per_split;
     int32_t nsplit;        // partial slices written
-    int32_t pad_;
+    int32_t comp;          // weight tables used: the group's w[comp]
+    int32_t coff;          // first history column of the item (a multiple of 16
+                           // unless the group is narrow)
+    int32_t ncols;         // columns of the item (narrow groups)
     int64_t mL;
     int64_t kfar;
     int64_t ldP;           // column stride of the partial slices (active columns,
-                           // padded to the tile width except in narrow groups)
+                           // padded to the tile width except in narrow groups;
+                           // all columns of a per-component group)
 };
 
 // Chain of one trajectory (group member) through block m.
@@ -101,7 +127,7 @@ struct ChainItem {
     int32_t group;
     int32_t member;
     int32_t nsplit;        // far partial slices of this block (0 when m < 2)
-    int32_t rhs;           // right-hand side (abm_rhs) of the group
+    int32_t kind;          // chain_kind of the group
     int64_t mL;
     int64_t ldP;
 };
@@ -146,13 +172,17 @@ hipError_t launch_far_hankel(const GroupDev* groups, const FarItem* items, int n
                              int max_nsplit, int L, int prec, hipStream_t st);
 
 // ---- K3: near band + predictor/corrector chain -----------------------------
-// One wave per item; all items of a launch share the right-hand side.
-hipError_t launch_chain(const GroupDev* groups, const ChainItem* items, int n, int rhs, int L,
+// One wave per item; all items of a launch share the chain kind.
+hipError_t launch_chain(const GroupDev* groups, const ChainItem* items, int n, int kind, int L,
                         uint32_t* status, hipStream_t st);
-// Items of any right-hand sides in one launch (one kernel for all systems).
+// Items of any kinds in one launch (one kernel for all systems); nw is the
+// largest chain_tables over the kinds of the items.
 hipError_t launch_chain_mixed(const GroupDev* groups, const ChainItem* items, int n, int L,
-                              uint32_t* status, hipStream_t st);
-// f_0 into history row 0 and y_0 = x0 for every member of the listed groups.
+                              int nw, uint32_t* status, hipStream_t st);
+// Weight tables a chain of this kind keeps in LDS (1, or d when per-component).
+int chain_tables(int kind);
+// f_0 into history row 0 and y_0 = x0 for every member of the listed groups
+// (all of right-hand side rhs).
 hipError_t launch_chain_init(const GroupDev* groups, const ChainItem* items, int n, int rhs,
                              hipStream_t st);
 

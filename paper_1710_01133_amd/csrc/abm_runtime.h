@@ -34,10 +34,16 @@ struct WeightTable {
     uint16_t* ah[3];
 };
 
-// Trajectories sharing one weight table, one right-hand side and one far-field
-// precision: their components form the columns of one time-major history.
+// Trajectories sharing their orders (one weight table per component, all the
+// same table unless per_comp), one right-hand side and one far-field
+// precision: their components form the columns of one time-major history,
+// member-major (component i of member j at j*d + i) or, when per_comp,
+// component-major (at i*ldC + j) so that every column tile holds one order.
 struct Group {
-    int table = 0;
+    int table[4] = {0, 0, 0, 0};
+    bool per_comp = false;
+    int deriv = 0;                // bit i: component i has order above 1
+    int64_t ldC = 0;              // per_comp: columns per component block
     int rhs = 0;
     int d = 0;
     int prec = 0;
@@ -86,7 +92,7 @@ struct abm_plan_s {
     int32_t B = 0;
     std::vector<abm_problem> shape;
     std::vector<abm::WeightTable> tables;
-    std::vector<int> table_of;
+    std::vector<int> table_of;    // [problem][component]: 4 entries per problem
     uint32_t* status = nullptr;
     // plain path (B == 1)
     int plain_G = 0;
@@ -133,6 +139,10 @@ abm_status hip_fail(hipError_t e, const char* what);
 int rhs_dim(int rhs);
 int64_t n_out(int64_t N, int64_t stride);
 abm_status validate(const abm_problem& p, int idx);
+double order_of(const abm_problem& p, int comp);   // order of component comp
+bool orders_differ(const abm_problem& p);          // components of different orders
+int deriv_mask(const abm_problem& p);              // bit i: component i of order above 1
+bool same_orders(const abm_problem& a, const abm_problem& b);
 int env_int(const char* name, int dflt);
 abm_status dev_alloc(void** p, size_t bytes, const char* what);
 void dev_free(void* p);
@@ -144,7 +154,10 @@ void free_reduced(WeightTable& t);
 void free_group(Group& g);
 abm_status ensure_reduced_weights(WeightTable& W, int prec, hipStream_t st);
 abm_status alloc_group(Group& g, int L, int nsplit_max, hipStream_t st);
-GroupDev group_dev(const Group& g, const WeightTable& W);
+GroupDev group_dev(const Group& g, const WeightTable* const W[4]);
+// Column layout of a group of nm members: ldF, ldC and each member's col0 /
+// cstride follow from (per_comp, narrow, d, tile width).
+void group_layout(Group& g, int L);
 void block_items(const Group& g, int gi, int64_t m, int L, int kchunk, int max_split,
                  const std::vector<int64_t>& memberN, std::vector<FarItem>* far,
                  std::vector<ChainItem>* chain);

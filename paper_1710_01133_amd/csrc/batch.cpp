@@ -1,11 +1,11 @@
 // Blocked batch path: plan-time grouping, sizing and tick schedule, and the
 // launch sequence of abm_solve_batch.
 //
-// Trajectories are grouped by (weight table = alpha, right-hand side, far
-// precision).  All groups advance in lockstep ticks: at tick t every group
-// still running steps its block m = t (chain) while the far field of its
-// block t+1 is computed on a second stream.  One far launch per precision
-// class and one chain launch per right-hand side cover all groups of a tick,
+// Trajectories are grouped by (weight table of each component = the orders,
+// right-hand side, far precision).  All groups advance in lockstep ticks: at
+// tick t every group still running steps its block m = t (chain) while the
+// far field of its block t+1 is computed on a second stream.  One far launch
+// per precision class and one chain launch cover all groups of a tick,
 // whatever their alpha, N or parameters (work items in device memory).
 #include <hip/hip_runtime.h>
 
@@ -145,21 +145,24 @@ abm_status alloc_group(Group& g, int L, int nsplit_max, hipStream_t st)
     return ABM_OK;
 }
 
-GroupDev group_dev(const Group& g, const WeightTable& W)
+GroupDev group_dev(const Group& g, const WeightTable* const W[4])
 {
     GroupDev d{};
-    d.b = W.b;
-    d.a = W.a;
-    d.c = W.c;
-    d.gam = W.gam;
-    d.b32 = W.b32;
-    d.a32 = W.a32;
-    for (int i = 0; i < 3; ++i) {
-        d.bh[i] = W.bh[i];
-        d.ah[i] = W.ah[i];
-        d.Fh[i] = g.Fh[i];
+    for (int c = 0; c < 4; ++c) {
+        CompWeights& w = d.w[c];
+        w.b = W[c]->b;
+        w.a = W[c]->a;
+        w.c = W[c]->c;
+        w.gam = W[c]->gam;
+        w.b32 = W[c]->b32;
+        w.a32 = W[c]->a32;
+        for (int i = 0; i < 3; ++i) {
+            w.bh[i] = W[c]->bh[i];
+            w.ah[i] = W[c]->ah[i];
+        }
+        w.alpha = W[c]->alpha;
     }
-    d.alpha = W.alpha;
+    for (int i = 0; i < 3; ++i) d.Fh[i] = g.Fh[i];
     d.F = g.F;
     d.F32 = g.F32;
     d.ldF = g.ldF;
@@ -170,7 +173,28 @@ GroupDev group_dev(const Group& g, const WeightTable& W)
     d.traj = g.traj_dev;
     d.d = g.d;
     d.narrow = g.narrow ? 1 : 0;
+    d.per_comp = g.per_comp ? 1 : 0;
+    d.deriv = g.deriv;
     return d;
+}
+
+void group_layout(Group& g, int L)
+{
+    const int64_t nm = (int64_t)g.members.size();
+    const int TN = far_tile_cols(L, g.prec);
+    g.cols = nm * g.d;
+    g.col0.resize(nm);
+    if (g.per_comp) {
+        // component-major: each component's columns form a block that starts
+        // on a tile (and 16-column) boundary unless the group is narrow
+        g.ldC = g.narrow ? nm : round_up(nm, std::max(TN, 16));
+        g.ldF = g.ldC * g.d;
+        for (int64_t j = 0; j < nm; ++j) g.col0[j] = (int32_t)j;
+    } else {
+        g.ldC = 1;
+        g.ldF = g.narrow ? g.cols : round_up(g.cols, TN);
+        for (int64_t j = 0; j < nm; ++j) g.col0[j] = (int32_t)(j * g.d);
+    }
 }
 
 // Work items of group g (index gi) when it is at block m: the far field of
@@ -194,27 +218,44 @@ void block_items(const Group& g, int gi, int64_t m, int L, int kchunk, int max_s
         it.group = gi;
         it.kfar = (mf - 1) * L;
         it.mL = mf * L;
-        if (g.narrow) {
-            it.ldP = (int64_t)active(mf) * g.d;
-            it.ncoltiles = hankel_tiles(it.ldP, L);
-        } else {
-            it.ldP = round_up((int64_t)active(mf) * g.d, TN);
-            it.ncoltiles = (int32_t)(it.ldP / TN);
-        }
         it.nsplit = group_split_plan(g, it.kfar, L, kchunk, max_split, &it.nchunks,
                                      &it.chunks_per_split);
-        far->push_back(it);
+        const int64_t na = active(mf);
+        if (g.per_comp) {
+            // one item per component: its column block, its weight tables;
+            // the partial slices keep the group's full column stride
+            it.ldP = g.ldF;
+            it.ncols = (int32_t)na;
+            it.ncoltiles = g.narrow ? hankel_tiles(na, L) : (int32_t)((na + TN - 1) / TN);
+            for (int c = 0; c < g.d; ++c) {
+                it.comp = c;
+                it.coff = (int32_t)(c * g.ldC);
+                far->push_back(it);
+            }
+        } else {
+            if (g.narrow) {
+                it.ldP = na * g.d;
+                it.ncoltiles = hankel_tiles(it.ldP, L);
+            } else {
+                it.ldP = round_up(na * g.d, TN);
+                it.ncoltiles = (int32_t)(it.ldP / TN);
+            }
+            it.ncols = (int32_t)(na * g.d);
+            far->push_back(it);
+        }
     }
     if (chain && m < nblocks) {
         int nsp = 0, nc = 0, cps = 0;
         if (m >= 2) nsp = group_split_plan(g, (m - 1) * L, L, kchunk, max_split, &nc, &cps);
         const int32_t na = active(m);
-        const int64_t ldP = g.narrow ? (int64_t)na * g.d : round_up((int64_t)na * g.d, TN);
+        const int64_t ldP = g.per_comp ? g.ldF
+                          : g.narrow  ? (int64_t)na * g.d
+                                      : round_up((int64_t)na * g.d, TN);
         for (int32_t j = 0; j < na; ++j) {
             ChainItem c{};
             c.group = gi;
             c.member = j;
-            c.rhs = g.rhs;
+            c.kind = chain_kind(g.rhs, g.per_comp);
             c.nsplit = nsp;
             c.mL = m * L;
             c.ldP = ldP;
@@ -270,15 +311,19 @@ abm_status batch_setup(abm_plan_s* pl)
     if (s) return s;
     const int L = pl->L, kchunk = pl->kchunk;
 
-    // groups: (weight table, rhs, precision); members sorted by N descending
-    std::map<std::tuple<int, int, int>, int> key_to_group;
+    // groups: (weight table of each component, rhs, precision); members
+    // sorted by N descending
+    std::map<std::tuple<int, int, int, int, int, int>, int> key_to_group;
     for (int i = 0; i < pl->B; ++i) {
         const abm_problem& p = pl->shape[i];
-        auto key = std::make_tuple(pl->table_of[i], p.rhs, p.far_prec);
+        const int* tb = &pl->table_of[(size_t)i * 4];
+        auto key = std::make_tuple(tb[0], tb[1], tb[2], tb[3], p.rhs, p.far_prec);
         auto it = key_to_group.find(key);
         if (it == key_to_group.end()) {
             Group g{};
-            g.table = pl->table_of[i];
+            for (int c = 0; c < 4; ++c) g.table[c] = tb[c];
+            g.per_comp = orders_differ(p);
+            g.deriv = deriv_mask(p);
             g.rhs = p.rhs;
             g.d = p.d;
             g.prec = p.far_prec;
@@ -303,17 +348,18 @@ abm_status batch_setup(abm_plan_s* pl)
     for (auto& g : pl->groups) {
         std::stable_sort(g.members.begin(), g.members.end(),
                          [&](int x, int y) { return pl->shape[x].N > pl->shape[y].N; });
-        const int TN = far_tile_cols(L, g.prec);
         g.nmax = pl->shape[g.members[0]].N;
         if (g.narrow) g.split_cap = narrow_split;
-        g.ldF = g.narrow ? g.cols : round_up(g.cols, TN);
+        group_layout(g, L);
         g.rows = g.nmax + 1 + L;
-        g.col0.resize(g.members.size());
-        for (size_t j = 0; j < g.members.size(); ++j) g.col0[j] = (int32_t)(j * g.d);
         ticks = std::max(ticks, (g.nmax + L - 1) / L);
-        if ((s = ensure_reduced_weights(pl->tables[g.table], g.prec, st))) return s;
+        const WeightTable* W[4];
+        for (int c = 0; c < 4; ++c) {
+            if ((s = ensure_reduced_weights(pl->tables[g.table[c]], g.prec, st))) return s;
+            W[c] = &pl->tables[g.table[c]];
+        }
         if ((s = alloc_group(g, L, (int)group_far_split_max(g, L, kchunk, pl->max_split), st))) return s;
-        gdev.push_back(group_dev(g, pl->tables[g.table]));
+        gdev.push_back(group_dev(g, W));
     }
 
     // static tick schedule: far items by precision class, chain items by rhs
@@ -323,7 +369,7 @@ abm_status batch_setup(abm_plan_s* pl)
         for (int idx : pl->groups[gi].members) memberN[gi].push_back(pl->shape[idx].N);
     pl->ticks = ticks;
     pl->far_spans.assign((size_t)ticks * kFarClasses, Span{});
-    pl->chain_spans.assign((size_t)ticks * 5, Span{});
+    pl->chain_spans.assign((size_t)ticks * kChainKinds, Span{});
     std::vector<FarItem> far_all;
     std::vector<ChainItem> chain_all, init_all;
     for (int64_t t = 0; t < ticks; ++t) {
@@ -340,18 +386,18 @@ abm_status batch_setup(abm_plan_s* pl)
                 sp.max_y = std::max(sp.max_y, far_all[k].nsplit);
             }
         }
-        for (int rhs = 0; rhs < 5; ++rhs) {
-            Span& sp = pl->chain_spans[t * 5 + rhs];
+        for (int kind = 0; kind < kChainKinds; ++kind) {
+            Span& sp = pl->chain_spans[t * kChainKinds + kind];
             sp.offset = (int64_t)chain_all.size();
             for (int gi = 0; gi < ngroups; ++gi)
-                if (pl->groups[gi].rhs == rhs)
+                if (chain_kind(pl->groups[gi].rhs, pl->groups[gi].per_comp) == kind)
                     block_items(pl->groups[gi], gi, t, L, kchunk, pl->max_split, memberN[gi],
                                 nullptr, &chain_all);
             sp.count = (int32_t)((int64_t)chain_all.size() - sp.offset);
         }
     }
-    pl->init_spans.assign(5, Span{});
-    for (int rhs = 0; rhs < 5; ++rhs) {
+    pl->init_spans.assign(kRhsCount, Span{});
+    for (int rhs = 0; rhs < kRhsCount; ++rhs) {
         Span& sp = pl->init_spans[rhs];
         sp.offset = (int64_t)init_all.size();
         for (int gi = 0; gi < ngroups; ++gi) {
@@ -371,8 +417,10 @@ abm_status batch_setup(abm_plan_s* pl)
         const Group& g = pl->groups[it.group];
         if (it.nsplit > g.nsplit_cap || it.ldP > g.ldF)
             return fail(ABM_EDEVICE, "internal: far item exceeds the partial buffer of group %d", it.group);
-        if (g.narrow && !hankel_fits(g.prec, it.ldP, L))
+        if (g.narrow && !hankel_fits(g.prec, it.ncols, L))
             return fail(ABM_EDEVICE, "internal: narrow far item of group %d has too many columns", it.group);
+        if (it.coff + (int64_t)it.ncols > g.ldF || (!g.narrow && it.coff % 16))
+            return fail(ABM_EDEVICE, "internal: far item of group %d outside its columns", it.group);
     }
     for (const ChainItem& it : chain_all)
         if (it.nsplit > pl->groups[it.group].nsplit_cap)
@@ -394,7 +442,7 @@ abm_status batch_setup(abm_plan_s* pl)
         const Group& g = pl->groups[it.group];
         for (int64_t N : memberN[it.group]) {
             if (N <= it.mL) continue;
-            pl->far_macs += (int64_t)g.d * std::min<int64_t>(L, N - it.mL) * it.kfar;
+            pl->far_macs += (int64_t)(g.per_comp ? 1 : g.d) * std::min<int64_t>(L, N - it.mL) * it.kfar;
         }
     }
     pl->overlap = env_int("ABM_OVERLAP", 1) != 0;
@@ -459,7 +507,7 @@ struct TickEnqueuer {
     {
         hipError_t e;
         const int L = pl->L;
-        for (int rhs = 0; rhs < 5; ++rhs) {
+        for (int rhs = 0; rhs < kRhsCount; ++rhs) {
             const Span& sp = pl->init_spans[rhs];
             if (!sp.count) continue;
             e = launch_chain_init(pl->groups_dev, pl->init_items_dev + sp.offset, sp.count, rhs, st);
@@ -495,31 +543,32 @@ struct TickEnqueuer {
             }
             if (ev_far_prev && (e = hipStreamWaitEvent(st, ev_far_prev, 0)) != hipSuccess)
                 return hip_fail(e, "stream wait");
-            // chains of every right-hand side: one launch (one kernel switching
-            // per wave when the tick mixes systems), so they run side by side
-            int nrhs = 0, nch = 0;
+            // chains of every kind: one launch (one kernel switching per wave
+            // when the tick mixes systems), so they run side by side
+            int nkind = 0, nch = 0, nw = 1;
             int64_t off0 = -1;
-            for (int rhs = 0; rhs < 5; ++rhs) {
-                const Span& sp = pl->chain_spans[t * 5 + rhs];
+            for (int kind = 0; kind < kChainKinds; ++kind) {
+                const Span& sp = pl->chain_spans[t * kChainKinds + kind];
                 if (!sp.count) continue;
-                ++nrhs;
+                ++nkind;
                 if (off0 < 0) off0 = sp.offset;
                 nch += sp.count;
+                nw = std::max(nw, chain_tables(kind));
             }
-            if (nrhs > 1) {
+            if (nkind > 1) {
                 e = timed(1, st, [&]() {
                     return launch_chain_mixed(pl->groups_dev, pl->chain_items_dev + off0, nch, L,
-                                              pl->status, st);
+                                              nw, pl->status, st);
                 });
                 if (e != hipSuccess) return hip_fail(e, "chain launch");
                 ++chain_launches;
             } else {
-                for (int rhs = 0; rhs < 5; ++rhs) {
-                    const Span& sp = pl->chain_spans[t * 5 + rhs];
+                for (int kind = 0; kind < kChainKinds; ++kind) {
+                    const Span& sp = pl->chain_spans[t * kChainKinds + kind];
                     if (!sp.count) continue;
                     e = timed(1, st, [&]() {
                         return launch_chain(pl->groups_dev, pl->chain_items_dev + sp.offset, sp.count,
-                                            rhs, L, pl->status, st);
+                                            kind, L, pl->status, st);
                     });
                     if (e != hipSuccess) return hip_fail(e, "chain launch");
                     ++chain_launches;
@@ -588,7 +637,7 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
         if (s) return s;
         const abm_problem& a = probs[i];
         const abm_problem& b = pl->shape[i];
-        if (a.rhs != b.rhs || a.d != b.d || a.alpha != b.alpha || a.N != b.N ||
+        if (a.rhs != b.rhs || a.d != b.d || !same_orders(a, b) || a.N != b.N ||
             a.far_prec != b.far_prec || a.out_stride != b.out_stride)
             return fail(ABM_EINVAL, "problem %d does not match the plan", i);
         if (!y_out[i]) return fail(ABM_EINVAL, "y_out[%d] is NULL", i);
@@ -613,13 +662,17 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
             const abm_problem& p = probs[g.members[j]];
             TrajDesc& T = td[j];
             memset(&T, 0, sizeof T);
-            for (int i = 0; i < 4; ++i) T.x0[i] = p.x0[i];
+            for (int i = 0; i < 4; ++i) {
+                T.x0[i] = p.x0[i];
+                T.x1[i] = p.x1[i];
+            }
             for (int i = 0; i < 8; ++i) T.p[i] = p.p[i];
             T.h = p.h;
             T.N = p.N;
             T.out_stride = p.out_stride;
             T.y_out = y_out[g.members[j]];
             T.col0 = g.col0[j];
+            T.cstride = (int32_t)g.ldC;
             S.history_macs += (int64_t)p.d * p.N * (p.N + 1) / 2;
         }
         e = hipMemcpyAsync(g.traj_dev, td, g.members.size() * sizeof(TrajDesc),

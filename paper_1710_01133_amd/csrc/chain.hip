@@ -28,11 +28,11 @@ namespace {
 
 // Per-wave view of one chain work item.
 struct ChainArgs {
-    gptr<const double> b;
-    gptr<const double> a;
-    gptr<const double> c;
-    gptr<const double> gam;
-    double alpha;
+    gptr<const double> b[4];   // component i's tables (component 0's unless per-component)
+    gptr<const double> a[4];
+    gptr<const double> c[4];
+    gptr<const double> gam[4];
+    double alpha[4];
     gptr<double> F;
     gptr<float> F32;
     gptr<uint16_t> Fhi;
@@ -52,11 +52,14 @@ template <int L>
 __device__ __forceinline__ void chain_view(const GroupDev& G, const ChainItem& it, int D,
                                            ChainArgs& A)
 {
-    A.b = as_global(G.b);
-    A.a = as_global(G.a);
-    A.c = as_global(G.c);
-    A.gam = as_global(G.gam);
-    A.alpha = G.alpha;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        A.b[i] = as_global(G.w[i].b);
+        A.a[i] = as_global(G.w[i].a);
+        A.c[i] = as_global(G.w[i].c);
+        A.gam[i] = as_global(G.w[i].gam);
+        A.alpha[i] = G.w[i].alpha;
+    }
     A.F = as_global(G.F);
     A.F32 = as_global(G.F32);
     A.Fhi = as_global(G.Fh[0]);
@@ -80,17 +83,23 @@ __device__ __forceinline__ double readlane_d(double v, int l)
     return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
 }
 
+// History column of component i of a trajectory.
+__device__ __forceinline__ int64_t comp_col(const TrajDesc& T, int i)
+{
+    return (int64_t)T.col0 + (int64_t)i * T.cstride;
+}
+
 template <int D>
 __device__ __forceinline__ void store_history(const ChainArgs& A, const TrajDesc& T, int64_t s,
                                               const double* fs)
 {
-    const int64_t row = s * A.ldF + T.col0;
+    const int64_t row = s * A.ldF;
 #pragma unroll
-    for (int i = 0; i < D; ++i) A.F[row + i] = fs[i];
+    for (int i = 0; i < D; ++i) A.F[row + comp_col(T, i)] = fs[i];
     if (A.F32) {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const int64_t at = A.narrow ? row + i : colblocked_index(s, T.col0 + i, A.rows);
+            const int64_t at = A.narrow ? row + comp_col(T, i) : colblocked_index(s, comp_col(T, i), A.rows);
             A.F32[at] = (float)fs[i];
         }
     }
@@ -99,7 +108,7 @@ __device__ __forceinline__ void store_history(const ChainArgs& A, const TrajDesc
         for (int i = 0; i < D; ++i) {
             uint16_t t[3];
             bf16_split3(fs[i], t);
-            const int64_t at = kblocked_index(s, T.col0 + i, A.ldF);
+            const int64_t at = kblocked_index(s, comp_col(T, i), A.ldF);
             A.Fhi[at] = t[0];
             A.Fmid[at] = t[1];
             if (A.Flo) A.Flo[at] = t[2];
@@ -128,20 +137,27 @@ __device__ __forceinline__ void store_output(const TrajDesc& T, int64_t s, const
 // are packed two waves per SIMD on as few CUs as possible, which leaves whole
 // CUs to the far-field kernel running beside them.
 // The block of one chain item, run by one wave (smw: that wave's 4L doubles
-// of LDS).
-template <int R, int D, int L>
+// of LDS per weight table in use).  PC: the components have orders of their
+// own, each with its weight table, weight rings and scalar factors;
+// otherwise all components share component 0's.
+template <int R, int D, int L, bool PC>
 __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& it, double* smw,
                                             int lane, uint32_t* status)
 {
     constexpr int Q = L / 64;
+    constexpr int NW = PC ? D : 1;            // weight tables in use
     ChainArgs A;
     chain_view<L>(G, it, D, A);
     const TrajDesc T = G.traj[it.member];
-    double* swb = smw;
-    double* swa = swb + 2 * L;
-    for (int x = lane; x < 2 * L; x += 64) {
-        swb[x] = A.b[x];
-        swa[x] = A.a[x];
+    // weight windows: table w's b[0..2L) at smw + 4Lw, a[0..2L) after it
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        double* swb = smw + (size_t)w * 4 * L;
+        double* swa = swb + 2 * L;
+        for (int x = lane; x < 2 * L; x += 64) {
+            swb[x] = A.b[w][x];
+            swa[x] = A.a[w][x];
+        }
     }
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -150,16 +166,24 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
     const int rows = (int)((T.N - mL) < L ? (T.N - mL) : L);
     const bool more = T.N > mL + L;           // a next block follows
 
-    double x0[D], F0[D], p[8];
+    double x0[D], x1[D], F0[D], p[8];
 #pragma unroll
-    for (int i = 0; i < D; ++i) x0[i] = T.x0[i];
+    for (int i = 0; i < D; ++i) {
+        x0[i] = T.x0[i];
+        x1[i] = T.x1[i];
+    }
 #pragma unroll
     for (int i = 0; i < 8; ++i) p[i] = T.p[i];
     const double h = T.h;
-    const double ha = pow(h, A.alpha);
-    const double g2inv = 1.0 / A.gam[1];
+    const int deriv = G.deriv;                // components whose start term is x0 + t x1
+    double ha[NW], g2inv[NW];
 #pragma unroll
-    for (int i = 0; i < D; ++i) F0[i] = A.F[T.col0 + i];
+    for (int w = 0; w < NW; ++w) {
+        ha[w] = pow(h, A.alpha[w]);
+        g2inv[w] = 1.0 / A.gam[w][1];
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) F0[i] = A.F[comp_col(T, i)];
 
     const int r0 = Q * lane;                  // first row of this lane
     // carried sums of block m (written by the previous block's chain)
@@ -174,7 +198,7 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
             // partial slices added in slice order; loaded 8 at a time so the
             // loads are in flight together instead of waiting one by one
             double sp = 0.0, sc = 0.0;
-            const gptr<const double> pc0 = A.part + (size_t)(T.col0 + i) * (2 * L) + r;
+            const gptr<const double> pc0 = A.part + (size_t)comp_col(T, i) * (2 * L) + r;
             const size_t sstride = (size_t)A.ldP * (2 * L);
             int ch = 0;
             for (; ch + 8 <= A.nchunks; ch += 8) {
@@ -194,8 +218,8 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
                 sp += pc0[ch * sstride];
                 sc += pc0[ch * sstride + L];
             }
-            sp += A.b[n] * F0[i];
-            sc += A.c[n] * F0[i];
+            sp += A.b[PC ? i : 0][n] * F0[i];
+            sc += A.c[PC ? i : 0][n] * F0[i];
             if (mL > 0) {
                 sp += accn[i * L + r];
                 sc += accn[(D + i) * L + r];
@@ -212,17 +236,23 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
 #pragma unroll
     for (int q = 0; q < Q; ++q) frc[q] = forcing<R>(p, (double)(mL + r0 + q + 1) * h);
 
-    // weight rings: at step r slot (x mod Q) holds w[x] for x = r0-r-1 .. r0-r-2+Q
-    // (block m rows, zero for x < 0) and w[L + x] (block m+1 rows)
-    double rbc[Q], rac[Q], rbn[Q], ran[Q];
+    // weight rings (one set per table): at step r slot (x mod Q) holds w[x]
+    // for x = r0-r-1 .. r0-r-2+Q (block m rows, zero for x < 0) and w[L + x]
+    // (block m+1 rows)
+    double rbc[NW][Q], rac[NW][Q], rbn[NW][Q], ran[NW][Q];
 #pragma unroll
-    for (int i = 0; i < Q; ++i) {
-        const int x = r0 - 1 + i;
-        const int sl = (x % Q + Q) % Q;
-        rbc[sl] = x < 0 ? 0.0 : swb[x < 0 ? 0 : x];
-        rac[sl] = x < 0 ? 0.0 : swa[x < 0 ? 0 : x];
-        rbn[sl] = swb[L + x];
-        ran[sl] = swa[L + x];
+    for (int w = 0; w < NW; ++w) {
+        const double* swb = smw + (size_t)w * 4 * L;
+        const double* swa = swb + 2 * L;
+#pragma unroll
+        for (int i = 0; i < Q; ++i) {
+            const int x = r0 - 1 + i;
+            const int sl = (x % Q + Q) % Q;
+            rbc[w][sl] = x < 0 ? 0.0 : swb[x < 0 ? 0 : x];
+            rac[w][sl] = x < 0 ? 0.0 : swa[x < 0 ? 0 : x];
+            rbn[w][sl] = swb[L + x];
+            ran[w][sl] = swa[L + x];
+        }
     }
 
     double myF[Q][D], myY[Q][D];
@@ -237,14 +267,29 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
             const int r = rb + jq;             // r mod Q == jq
             if (r < rows) {
                 const int owner = r / Q;
-                // the weight entering the rings after this step: x = r0 - r - 2
+                // the weights entering the rings after this step: x = r0 - r - 2
                 const int xn = r0 - r - 2;
-                const double nbc = xn < 0 ? 0.0 : swb[xn < 0 ? 0 : xn];
-                const double nac = xn < 0 ? 0.0 : swa[xn < 0 ? 0 : xn];
-                const double nbn = swb[L + xn];
-                const double nan_ = swa[L + xn];
+                double nbc[NW], nac[NW], nbn[NW], nan_[NW];
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    const double* swb = smw + (size_t)w * 4 * L;
+                    const double* swa = swb + 2 * L;
+                    nbc[w] = xn < 0 ? 0.0 : swb[xn < 0 ? 0 : xn];
+                    nac[w] = xn < 0 ? 0.0 : swa[xn < 0 ? 0 : xn];
+                    nbn[w] = swb[L + xn];
+                    nan_[w] = swa[L + xn];
+                }
                 const int64_t s = mL + r + 1;
-                (void)s;
+                // start term of eq. abm: x0, plus t_s x1 for orders above 1
+                double base[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) base[i] = x0[i];
+                if (deriv) {
+                    const double ts = (double)s * h;
+#pragma unroll
+                    for (int i = 0; i < D; ++i)
+                        if ((deriv >> i) & 1) base[i] = x0[i] + ts * x1[i];
+                }
                 double P[D], C[D], yP[D], fP[D], y[D], fs[D];
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
@@ -253,10 +298,11 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
                 }
                 const double force = readlane_d(frc[jq], owner);
 #pragma unroll
-                for (int i = 0; i < D; ++i) yP[i] = x0[i] + ha * P[i];
+                for (int i = 0; i < D; ++i) yP[i] = base[i] + ha[PC ? i : 0] * P[i];
                 rhs_eval_forced<R, D>(p, yP, force, fP);
 #pragma unroll
-                for (int i = 0; i < D; ++i) y[i] = x0[i] + ha * (C[i] + fP[i] * g2inv);
+                for (int i = 0; i < D; ++i)
+                    y[i] = base[i] + ha[PC ? i : 0] * (C[i] + fP[i] * g2inv[PC ? i : 0]);
                 rhs_eval_forced<R, D>(p, y, force, fs);
                 const bool mine = lane == owner;
 #pragma unroll
@@ -271,18 +317,22 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
                     const int sl = ((q - jq - 1) % Q + Q) % Q;
 #pragma unroll
                     for (int i = 0; i < D; ++i) {
-                        accP[q][i] = fma(rbc[sl], fs[i], accP[q][i]);
-                        accC[q][i] = fma(rac[sl], fs[i], accC[q][i]);
-                        nxtP[q][i] = fma(rbn[sl], fs[i], nxtP[q][i]);
-                        nxtC[q][i] = fma(ran[sl], fs[i], nxtC[q][i]);
+                        const int w = PC ? i : 0;
+                        accP[q][i] = fma(rbc[w][sl], fs[i], accP[q][i]);
+                        accC[q][i] = fma(rac[w][sl], fs[i], accC[q][i]);
+                        nxtP[q][i] = fma(rbn[w][sl], fs[i], nxtP[q][i]);
+                        nxtC[q][i] = fma(ran[w][sl], fs[i], nxtC[q][i]);
                     }
                 }
                 // slide the rings: x = r0 - r - 2 replaces x = r0 - r - 2 + Q
                 const int sn = ((-jq - 2) % Q + Q) % Q;
-                rbc[sn] = nbc;
-                rac[sn] = nac;
-                rbn[sn] = nbn;
-                ran[sn] = nan_;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    rbc[w][sn] = nbc[w];
+                    rac[w][sn] = nac[w];
+                    rbn[w][sn] = nbn[w];
+                    ran[w][sn] = nan_[w];
+                }
             }
         }
     }
@@ -314,25 +364,30 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
     if (bad) raise_status(status, kStatusNonFinite);
 }
 
-template <int R, int D, int L, int W>
+template <int R, int D, int L, int W, bool PC>
 __global__ __launch_bounds__(64 * W) void k_chain(const GroupDev* __restrict__ groups,
                                                const ChainItem* __restrict__ items, int nitems,
                                                uint32_t* status)
 {
-    extern __shared__ double smc[];           // per wave: b[0..2L), a[0..2L)
+    extern __shared__ double smc[];           // per wave and table: b[0..2L), a[0..2L)
+    constexpr int NW = PC ? D : 1;
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     const int j = blockIdx.x * W + wid;
     if (j >= nitems) return;                  // whole wave: no barrier below
     const ChainItem it = items[j];
-    chain_block<R, D, L>(groups[it.group], it, smc + (size_t)wid * 4 * L, lane, status);
+    chain_block<R, D, L, PC>(groups[it.group], it, smc + (size_t)wid * NW * 4 * L, lane, status);
 }
 
-// Items of several right-hand sides in one launch (each wave switches on its
-// item's): chains of different systems then run side by side in one kernel.
-template <int L, int W>
+// Items of several kinds in one launch (each wave switches on its item's):
+// chains of different systems then run side by side in one kernel.  Each
+// wave owns wave_lds doubles of LDS (4L per weight table of the largest kind
+// in the launch).  NW3: the three-table kind (per-component Lorenz) is
+// compiled in; at L = 512 it would make every kind's kernel spill, so it has
+// an instantiation of its own there.
+template <int L, int W, bool NW3>
 __global__ __launch_bounds__(64 * W) void k_chain_mixed(const GroupDev* __restrict__ groups,
                                                      const ChainItem* __restrict__ items,
-                                                     int nitems, uint32_t* status)
+                                                     int nitems, int wave_lds, uint32_t* status)
 {
     extern __shared__ double smc[];
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -340,51 +395,65 @@ __global__ __launch_bounds__(64 * W) void k_chain_mixed(const GroupDev* __restri
     if (j >= nitems) return;
     const ChainItem it = items[j];
     const GroupDev& G = groups[it.group];
-    double* smw = smc + (size_t)wid * 4 * L;
-    switch (it.rhs) {
-    case ABM_RHS_LINEAR: chain_block<ABM_RHS_LINEAR, 1, L>(G, it, smw, lane, status); break;
-    case ABM_RHS_DUFFING: chain_block<ABM_RHS_DUFFING, 2, L>(G, it, smw, lane, status); break;
-    case ABM_RHS_LORENZ: chain_block<ABM_RHS_LORENZ, 3, L>(G, it, smw, lane, status); break;
-    case ABM_RHS_POLY: chain_block<ABM_RHS_POLY, 1, L>(G, it, smw, lane, status); break;
-    case ABM_RHS_LCR: chain_block<ABM_RHS_LCR, 2, L>(G, it, smw, lane, status); break;
+    double* smw = smc + (size_t)wid * wave_lds;
+    constexpr int P = kRhsCount;
+    switch (it.kind) {
+    case ABM_RHS_LINEAR: chain_block<ABM_RHS_LINEAR, 1, L, false>(G, it, smw, lane, status); break;
+    case ABM_RHS_DUFFING: chain_block<ABM_RHS_DUFFING, 2, L, false>(G, it, smw, lane, status); break;
+    case ABM_RHS_LORENZ: chain_block<ABM_RHS_LORENZ, 3, L, false>(G, it, smw, lane, status); break;
+    case ABM_RHS_POLY: chain_block<ABM_RHS_POLY, 1, L, false>(G, it, smw, lane, status); break;
+    case ABM_RHS_LCR: chain_block<ABM_RHS_LCR, 2, L, false>(G, it, smw, lane, status); break;
+    case ABM_RHS_DIAG: chain_block<ABM_RHS_DIAG, 2, L, false>(G, it, smw, lane, status); break;
+    case P + ABM_RHS_DUFFING: chain_block<ABM_RHS_DUFFING, 2, L, true>(G, it, smw, lane, status); break;
+    case P + ABM_RHS_LORENZ:
+        if constexpr (NW3) chain_block<ABM_RHS_LORENZ, 3, L, true>(G, it, smw, lane, status);
+        break;
+    case P + ABM_RHS_LCR: chain_block<ABM_RHS_LCR, 2, L, true>(G, it, smw, lane, status); break;
+    case P + ABM_RHS_DIAG: chain_block<ABM_RHS_DIAG, 2, L, true>(G, it, smw, lane, status); break;
     default: break;   // validated on the host
     }
 }
 
-template <int L, int W>
-hipError_t launch_mixed_l(const GroupDev* groups, const ChainItem* items, int n, uint32_t* status,
-                          hipStream_t st)
+template <int L, int W, bool NW3>
+hipError_t launch_mixed_l(const GroupDev* groups, const ChainItem* items, int n, int nw,
+                          uint32_t* status, hipStream_t st)
 {
+    if (nw > (NW3 ? 3 : 2)) return hipErrorInvalidValue;
     const dim3 grid((unsigned)((n + W - 1) / W));
-    const size_t shmem = (size_t)W * 4 * L * sizeof(double);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_chain_mixed<L, W>), shmem);
+    const int wave_lds = nw * 4 * L;
+    const size_t shmem = (size_t)W * wave_lds * sizeof(double);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_chain_mixed<L, W, NW3>), shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_chain_mixed<L, W>), grid, dim3(64 * W), shmem, st, groups, items, n, status);
+    hipLaunchKernelGGL((k_chain_mixed<L, W, NW3>), grid, dim3(64 * W), shmem, st, groups, items, n,
+                       wave_lds, status);
     return hipGetLastError();
 }
 
-template <int R, int D, int L, int W>
+template <int R, int D, int L, int W, bool PC>
 hipError_t launch_rdl(const GroupDev* groups, const ChainItem* items, int n, uint32_t* status,
                       hipStream_t st)
 {
     const dim3 grid((unsigned)((n + W - 1) / W));
-    const size_t shmem = (size_t)W * 4 * L * sizeof(double);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_chain<R, D, L, W>), shmem);
+    const size_t shmem = (size_t)W * (PC ? D : 1) * 4 * L * sizeof(double);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_chain<R, D, L, W, PC>), shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_chain<R, D, L, W>), grid, dim3(64 * W), shmem, st, groups, items, n, status);
+    hipLaunchKernelGGL((k_chain<R, D, L, W, PC>), grid, dim3(64 * W), shmem, st, groups, items, n,
+                       status);
     return hipGetLastError();
 }
 
-template <int R, int D>
+// Waves per workgroup: two per SIMD where the registers allow it, and the
+// weight windows of all waves within the CU's LDS.
+template <int R, int D, bool PC>
 hipError_t launch_rd(const GroupDev* groups, const ChainItem* items, int n, int L, uint32_t* status,
                      hipStream_t st)
 {
+    constexpr bool big = D > 2 || PC;   // more than half a SIMD's registers at L = 256
     switch (L) {
-    case 64: return launch_rdl<R, D, 64, 8>(groups, items, n, status, st);
-    case 128: return launch_rdl<R, D, 128, 8>(groups, items, n, status, st);
-    // three components at L = 256 need more than half a SIMD's registers
-    case 256: return launch_rdl<R, D, 256, (D <= 2 ? 8 : 4)>(groups, items, n, status, st);
-    case 512: return launch_rdl<R, D, 512, 4>(groups, items, n, status, st);   // one wave per SIMD fits
+    case 64: return launch_rdl<R, D, 64, 8, PC>(groups, items, n, status, st);
+    case 128: return launch_rdl<R, D, 128, 8, PC>(groups, items, n, status, st);
+    case 256: return launch_rdl<R, D, 256, (big ? 4 : 8), PC>(groups, items, n, status, st);
+    case 512: return launch_rdl<R, D, 512, (PC && D > 2 ? 2 : 4), PC>(groups, items, n, status, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -423,29 +492,45 @@ hipError_t launch_init_rd(const GroupDev* groups, const ChainItem* items, int n,
 }  // namespace
 
 hipError_t launch_chain_mixed(const GroupDev* groups, const ChainItem* items, int n, int L,
-                              uint32_t* status, hipStream_t st)
+                              int nw, uint32_t* status, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    // register demand is the largest system's (three components)
+    if (nw < 1 || nw > 3) return hipErrorInvalidValue;
+    // register demand is the largest system's (three components); the LDS
+    // of nw weight tables per wave must fit the CU
     switch (L) {
-    case 64: return launch_mixed_l<64, 8>(groups, items, n, status, st);
-    case 128: return launch_mixed_l<128, 8>(groups, items, n, status, st);
-    case 256: return launch_mixed_l<256, 4>(groups, items, n, status, st);
-    case 512: return launch_mixed_l<512, 4>(groups, items, n, status, st);
+    case 64: return launch_mixed_l<64, 8, true>(groups, items, n, nw, status, st);
+    case 128: return launch_mixed_l<128, 8, true>(groups, items, n, nw, status, st);
+    case 256: return launch_mixed_l<256, 4, true>(groups, items, n, nw, status, st);
+    case 512:
+        return nw <= 2 ? launch_mixed_l<512, 4, false>(groups, items, n, nw, status, st)
+                       : launch_mixed_l<512, 2, true>(groups, items, n, nw, status, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_chain(const GroupDev* groups, const ChainItem* items, int n, int rhs, int L,
+int chain_tables(int kind)
+{
+    if (kind < kRhsCount) return 1;
+    return kind - kRhsCount == ABM_RHS_LORENZ ? 3 : 2;
+}
+
+hipError_t launch_chain(const GroupDev* groups, const ChainItem* items, int n, int kind, int L,
                         uint32_t* status, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
-    switch (rhs) {
-    case ABM_RHS_LINEAR: return launch_rd<ABM_RHS_LINEAR, 1>(groups, items, n, L, status, st);
-    case ABM_RHS_DUFFING: return launch_rd<ABM_RHS_DUFFING, 2>(groups, items, n, L, status, st);
-    case ABM_RHS_LORENZ: return launch_rd<ABM_RHS_LORENZ, 3>(groups, items, n, L, status, st);
-    case ABM_RHS_POLY: return launch_rd<ABM_RHS_POLY, 1>(groups, items, n, L, status, st);
-    case ABM_RHS_LCR: return launch_rd<ABM_RHS_LCR, 2>(groups, items, n, L, status, st);
+    constexpr int P = kRhsCount;
+    switch (kind) {
+    case ABM_RHS_LINEAR: return launch_rd<ABM_RHS_LINEAR, 1, false>(groups, items, n, L, status, st);
+    case ABM_RHS_DUFFING: return launch_rd<ABM_RHS_DUFFING, 2, false>(groups, items, n, L, status, st);
+    case ABM_RHS_LORENZ: return launch_rd<ABM_RHS_LORENZ, 3, false>(groups, items, n, L, status, st);
+    case ABM_RHS_POLY: return launch_rd<ABM_RHS_POLY, 1, false>(groups, items, n, L, status, st);
+    case ABM_RHS_LCR: return launch_rd<ABM_RHS_LCR, 2, false>(groups, items, n, L, status, st);
+    case ABM_RHS_DIAG: return launch_rd<ABM_RHS_DIAG, 2, false>(groups, items, n, L, status, st);
+    case P + ABM_RHS_DUFFING: return launch_rd<ABM_RHS_DUFFING, 2, true>(groups, items, n, L, status, st);
+    case P + ABM_RHS_LORENZ: return launch_rd<ABM_RHS_LORENZ, 3, true>(groups, items, n, L, status, st);
+    case P + ABM_RHS_LCR: return launch_rd<ABM_RHS_LCR, 2, true>(groups, items, n, L, status, st);
+    case P + ABM_RHS_DIAG: return launch_rd<ABM_RHS_DIAG, 2, true>(groups, items, n, L, status, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -460,6 +545,7 @@ hipError_t launch_chain_init(const GroupDev* groups, const ChainItem* items, int
     case ABM_RHS_LORENZ: return launch_init_rd<ABM_RHS_LORENZ, 3>(groups, items, n, st);
     case ABM_RHS_POLY: return launch_init_rd<ABM_RHS_POLY, 1>(groups, items, n, st);
     case ABM_RHS_LCR: return launch_init_rd<ABM_RHS_LCR, 2>(groups, items, n, st);
+    case ABM_RHS_DIAG: return launch_init_rd<ABM_RHS_DIAG, 2>(groups, items, n, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -36,18 +36,23 @@ __device__ __forceinline__ bool far_view(const GroupDev* __restrict__ groups,
     const FarItem it = items[blockIdx.z];
     if ((int)blockIdx.x >= it.ncoltiles || (int)blockIdx.y >= it.nsplit) return false;
     const GroupDev& G = groups[it.group];
-    A.b = as_global(G.b);
-    A.a = as_global(G.a);
-    A.b32 = as_global(G.b32);
-    A.a32 = as_global(G.a32);
+    const CompWeights& W = G.w[it.comp];
+    A.b = as_global(W.b);
+    A.a = as_global(W.a);
+    A.b32 = as_global(W.b32);
+    A.a32 = as_global(W.a32);
+    // the item's columns start at coff (a multiple of 16): every layout of
+    // the history and of the partial slices is shifted by whole columns or
+    // whole 16-column blocks
+    const int64_t coff = it.coff;
 #pragma unroll
     for (int i = 0; i < 3; ++i) {
-        A.bh[i] = as_global(G.bh[i]);
-        A.ah[i] = as_global(G.ah[i]);
-        A.Fh[i] = as_global((const uint16_t*)G.Fh[i]);
+        A.bh[i] = as_global(W.bh[i]);
+        A.ah[i] = as_global(W.ah[i]);
+        A.Fh[i] = G.Fh[i] ? as_global((const uint16_t*)G.Fh[i]) + coff * 8 : nullptr;
     }
-    A.F = as_global((const double*)G.F);
-    A.F32 = as_global((const float*)G.F32);
+    A.F = as_global((const double*)G.F) + coff;
+    A.F32 = G.F32 ? as_global((const float*)G.F32) + (coff >> 4) * G.rows * 16 : nullptr;
     A.ldF = G.ldF;
     A.rows = G.rows;
     A.mL = it.mL;
@@ -55,7 +60,7 @@ __device__ __forceinline__ bool far_view(const GroupDev* __restrict__ groups,
     A.kchunk = kchunk;
     A.nchunks = it.nchunks;
     A.chunks_per_split = it.chunks_per_split;
-    A.part = as_global(G.part[(it.mL / L) & 1]);
+    A.part = as_global(G.part[(it.mL / L) & 1]) + coff * (2 * L);
     A.ldP = it.ldP;
     return true;
 }

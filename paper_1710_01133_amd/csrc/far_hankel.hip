@@ -49,16 +49,16 @@ constexpr int hist_stride() { return 17 * (kDch + L / 16 - 1); }
 constexpr int kWlen = 16 * kDch + 16;
 
 template <typename T>
-__device__ __forceinline__ const T* hk_weights(const GroupDev& G, bool corr);
+__device__ __forceinline__ const T* hk_weights(const CompWeights& W, bool corr);
 template <>
-__device__ __forceinline__ const float* hk_weights<float>(const GroupDev& G, bool corr)
+__device__ __forceinline__ const float* hk_weights<float>(const CompWeights& W, bool corr)
 {
-    return corr ? G.a32 : G.b32;
+    return corr ? W.a32 : W.b32;
 }
 template <>
-__device__ __forceinline__ const double* hk_weights<double>(const GroupDev& G, bool corr)
+__device__ __forceinline__ const double* hk_weights<double>(const CompWeights& W, bool corr)
 {
-    return corr ? G.a : G.b;
+    return corr ? W.a : W.b;
 }
 template <typename T>
 __device__ __forceinline__ const T* hk_history(const GroupDev& G);
@@ -96,16 +96,17 @@ __device__ __forceinline__ void hankel_body(const GroupDev& G, const FarItem& it
     constexpr bool kFloat = sizeof(T) == 4;
     typedef typename std::conditional<kFloat, f4, d4>::type acc_t;
 
-    const int ncols = (int)it.ldP;
+    const int ncols = it.ncols;
     // floor(e / ncols) = (e * inv_cols) >> 20 for every staged e (e < 2^17,
     // ncols <= 8; checked exhaustively)
     const unsigned inv_cols = (1u << 20) / (unsigned)ncols + 1u;
     const int64_t K = it.kfar, mL = it.mL;
     const int64_t dmin = 1 - K / 16;
     const int64_t ndelta = K / 16 + R - 1;
-    const gptr<const T> wbg = as_global(hk_weights<T>(G, false));
-    const gptr<const T> wag = as_global(hk_weights<T>(G, true));
-    const gptr<const T> hist = as_global(hk_history<T>(G));
+    // the item's columns start at coff (time-major history: a plain shift)
+    const gptr<const T> wbg = as_global(hk_weights<T>(G.w[it.comp], false));
+    const gptr<const T> wag = as_global(hk_weights<T>(G.w[it.comp], true));
+    const gptr<const T> hist = as_global(hk_history<T>(G)) + it.coff;
     const int64_t ldF = G.ldF;
 
     T* sw = reinterpret_cast<T*>(hk_smem);    // [2][kWlen] predictor, corrector weights
@@ -233,7 +234,8 @@ __device__ __forceinline__ void hankel_body(const GroupDev& G, const FarItem& it
     // reduce the four waves' sums (wave order 0..3) and store: tile q is the
     // predictor tile q (q < TMAX) or the corrector tile q - TMAX
     double* red = reinterpret_cast<double*>(hk_smem);   // [kRedSlots][kHWaves][64][4]
-    const gptr<double> out = as_global(G.part[(mL / L) & 1]) + (size_t)blockIdx.y * it.ldP * (2 * L);
+    const gptr<double> out = as_global(G.part[(mL / L) & 1]) +
+                             ((size_t)it.coff + (size_t)blockIdx.y * it.ldP) * (2 * L);
 #pragma unroll
     for (int q0 = 0; q0 < 2 * TMAX; q0 += kRedSlots) {
         __syncthreads();   // LDS free (staging or the previous round)

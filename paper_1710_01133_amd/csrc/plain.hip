@@ -29,23 +29,36 @@ constexpr int kCh = 256;          // history indices per chunk (= threads per wo
 constexpr int kPartStride = 8;    // doubles per partial slot (2d <= 6 used)
 constexpr size_t kPlainLds = 160 * 1024 - 256;   // LDS of one gfx950 CU, less the static flag
 
-template <int R, int D>
+// PC: the components have orders of their own (a weight table each);
+// otherwise every component uses component 0's table.
+template <int R, int D, bool PC>
 __global__ __launch_bounds__(256) void k_plain(PlainArgs A)
 {
     extern __shared__ double sm[];
     double* Fl = sm;                                   // [nloc][256][D] history slice
     double* red = sm + (size_t)A.nloc * kCh * D;       // [4][2D] per-wave partials
     __shared__ int s_abort;
+    constexpr int NW = PC ? D : 1;                     // weight tables in use
 
     const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int G = A.G;
     const int64_t N = A.N;
-    const double ha = pow(A.h, A.alpha);
-    const double g2 = A.gam[1];
-
-    double x0[D], F0[D];
+    double ha[D], g2[D];
+    bool deriv[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) x0[i] = A.x0[i];
+    for (int i = 0; i < D; ++i) {
+        const int w = PC ? i : 0;
+        ha[i] = pow(A.h, A.alpha[w]);
+        g2[i] = A.gam[w][1];
+        deriv[i] = A.alpha[w] > 1.0;
+    }
+
+    double x0[D], x1[D], F0[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        x0[i] = A.x0[i];
+        x1[i] = A.x1[i];
+    }
     rhs_eval<R, D>(A.p, 0.0, x0, F0);
 
     if (t == 0) s_abort = 0;
@@ -67,13 +80,17 @@ __global__ __launch_bounds__(256) void k_plain(PlainArgs A)
         for (int lc = 0; lc < A.nloc; ++lc) {
             const int64_t k = (int64_t)(g + lc * G) * kCh + t;
             if (k > n) break;               // later local chunks lie further out
-            const double wb = A.b[n - k];
-            const double wa = (k >= 1) ? A.a[n - k] : 0.0;   // k = 0 enters through c_n
+            double wb[NW], wa[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                wb[w] = A.b[w][n - k];
+                wa[w] = (k >= 1) ? A.a[w][n - k] : 0.0;   // k = 0 enters through c_n
+            }
             const double* f = Fl + ((size_t)lc * kCh + t) * D;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                P[i] = fma(wb, f[i], P[i]);
-                C[i] = fma(wa, f[i], C[i]);
+                P[i] = fma(wb[PC ? i : 0], f[i], P[i]);
+                C[i] = fma(wa[PC ? i : 0], f[i], C[i]);
             }
         }
         // workgroup partial: wavefront butterfly, then the 4 waves in order
@@ -119,15 +136,22 @@ __global__ __launch_bounds__(256) void k_plain(PlainArgs A)
                 for (int q = lane; q < G; q += kWave) acc += slot_base[(size_t)q * kPartStride + j];
                 tot[j] = wave_sum(acc);
             }
-            // predictor / corrector (eq. abm and the corrector after it)
+            // predictor / corrector (eq. abm and the corrector after it),
+            // from the start term x0 (+ t x1 for orders above 1)
             const double td = (double)s * A.h;
-            const double cn = A.c[n];
+            double base[D], cn[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                base[i] = deriv[i] ? x0[i] + td * x1[i] : x0[i];
+                cn[i] = A.c[PC ? i : 0][n];
+            }
             double yP[D], fP[D], y[D], fs[D];
 #pragma unroll
-            for (int i = 0; i < D; ++i) yP[i] = x0[i] + ha * tot[i];
+            for (int i = 0; i < D; ++i) yP[i] = base[i] + ha[i] * tot[i];
             rhs_eval<R, D>(A.p, td, yP, fP);
 #pragma unroll
-            for (int i = 0; i < D; ++i) y[i] = x0[i] + ha * ((tot[D + i] + cn * F0[i]) + fP[i] / g2);
+            for (int i = 0; i < D; ++i)
+                y[i] = base[i] + ha[i] * ((tot[D + i] + cn[i] * F0[i]) + fP[i] / g2[i]);
             rhs_eval<R, D>(A.p, td, y, fs);
             if (lane == 0) {
                 if (s < N) {
@@ -162,15 +186,15 @@ __global__ __launch_bounds__(256) void k_plain(PlainArgs A)
     }
 }
 
-template <int R, int D>
+template <int R, int D, bool PC>
 hipError_t launch_plain_t(const PlainArgs& A, hipStream_t st)
 {
     const size_t shmem = ((size_t)A.nloc * kCh * D + 4 * 2 * D) * sizeof(double);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_plain<R, D>), shmem);
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_plain<R, D, PC>), shmem);
     if (e != hipSuccess) return e;
     PlainArgs a = A;
     void* args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plain<R, D>), dim3(A.G),
+    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plain<R, D, PC>), dim3(A.G),
                                       dim3(kCh), args, (unsigned)shmem, st);
 }
 
@@ -186,14 +210,19 @@ int plain_chunk() { return kCh; }
 
 int plain_part_doubles(int G) { return 2 * G * kPartStride; }
 
-hipError_t launch_plain(const PlainArgs& A, int rhs, hipStream_t st)
+hipError_t launch_plain(const PlainArgs& A, int kind, hipStream_t st)
 {
-    switch (rhs) {
-    case ABM_RHS_LINEAR: return launch_plain_t<ABM_RHS_LINEAR, 1>(A, st);
-    case ABM_RHS_DUFFING: return launch_plain_t<ABM_RHS_DUFFING, 2>(A, st);
-    case ABM_RHS_LORENZ: return launch_plain_t<ABM_RHS_LORENZ, 3>(A, st);
-    case ABM_RHS_POLY: return launch_plain_t<ABM_RHS_POLY, 1>(A, st);
-    case ABM_RHS_LCR: return launch_plain_t<ABM_RHS_LCR, 2>(A, st);
+    switch (kind) {
+    case ABM_RHS_LINEAR: return launch_plain_t<ABM_RHS_LINEAR, 1, false>(A, st);
+    case ABM_RHS_DUFFING: return launch_plain_t<ABM_RHS_DUFFING, 2, false>(A, st);
+    case ABM_RHS_LORENZ: return launch_plain_t<ABM_RHS_LORENZ, 3, false>(A, st);
+    case ABM_RHS_POLY: return launch_plain_t<ABM_RHS_POLY, 1, false>(A, st);
+    case ABM_RHS_LCR: return launch_plain_t<ABM_RHS_LCR, 2, false>(A, st);
+    case ABM_RHS_DIAG: return launch_plain_t<ABM_RHS_DIAG, 2, false>(A, st);
+    case kRhsCount + ABM_RHS_DUFFING: return launch_plain_t<ABM_RHS_DUFFING, 2, true>(A, st);
+    case kRhsCount + ABM_RHS_LORENZ: return launch_plain_t<ABM_RHS_LORENZ, 3, true>(A, st);
+    case kRhsCount + ABM_RHS_LCR: return launch_plain_t<ABM_RHS_LCR, 2, true>(A, st);
+    case kRhsCount + ABM_RHS_DIAG: return launch_plain_t<ABM_RHS_DIAG, 2, true>(A, st);
     default: return hipErrorInvalidValue;
     }
 }

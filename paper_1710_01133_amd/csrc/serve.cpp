@@ -5,7 +5,8 @@
 // as its device footprint (weight tables, history and its reduced copy,
 // carried sums, far partials) fits the free arena memory, so admission is
 // FIFO and never over-commits the arena.  Every admitted request is a group
-// of one trajectory with its own weight table.  The server advances all
+// of one trajectory with its own weight tables (one per distinct order of
+// its components).  The server advances all
 // admitted requests in ticks, exactly like abm_solve_batch: one far-field
 // launch per precision class and one chain launch per right-hand side per
 // tick cover every active request, whatever its alpha, N or start time;
@@ -36,6 +37,7 @@ namespace abm {
 namespace {
 
 constexpr int kMaxActive = 1024;     // group slots on the device
+constexpr int kMaxFar = 4 * kMaxActive;   // far items per tick (one per component at most)
 constexpr int kRing = 8;             // ticks in flight (item staging ring)
 constexpr size_t kAlign = 256;
 
@@ -59,7 +61,7 @@ struct Request {
     // device side (valid while running)
     size_t off = 0, bytes = 0;        // arena chunk
     int slot = -1;
-    WeightTable W{};
+    WeightTable W[4] = {};            // one per distinct order
     Group g{};
     int64_t m = 0, nblocks = 0;
     bool finishing = false;           // last work enqueued; waiting for done_ev
@@ -94,7 +96,7 @@ struct ServeState {
     hipStream_t s0 = nullptr, s1 = nullptr;
     GroupDev* groups_dev = nullptr;
     GroupDev* groups_host = nullptr;      // pinned staging, one entry per slot
-    FarItem* far_dev = nullptr;           // [kRing][kMaxActive]
+    FarItem* far_dev = nullptr;           // [kRing][kMaxFar]
     ChainItem* chain_dev = nullptr;       // [kRing][kMaxActive]
     ChainItem* init_dev = nullptr;        // [kRing][kMaxActive]
     FarItem* far_host = nullptr;
@@ -145,38 +147,66 @@ void arena_free(ServeState* S, size_t off, size_t bytes)
 }
 
 // Layout of one request's arena chunk (all offsets 256-byte aligned).
+struct TableLayout {
+    double alpha;
+    size_t gam, b, a, c, b32, a32, bh[3], ah[3];
+};
 struct ReqLayout {
-    size_t gam, b, a, c, b32, a32, bh[3], ah[3], F, F32, Fh[3], traj, accn, part, total;
-    int64_t wn, rows, ldF;
+    TableLayout tab[4];
+    int ntab;
+    int tab_of[4];                    // table of each component
+    size_t F, F32, Fh[3], traj, accn, part, total;
+    int64_t wn, rows, ldF, ldC;
     size_t part_half;
-    bool narrow;
+    bool narrow, per_comp;
 };
 
 ReqLayout layout_of(const abm_problem& p, int L, int kchunk, int max_split)
 {
     ReqLayout r{};
-    const int TN = far_tile_cols(L, p.far_prec);
     r.wn = p.N + kWeightPad;
     r.rows = p.N + 1 + L;
     r.narrow = env_int("ABM_NARROW", 1) != 0 && hankel_fits(p.far_prec, p.d, L);
-    r.ldF = r.narrow ? p.d : (p.d + TN - 1) / TN * TN;
+    r.per_comp = orders_differ(p);
+    {
+        Group g{};                    // the column layout of a one-member group
+        g.members = {0};
+        g.d = p.d;
+        g.prec = p.far_prec;
+        g.narrow = r.narrow;
+        g.per_comp = r.per_comp;
+        group_layout(g, L);
+        r.ldF = g.ldF;
+        r.ldC = g.ldC;
+    }
     size_t o = 0;
     auto take = [&](size_t bytes) { const size_t at = o; o += align_up(bytes); return at; };
-    r.gam = take(2 * sizeof(double));
-    r.b = take(r.wn * sizeof(double));
-    r.a = take(r.wn * sizeof(double));
-    r.c = take(r.wn * sizeof(double));
-    r.b32 = r.a32 = 0;
-    for (int i = 0; i < 3; ++i) r.bh[i] = r.ah[i] = r.Fh[i] = 0;
-    if (p.far_prec == ABM_FAR_FP32) {
-        r.b32 = take(r.wn * sizeof(float));
-        r.a32 = take(r.wn * sizeof(float));
-    } else if (p.far_prec != ABM_FAR_FP64) {
-        for (int i = 0; i < 3; ++i) {
-            r.bh[i] = take(r.wn * sizeof(uint16_t));
-            r.ah[i] = take(r.wn * sizeof(uint16_t));
+    r.ntab = 0;
+    for (int c = 0; c < 4; ++c) {
+        const double al = order_of(p, c < p.d ? c : 0);
+        int t = 0;
+        while (t < r.ntab && r.tab[t].alpha != al) ++t;
+        r.tab_of[c] = t;
+        if (t < r.ntab) continue;
+        TableLayout& T = r.tab[r.ntab++];
+        T.alpha = al;
+        T.gam = take(2 * sizeof(double));
+        T.b = take(r.wn * sizeof(double));
+        T.a = take(r.wn * sizeof(double));
+        T.c = take(r.wn * sizeof(double));
+        T.b32 = T.a32 = 0;
+        for (int i = 0; i < 3; ++i) T.bh[i] = T.ah[i] = 0;
+        if (p.far_prec == ABM_FAR_FP32) {
+            T.b32 = take(r.wn * sizeof(float));
+            T.a32 = take(r.wn * sizeof(float));
+        } else if (p.far_prec != ABM_FAR_FP64) {
+            for (int i = 0; i < 3; ++i) {
+                T.bh[i] = take(r.wn * sizeof(uint16_t));
+                T.ah[i] = take(r.wn * sizeof(uint16_t));
+            }
         }
     }
+    for (int i = 0; i < 3; ++i) r.Fh[i] = 0;
     r.F = take((size_t)r.rows * r.ldF * sizeof(double));
     r.F32 = 0;
     if (p.far_prec == ABM_FAR_FP32) r.F32 = take((size_t)r.rows * r.ldF * sizeof(float));
@@ -236,13 +266,13 @@ abm_status server_init(ServeState* S)
 
     abm_status s;
     if ((s = dev_alloc((void**)&S->groups_dev, kMaxActive * sizeof(GroupDev), "group slots")) ||
-        (s = dev_alloc((void**)&S->far_dev, (size_t)kRing * kMaxActive * sizeof(FarItem), "far ring")) ||
+        (s = dev_alloc((void**)&S->far_dev, (size_t)kRing * kMaxFar * sizeof(FarItem), "far ring")) ||
         (s = dev_alloc((void**)&S->chain_dev, (size_t)kRing * kMaxActive * sizeof(ChainItem), "chain ring")) ||
         (s = dev_alloc((void**)&S->init_dev, (size_t)kRing * kMaxActive * sizeof(ChainItem), "init ring")) ||
         (s = dev_alloc((void**)&S->status, sizeof(uint32_t), "status")))
         return s;
     if ((e = hipHostMalloc((void**)&S->groups_host, kMaxActive * sizeof(GroupDev), hipHostMallocDefault)) ||
-        (e = hipHostMalloc((void**)&S->far_host, (size_t)kRing * kMaxActive * sizeof(FarItem), hipHostMallocDefault)) ||
+        (e = hipHostMalloc((void**)&S->far_host, (size_t)kRing * kMaxFar * sizeof(FarItem), hipHostMallocDefault)) ||
         (e = hipHostMalloc((void**)&S->chain_host, (size_t)kRing * kMaxActive * sizeof(ChainItem), hipHostMallocDefault)) ||
         (e = hipHostMalloc((void**)&S->init_host, (size_t)kRing * kMaxActive * sizeof(ChainItem), hipHostMallocDefault)))
         return hip_fail(e, "pinned staging");
@@ -268,30 +298,34 @@ abm_status admit(ServeState* S, Request* r, size_t off, const ReqLayout& lay)
     r->bytes = lay.total;
     r->slot = S->free_slots.back();
     S->free_slots.pop_back();
-    WeightTable& W = r->W;
-    W.alpha = p.alpha;
-    W.n = p.N;
-    W.gam = (double*)(base + lay.gam);
-    W.b = (double*)(base + lay.b);
-    W.a = (double*)(base + lay.a);
-    W.c = (double*)(base + lay.c);
-    W.b32 = lay.b32 ? (float*)(base + lay.b32) : nullptr;
-    W.a32 = lay.a32 ? (float*)(base + lay.a32) : nullptr;
-    for (int i = 0; i < 3; ++i) {
-        W.bh[i] = lay.bh[i] ? (uint16_t*)(base + lay.bh[i]) : nullptr;
-        W.ah[i] = lay.ah[i] ? (uint16_t*)(base + lay.ah[i]) : nullptr;
+    for (int t = 0; t < lay.ntab; ++t) {
+        const TableLayout& T = lay.tab[t];
+        WeightTable& W = r->W[t];
+        W.alpha = T.alpha;
+        W.n = p.N;
+        W.gam = (double*)(base + T.gam);
+        W.b = (double*)(base + T.b);
+        W.a = (double*)(base + T.a);
+        W.c = (double*)(base + T.c);
+        W.b32 = T.b32 ? (float*)(base + T.b32) : nullptr;
+        W.a32 = T.a32 ? (float*)(base + T.a32) : nullptr;
+        for (int i = 0; i < 3; ++i) {
+            W.bh[i] = T.bh[i] ? (uint16_t*)(base + T.bh[i]) : nullptr;
+            W.ah[i] = T.ah[i] ? (uint16_t*)(base + T.ah[i]) : nullptr;
+        }
     }
     Group& g = r->g;
-    g.table = 0;
+    for (int c = 0; c < 4; ++c) g.table[c] = lay.tab_of[c];
+    g.per_comp = lay.per_comp;
+    g.deriv = deriv_mask(p);
     g.rhs = p.rhs;
     g.d = p.d;
     g.prec = p.far_prec;
     g.nmax = p.N;
     g.members = {0};
-    g.col0 = {0};
-    g.cols = p.d;
     g.narrow = lay.narrow;
-    g.ldF = lay.ldF;
+    group_layout(g, S->L);
+    if (g.ldF != lay.ldF || g.ldC != lay.ldC) return fail(ABM_EDEVICE, "internal: request layout");
     g.rows = lay.rows;
     g.F = (double*)(base + lay.F);
     g.F32 = lay.F32 ? (float*)(base + lay.F32) : nullptr;
@@ -305,29 +339,39 @@ abm_status admit(ServeState* S, Request* r, size_t off, const ReqLayout& lay)
     r->m = 0;
     r->nblocks = (p.N + S->L - 1) / S->L;
 
-    hipError_t e = launch_weights(p.alpha, lay.wn, W.gam, W.b, W.a, W.c, S->s0);
-    if (e == hipSuccess && (W.b32 || W.bh[0]))
-        e = launch_weights_lowp(lay.wn, W.b, W.a, W.b32, W.a32, W.bh, W.ah, S->s0);
+    hipError_t e = hipSuccess;
+    for (int t = 0; t < lay.ntab && e == hipSuccess; ++t) {
+        WeightTable& W = r->W[t];
+        e = launch_weights(W.alpha, lay.wn, W.gam, W.b, W.a, W.c, S->s0);
+        if (e == hipSuccess && (W.b32 || W.bh[0]))
+            e = launch_weights_lowp(lay.wn, W.b, W.a, W.b32, W.a32, W.bh, W.ah, S->s0);
+    }
     if (e != hipSuccess) return hip_fail(e, "request weights");
     // descriptor and group slot through pinned staging (the slot's staging
     // entry is only rewritten when the slot is reused, long after this copy)
     if ((e = hipHostMalloc((void**)&r->final_host, 4 * sizeof(double) + sizeof(TrajDesc),
                            hipHostMallocDefault)) != hipSuccess)
         return hip_fail(e, "pinned staging");
-    GroupDev gd = group_dev(g, W);
+    const WeightTable* Wc[4];
+    for (int c = 0; c < 4; ++c) Wc[c] = &r->W[lay.tab_of[c]];
+    GroupDev gd = group_dev(g, Wc);
     S->groups_host[r->slot] = gd;
     if ((e = hipMemcpyAsync(&S->groups_dev[r->slot], &S->groups_host[r->slot], sizeof(GroupDev),
                             hipMemcpyHostToDevice, S->s0)) != hipSuccess)
         return hip_fail(e, "slot upload");
     TrajDesc& T = *reinterpret_cast<TrajDesc*>(r->final_host + 4);
     memset(&T, 0, sizeof T);
-    for (int i = 0; i < 4; ++i) T.x0[i] = p.x0[i];
+    for (int i = 0; i < 4; ++i) {
+        T.x0[i] = p.x0[i];
+        T.x1[i] = p.x1[i];
+    }
     for (int i = 0; i < 8; ++i) T.p[i] = p.p[i];
     T.h = p.h;
     T.N = p.N;
     T.out_stride = p.out_stride;
     T.y_out = r->y_out;
-    T.col0 = 0;
+    T.col0 = g.col0[0];
+    T.cstride = (int32_t)g.ldC;
     if ((e = hipMemcpyAsync(g.traj_dev, &T, sizeof T, hipMemcpyHostToDevice, S->s0)) != hipSuccess)
         return hip_fail(e, "descriptor upload");
     if ((e = hipEventCreateWithFlags(&r->done_ev, hipEventDisableTiming)) != hipSuccess)
@@ -353,26 +397,30 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
     hipError_t e;
     if (S->ring_live[ring] && (e = hipEventSynchronize(S->ring_ev[ring])) != hipSuccess)
         return hip_fail(e, "ring wait");
-    FarItem* fh = S->far_host + (size_t)ring * kMaxActive;
+    FarItem* fh = S->far_host + (size_t)ring * kMaxFar;
     ChainItem* ch = S->chain_host + (size_t)ring * kMaxActive;
     ChainItem* ih = S->init_host + (size_t)ring * kMaxActive;
-    // items grouped by class: far by launch class, chain and init by rhs
+    // items grouped by class: far by launch class, chain by kind, init by rhs
     std::vector<FarItem> far[kFarClasses];
-    std::vector<ChainItem> chain[5], init[5];
+    std::vector<ChainItem> chain[kChainKinds], init[kRhsCount];
     for (Request* r : S->active) {
         if (r->finishing || r->cancel_seen) continue;
         const std::vector<int64_t> memberN{r->prob.N};
         const int cls = far_class(r->g.prec, r->g.narrow);
-        const size_t f0 = far[cls].size(), c0 = chain[r->g.rhs].size();
+        const int kind = chain_kind(r->g.rhs, r->g.per_comp);
+        const size_t f0 = far[cls].size(), c0 = chain[kind].size();
         block_items(r->g, r->slot, r->m, S->L, S->kchunk, S->max_split, memberN,
-                    &far[cls], &chain[r->g.rhs]);
+                    &far[cls], &chain[kind]);
         // every item must fit the request's partial buffers (checked, not assumed)
-        for (size_t k = f0; k < far[cls].size(); ++k)
-            if (far[cls][k].nsplit > r->g.nsplit_cap || far[cls][k].ldP > r->g.ldF ||
-                (r->g.narrow && !hankel_fits(r->g.prec, far[cls][k].ldP, S->L)))
+        for (size_t k = f0; k < far[cls].size(); ++k) {
+            const FarItem& it = far[cls][k];
+            if (it.nsplit > r->g.nsplit_cap || it.ldP > r->g.ldF ||
+                it.coff + (int64_t)it.ncols > r->g.ldF ||
+                (r->g.narrow && !hankel_fits(r->g.prec, it.ncols, S->L)))
                 return fail(ABM_EDEVICE, "internal: far item exceeds a request's partial buffer");
-        for (size_t k = c0; k < chain[r->g.rhs].size(); ++k)
-            if (chain[r->g.rhs][k].nsplit > r->g.nsplit_cap)
+        }
+        for (size_t k = c0; k < chain[kind].size(); ++k)
+            if (chain[kind][k].nsplit > r->g.nsplit_cap)
                 return fail(ABM_EDEVICE, "internal: chain item exceeds a request's partial buffer");
     }
     for (Request* r : fresh) {
@@ -382,7 +430,12 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
         init[r->g.rhs].push_back(c);
     }
     int nf = 0, nc = 0, ni = 0;
-    Span fsp[kFarClasses], csp[5], isp[5];
+    size_t nfar = 0, nchain = 0;
+    for (const auto& v : far) nfar += v.size();
+    for (const auto& v : chain) nchain += v.size();
+    if (nfar > (size_t)kMaxFar || nchain > (size_t)kMaxActive)
+        return fail(ABM_EDEVICE, "internal: more items than the staging ring holds");
+    Span fsp[kFarClasses], csp[kChainKinds], isp[kRhsCount];
     for (int k = 0; k < kFarClasses; ++k) {
         fsp[k].offset = nf;
         fsp[k].count = (int32_t)far[k].size();
@@ -392,15 +445,17 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
             fh[nf++] = it;
         }
     }
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < kChainKinds; ++k) {
         csp[k].offset = nc;
         csp[k].count = (int32_t)chain[k].size();
         for (const ChainItem& it : chain[k]) ch[nc++] = it;
+    }
+    for (int k = 0; k < kRhsCount; ++k) {
         isp[k].offset = ni;
         isp[k].count = (int32_t)init[k].size();
         for (const ChainItem& it : init[k]) ih[ni++] = it;
     }
-    FarItem* fd = S->far_dev + (size_t)ring * kMaxActive;
+    FarItem* fd = S->far_dev + (size_t)ring * kMaxFar;
     ChainItem* cd = S->chain_dev + (size_t)ring * kMaxActive;
     ChainItem* id = S->init_dev + (size_t)ring * kMaxActive;
     // items reach s1 through s0: upload on s0, then s1 waits for it
@@ -429,20 +484,24 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
     }
     if (S->ev_far_prev && (e = hipStreamWaitEvent(S->s0, S->ev_far_prev, 0)) != hipSuccess)
         return hip_fail(e, "wait");
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < kRhsCount; ++k) {
         if (isp[k].count &&
             (e = launch_chain_init(S->groups_dev, id + isp[k].offset, isp[k].count, k, S->s0)) != hipSuccess)
             return hip_fail(e, "init launch");
     }
-    // chains of every right-hand side: one launch (one kernel switching per
-    // wave when the tick mixes systems), so they run side by side
-    int nrhs = 0;
-    for (int k = 0; k < 5; ++k) nrhs += csp[k].count ? 1 : 0;
-    if (nrhs > 1) {
-        if ((e = launch_chain_mixed(S->groups_dev, cd, nc, S->L, S->status, S->s0)) != hipSuccess)
+    // chains of every kind: one launch (one kernel switching per wave when
+    // the tick mixes systems), so they run side by side
+    int nkind = 0, nw = 1;
+    for (int k = 0; k < kChainKinds; ++k)
+        if (csp[k].count) {
+            ++nkind;
+            nw = std::max(nw, chain_tables(k));
+        }
+    if (nkind > 1) {
+        if ((e = launch_chain_mixed(S->groups_dev, cd, nc, S->L, nw, S->status, S->s0)) != hipSuccess)
             return hip_fail(e, "chain launch");
     } else {
-        for (int k = 0; k < 5; ++k) {
+        for (int k = 0; k < kChainKinds; ++k) {
             if (csp[k].count &&
                 (e = launch_chain(S->groups_dev, cd + csp[k].offset, csp[k].count, k, S->L, S->status,
                                   S->s0)) != hipSuccess)

@@ -24,25 +24,26 @@ three-dimensional chaotic system):
 from __future__ import annotations
 
 from dataclasses import dataclass, field
-from typing import List, Tuple
+from typing import List, Optional, Tuple, Union
 
 import numpy as np
 
 SEED = 1710
 
-RHS_NAMES = ("LINEAR", "DUFFING", "LORENZ", "POLY", "LCR")
-RHS_DIM = {"LINEAR": 1, "DUFFING": 2, "LORENZ": 3, "POLY": 1, "LCR": 2}
+RHS_NAMES = ("LINEAR", "DUFFING", "LORENZ", "POLY", "LCR", "DIAG")
+RHS_DIM = {"LINEAR": 1, "DUFFING": 2, "LORENZ": 3, "POLY": 1, "LCR": 2, "DIAG": 2}
 
 
 @dataclass
 class Problem:
     rhs: str                      # one of RHS_NAMES
-    alpha: float                  # 0 < alpha <= 1
+    alpha: Union[float, Tuple[float, ...]]   # order in (0, 2], or one per component
     h: float                      # step size
     N: int                        # number of steps
     x0: Tuple[float, ...]         # initial state, length d
     p: Tuple[float, ...] = field(default_factory=tuple)   # rhs parameters
     far_prec: str = "fp64"        # far-field precision: fp64 | fp32 | bf16x3 | bf16x6
+    x1: Optional[Tuple[float, ...]] = None   # y'(0), for components of order above 1
 
     @property
     def d(self) -> int:

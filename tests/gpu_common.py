@@ -9,7 +9,7 @@ import oracle as O
 from paper_1710_01133_amd import abm
 
 RID = {"LINEAR": O.RHS_LINEAR, "DUFFING": O.RHS_DUFFING, "LORENZ": O.RHS_LORENZ,
-       "POLY": O.RHS_POLY, "LCR": O.RHS_LCR}
+       "POLY": O.RHS_POLY, "LCR": O.RHS_LCR, "DIAG": O.RHS_DIAG}
 
 # Parity bar of the double-precision GPU path against the oracle: normwise
 # relative error max_s |y_s - yref_s|_inf / max_s |yref_s|_inf.  Both sides
@@ -21,7 +21,7 @@ GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "ora
 
 
 def oracle_run(p, stride):
-    return O.solve(RID[p.rhs], p.alpha, p.h, p.N, p.x0, p.p, out_stride=stride)
+    return O.solve(RID[p.rhs], p.alpha, p.h, p.N, p.x0, p.p, out_stride=stride, x1=p.x1)
 
 
 def normerr(y, ref):

@@ -1,0 +1,243 @@
+"""GPU parity of per-component orders (incommensurate systems, eq. sys.LRC with
+alpha_1 != alpha_2) and of orders in (1, 2] (start term x0 + t x1 of eq. abm)
+against the CPU oracle, through the C ABI: the weight kernel above order 1,
+the plain path, the blocked path (column tiles and blocked convolution, every
+block length, mixed with commensurate groups in one launch, reduced
+far-field precisions), graph replay and the serving loop.
+
+The forced LCR circuit is chaotic at some forcings (the numerical experiment
+reports chaotic attractors near F = 0.117), so its runs here stay within a
+time span where the oracle's own rounding noise (a 1e-15 change of x0, or
+compensated summation) moves the trajectory by less than 1e-13: h = 0.01 and
+t <= 36.  Orders above 1 carry weights that grow like k^(alpha - 1), which
+raises that noise floor with t; their runs keep it near 1e-13 as well."""
+import time
+
+import numpy as np
+import pytest
+
+import oracle as O
+from paper_1710_01133_amd import abm, inputs
+from gpu_common import TOL_FP64, normerr, oracle_run, run_batch, run_plain
+
+pytestmark = pytest.mark.gpu
+
+TOL_LOWP = 1e-6      # float / bf16x6 far field, double near band and state
+
+LCR = inputs.LCR_P   # sigma, omega, a, b (forcing F appended)
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.init()
+    c = abm.Context(0)
+    yield c
+    c.close()
+
+
+# ------------------------------------------------------------------ weights
+@pytest.mark.parametrize("alpha", [1.25, 1.5, 1.9, 2.0])
+def test_device_weights_above_one(ctx, alpha):
+    N = 300000
+    p = inputs.Problem("LINEAR", alpha, 0.01, N, (1.0,), (1.0,), x1=(0.0,))
+    plan = abm.Plan(ctx, [p])
+    b, a, c = plan.weights(0, N)
+    for lo, n in ((0, 4000), (N - 2000, 2000)):
+        ob, oa, oc = O.weights(alpha, n, k0=lo)
+        for dev, ref in ((b, ob), (a, oa), (c, oc)):
+            rel = np.max(np.abs(dev[lo:lo + n] - ref) / np.abs(ref))
+            assert rel <= 1.2e-15, (alpha, lo, rel)
+    plan.close()
+
+
+# ------------------------------------------------------------------ plain path
+PLAIN_CASES = [
+    ("lcr_incommensurate", inputs.Problem("LCR", (0.9, 0.8), 0.01, 0, (1.2, -0.4), LCR + (0.117,))),
+    ("lorenz_three_orders", inputs.Problem("LORENZ", (0.95, 0.9, 0.85), 2 ** -8, 0, (1.0, 1.0, 1.0),
+                                           inputs.LORENZ_P)),
+    ("diag_uncoupled", inputs.Problem("DIAG", (0.6, 0.95), 1 / 64, 0, (1.0, -0.5),
+                                      (1.3, 0.7, 0.2, -0.1))),
+    ("linear_1.5", inputs.Problem("LINEAR", 1.5, 1 / 64, 0, (1.0,), (1.0,), x1=(0.5,))),
+    ("lcr_1.1_0.9", inputs.Problem("LCR", (1.1, 0.9), 0.01, 0, (1.2, -0.4), LCR + (0.117,),
+                                   x1=(0.1, 0.0))),
+    ("duffing_1.05_0.95", inputs.Problem("DUFFING", (1.05, 0.95), 1e-2, 0, (0.1, 0.0),
+                                         (0.1, 0.45, 1.2), x1=(0.2, 0.0))),
+    ("diag_2.0_1.7", inputs.Problem("DIAG", (2.0, 1.7), 1 / 64, 0, (1.0, 0.0),
+                                    (1.0, 2.0, 0.0, 0.3), x1=(0.0, 1.0))),
+]
+
+
+def _with_N(p, N, prec=None):
+    return inputs.Problem(p.rhs, p.alpha, p.h, N, p.x0, p.p, prec or p.far_prec, p.x1)
+
+
+@pytest.mark.parametrize("N", [1, 257, 2000])
+@pytest.mark.parametrize("name,proto", PLAIN_CASES, ids=[c[0] for c in PLAIN_CASES])
+def test_plain_general_orders(ctx, name, proto, N):
+    p = _with_N(proto, N)
+    print("plain", name, N, flush=True)
+    y = run_plain(ctx, p, 1)
+    assert normerr(y, oracle_run(p, 1)) <= TOL_FP64
+
+
+# ------------------------------------------------------------------ blocked path
+def _lcr_sweep(n, alphas, prec, N0, seed, x1=None):
+    """n forced LCR circuits, F uniform in [0, 0.2] (the bifurcation sweep of
+    the numerical experiment), h = 0.01, lengths N0 .. N0 + 600 (ragged)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(n):
+        F = float(rng.uniform(0.0, 0.2))
+        N = N0 + int(rng.integers(0, 600))
+        out.append(inputs.Problem("LCR", alphas, 0.01, N, (1.2, -0.4), LCR + (F,), prec, x1))
+    return out
+
+
+def _mix(prec, N0=1500, seed=7):
+    probs = _lcr_sweep(40, (0.9, 0.8), prec, N0, seed)                 # wide, per-component
+    probs += _lcr_sweep(8, 0.9, prec, N0, seed + 1)                    # commensurate
+    probs.append(inputs.Problem("LORENZ", (0.95, 0.9, 0.85), 2 ** -8, N0 + 11, (1.0, 1.0, 1.0),
+                                inputs.LORENZ_P, prec))
+    probs.append(inputs.Problem("LORENZ", (0.95, 0.9, 0.85), 2 ** -8, N0 - 300, (1.0, -1.0, 2.0),
+                                inputs.LORENZ_P, prec))
+    probs.append(inputs.Problem("LORENZ", (0.95, 0.9, 0.85), 2 ** -8, 700, (-1.0, 1.0, 3.0),
+                                inputs.LORENZ_P, prec))
+    for A in (0.2, 0.45):
+        probs.append(inputs.Problem("DUFFING", (1.05, 0.95), 1e-2, N0 + 77, (0.1, 0.0),
+                                    (0.1, A, 1.2), prec, x1=(0.2, 0.0)))
+    probs += _lcr_sweep(3, (1.1, 0.9), prec, N0, seed + 2, x1=(0.1, 0.0))
+    probs.append(inputs.Problem("LINEAR", 1.5, 1 / 64, N0 + 5, (1.0,), (1.0,), prec, x1=(0.5,)))
+    probs.append(inputs.Problem("DIAG", (0.6, 0.95), 1 / 64, N0 - 33, (1.0, -0.5),
+                                (1.3, 0.7, 0.2, -0.1), prec))
+    return probs
+
+
+@pytest.mark.parametrize("L", [128, 256, 512])
+def test_batch_general_orders_fp64(ctx, L, monkeypatch):
+    monkeypatch.setenv("ABM_BLOCK_L", str(L))
+    monkeypatch.setenv("ABM_KCHUNK", "512")
+    monkeypatch.setenv("ABM_MAX_SPLIT", "3")
+    probs = _mix("fp64")
+    print("batch fp64 L", L, flush=True)
+    outs, st = run_batch(ctx, probs, 3)
+    assert st["narrow_groups"] >= 2
+    for p, y in zip(probs, outs):
+        e = normerr(y, oracle_run(p, 3))
+        assert e <= TOL_FP64, (p.rhs, p.alpha, p.N, e)
+
+
+def test_batch_general_orders_column_tiles_only(ctx, monkeypatch):
+    monkeypatch.setenv("ABM_BLOCK_L", "256")
+    monkeypatch.setenv("ABM_NARROW", "0")
+    probs = _mix("fp64", seed=8)
+    outs, st = run_batch(ctx, probs, 0)
+    assert st["narrow_groups"] == 0
+    for p, y in zip(probs, outs):
+        e = normerr(y, oracle_run(p, 0))
+        assert e <= TOL_FP64, (p.rhs, p.alpha, p.N, e)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+def test_batch_general_orders_reduced_precision(ctx, prec, monkeypatch):
+    monkeypatch.setenv("ABM_BLOCK_L", "256")
+    probs = _lcr_sweep(40, (0.9, 0.8), prec, 3000, 9) + _lcr_sweep(8, 0.9, prec, 3000, 10)
+    probs.append(inputs.Problem("DUFFING", (1.05, 0.95), 1e-2, 2500, (0.1, 0.0), (0.1, 0.3, 1.2),
+                                prec, x1=(0.2, 0.0)))
+    outs, _ = run_batch(ctx, probs, 5)
+    for p, y in zip(probs, outs):
+        e = normerr(y, oracle_run(p, 5))
+        assert e <= TOL_LOWP, (prec, p.alpha, p.N, e)
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("fp32", TOL_LOWP)])
+def test_single_incommensurate_trajectory_narrow_vs_tiles(ctx, prec, tol, monkeypatch):
+    """One LCR circuit with alpha_1 != alpha_2: its far field runs as the
+    blocked convolution, one item per component, and as column tiles."""
+    monkeypatch.setenv("ABM_BLOCK_L", "256")
+    p = inputs.Problem("LCR", (0.9, 0.8), 0.01, 3600, (1.2, -0.4), LCR + (0.117,), prec)
+    ref = oracle_run(p, 1)
+    (yn,), st = run_batch(ctx, [p], 1)
+    assert st["narrow_groups"] == 1
+    monkeypatch.setenv("ABM_NARROW", "0")
+    (yt,), st = run_batch(ctx, [p], 1)
+    assert st["narrow_groups"] == 0
+    assert normerr(yn, ref) <= tol
+    assert normerr(yt, ref) <= tol
+    assert normerr(yn, yt) <= (1e-13 if prec == "fp64" else tol)
+
+
+def test_graph_replay_with_general_orders(ctx, monkeypatch):
+    monkeypatch.setenv("ABM_BLOCK_L", "128")
+    probs = _mix("fp64", N0=900, seed=12)
+    plan = abm.Plan(ctx, probs, out_stride=2)
+    ys = [abm.alloc_out(p, 2) for p in probs]
+    abm.solve_batch(plan, probs, ys)
+    plan.check()
+    eager = [y.cpu().numpy() for y in ys]
+    plan.graph(True)
+    for rep in range(3):
+        ys = [abm.alloc_out(p, 2) for p in probs]
+        abm.solve_batch(plan, probs, ys)
+        plan.check()
+        for y, r in zip(ys, eager):
+            assert np.array_equal(y.cpu().numpy(), r), rep
+    plan.close()
+    for p, r in zip(probs[::7], eager[::7]):
+        assert normerr(r, oracle_run(p, 2)) <= TOL_FP64
+
+
+def test_invalid_orders_rejected(ctx):
+    bad = [
+        inputs.Problem("LINEAR", 2.5, 0.01, 10, (1.0,), (1.0,)),
+        inputs.Problem("LCR", (0.9, 0.0), 0.01, 10, (1.0, 0.0), LCR + (0.1,)),
+        inputs.Problem("LCR", (0.9, 2.1), 0.01, 10, (1.0, 0.0), LCR + (0.1,)),
+        inputs.Problem("LINEAR", 1.5, 0.01, 10, (1.0,), (1.0,), x1=(float("nan"),)),
+    ]
+    for p in bad:
+        with pytest.raises(abm.AbmError) as ei:
+            abm.Plan(ctx, [p])
+        assert ei.value.code == abm.ABM_EINVAL
+    # a plan fixes the orders: a solve with other orders is refused
+    p = inputs.Problem("LCR", (0.9, 0.8), 0.05, 300, (1.2, -0.4), LCR + (0.1,))
+    q = inputs.Problem("LCR", (0.9, 0.7), 0.05, 300, (1.2, -0.4), LCR + (0.1,))
+    plan = abm.Plan(ctx, [p])
+    with pytest.raises(abm.AbmError):
+        abm.solve_batch(plan, [q], [abm.alloc_out(q, 0)])
+    plan.close()
+
+
+# ------------------------------------------------------------------ serving
+def test_served_general_orders_match_oracle(ctx):
+    import torch
+    sctx = abm.Context(0, arena_bytes=512 << 20)
+    probs = []
+    for prec in ("fp64", "fp32", "bf16x6"):
+        probs += [
+            inputs.Problem("LCR", (0.9, 0.8), 0.01, 3000, (1.2, -0.4), LCR + (0.117,), prec),
+            inputs.Problem("LORENZ", (0.95, 0.9, 0.85), 2 ** -8, 1700, (1.0, 1.0, 1.0),
+                           inputs.LORENZ_P, prec),
+            inputs.Problem("DUFFING", (1.05, 0.95), 1e-2, 2100, (0.1, 0.0), (0.1, 0.3, 1.2), prec,
+                           x1=(0.2, 0.0)),
+            inputs.Problem("DUFFING", 0.93, 2 ** -8, 2600, (0.1, 0.0), (0.1, 0.3, 1.2), prec),
+        ]
+    ys = [abm.alloc_out(p, 1) for p in probs]
+    tickets = [abm.submit(sctx, p, y, out_stride=1) for p, y in zip(probs, ys)]
+    done = {}
+    t0 = time.time()
+    while len(done) < len(tickets):
+        for t in tickets:
+            if t not in done:
+                r = abm.poll(sctx, t)
+                if r is not None:
+                    done[t] = r
+        assert time.time() - t0 < 120.0
+        time.sleep(0.002)
+    torch.cuda.synchronize()
+    for p, y, t in zip(probs, ys, tickets):
+        assert done[t]["status"] == abm.ABM_OK
+        tol = TOL_FP64 if p.far_prec == "fp64" else TOL_LOWP
+        e = normerr(y.cpu().numpy(), oracle_run(p, 1))
+        assert e <= tol, (p.rhs, p.alpha, p.far_prec, e)
+    sctx.close()

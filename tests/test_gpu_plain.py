@@ -108,7 +108,7 @@ def test_plain_rejects_mismatched_problem(ctx):
     with pytest.raises(abm.AbmError) as e:
         abm.solve(plan, q, y)
     assert e.value.code == abm.ABM_EINVAL
-    bad = inputs.Problem("DUFFING", 1.5, 0.01, 100, (0.1, 0.0), (0.1, 0.3, 1.2))
+    bad = inputs.Problem("DUFFING", 2.5, 0.01, 100, (0.1, 0.0), (0.1, 0.3, 1.2))
     with pytest.raises(abm.AbmError) as e:
         abm.Plan(ctx, [bad])
     assert e.value.code == abm.ABM_EINVAL
