@@ -182,6 +182,65 @@ __global__ __launch_bounds__(512, 1) void k_far_f32(const GroupDev* groups, cons
 }
 
 // ------------------------------------------------------------------ bf16 split
+// History stages of the bf16 kernels: two buffers of 128 rows x 16 columns x
+// up to 3 split terms.  A stage is copied from global memory straight into
+// LDS (no registers in between, which keeps the kernel within its register
+// budget).  The copy of stage st+1 is issued in the last product step of
+// stage st, after that step's LDS reads: the compiler makes every later LDS
+// read wait for the copy, and the next such read comes after the stage
+// barrier anyway, so the copy runs under the last step's products.
+constexpr int kBfStageRows = 128;
+constexpr int kBfStageU4 = 3 * (kBfStageRows / 8) * 16;   // 16-byte units per stage
+
+// Copy of one history stage (8-row blocks blk0 .. blk0 + NB8 - 1 of 16
+// columns from col0, TERMS split terms) into LDS at dst.  Unit
+// u = tt * NB8 * 16 + 16 b + c holds the 8 rows of block b, column c, term
+// tt; thread t copies units t, t + NTH, ...  A wave's 64 units are
+// consecutive, so each lane's 16 bytes land at (the wave's first unit +
+// lane), which is where the copy puts them.  Arguments by value: the term's
+// pointer is then a select among values (a select among addresses of the
+// caller's variables would move them to scratch memory).
+template <int TERMS, int NB8, int NTH>
+__device__ __forceinline__ void bf_dma_stage(gptr<const uint16_t> fh0, gptr<const uint16_t> fh1,
+                                             gptr<const uint16_t> fh2, int64_t ldF, int col0,
+                                             int64_t blk0, int t, u4* dst)
+{
+    constexpr int TN = 16, kTermU4 = NB8 * TN, kStageU4 = TERMS * kTermU4;
+    static_assert(kTermU4 % 64 == 0 && NTH % 64 == 0, "a wave copies whole 1 KiB runs");
+    const int lane = t & 63;
+#pragma unroll
+    for (int e = 0; e < (kStageU4 + NTH - 1) / NTH; ++e) {
+        const int u = t + e * NTH;
+        if (u - lane < kStageU4) {          // whole waves only
+            const int tt = u / kTermU4, rem = u % kTermU4;
+            const int b = rem / TN, c = rem % TN;
+            const gptr<const uint16_t> src =
+                (tt == 0 ? fh0 : (tt == 1 ? fh1 : fh2)) + ((blk0 + b) * ldF + col0 + c) * 8;
+            __builtin_amdgcn_global_load_lds((const ABM_GLOBAL void*)src,
+                                             (__attribute__((address_space(3))) void*)(dst + (u - lane)),
+                                             16, 0, 0);
+        }
+    }
+}
+
+// Wait for this wave's stage copies (vmcnt) after the products that produce
+// acc64: one element of every tile is an input of the wait.
+template <int MT>
+__device__ __forceinline__ void stage_wait(d4 (&acc64)[MT][1])
+{
+    static_assert(MT == 4 || MT == 8, "tiles per wave");
+    if constexpr (MT == 4) {
+        asm volatile("s_waitcnt vmcnt(0)" ::"v"(acc64[0][0][0]), "v"(acc64[1][0][0]),
+                     "v"(acc64[2][0][0]), "v"(acc64[3][0][0])
+                     : "memory");
+    } else {
+        asm volatile("s_waitcnt vmcnt(0)" ::"v"(acc64[0][0][0]), "v"(acc64[1][0][0]),
+                     "v"(acc64[2][0][0]), "v"(acc64[3][0][0]), "v"(acc64[4][0][0]),
+                     "v"(acc64[5][0][0]), "v"(acc64[6][0][0]), "v"(acc64[7][0][0])
+                     : "memory");
+    }
+}
+
 // MT row tiles per wave, WPR waves per row kind (predictor, corrector); with
 // 4 waves two workgroups share a CU, so each SIMD runs two waves.
 template <int MT, int TERMS, int WPR>
@@ -196,6 +255,7 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
     constexpr int KS = 32 * QS;                 // history rows per stage
     constexpr int NB8 = KS / 8;                 // 8-row blocks per stage
     constexpr int kStageU4 = TERMS * NB8 * TN;  // 16-byte units per stage
+    static_assert(KS == kBfStageRows && kStageU4 <= kBfStageU4, "stage buffers");
     static_assert((2 * QS) % MT == 0, "ring slots must repeat within a stage");
     extern __shared__ __attribute__((aligned(16))) uint16_t smh[];
     const int win = L + A.kchunk;               // multiple of 8
@@ -219,38 +279,7 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
         acc64[i][0] = d4{0.0, 0.0, 0.0, 0.0};
     }
 
-    constexpr int kPerThread = (kStageU4 + NTH - 1) / NTH;
-    u4 pre[kPerThread];
-    // split term of each staged element, chosen without indexing A.Fh by a
-    // per-thread value (which would move the descriptor to scratch memory)
-    gptr<const uint16_t> fsrc[kPerThread];
-    int64_t foff[kPerThread];
-#pragma unroll
-    for (int e = 0; e < kPerThread; ++e) {
-        const int idx = t + e * NTH;
-        const int tt = idx / (NB8 * TN);
-        const int rem = idx % (NB8 * TN);
-        const int b = rem / TN, c = rem % TN;
-        fsrc[e] = tt == 0 ? A.Fh[0] : (tt == 1 ? A.Fh[1] : A.Fh[TERMS - 1]);
-        foff[e] = (int64_t)b * A.ldF + col0 + c;
-    }
-    auto load_stage = [&](int64_t kb8, int st) {
-#pragma unroll
-        for (int e = 0; e < kPerThread; ++e) {
-            const int idx = t + e * NTH;
-            if (idx < kStageU4) {
-                const int64_t blk0 = kb8 + (int64_t)st * NB8;
-                pre[e] = *reinterpret_cast<const ABM_GLOBAL u4*>(fsrc[e] + (blk0 * A.ldF + foff[e]) * 8);
-            }
-        }
-    };
-    auto store_stage = [&](int buf) {
-#pragma unroll
-        for (int e = 0; e < kPerThread; ++e) {
-            const int idx = t + e * NTH;
-            if (idx < kStageU4) Bst[buf * kStageU4 + idx] = pre[e];
-        }
-    };
+    const gptr<const uint16_t> fh0 = A.Fh[0], fh1 = A.Fh[1], fh2 = A.Fh[TERMS - 1];
     auto afrag = [&](int tt, int v) -> bf8 {
         u4 x;
         __builtin_memcpy(&x, wr + tt * win + abase + 16 * v, 16);
@@ -273,9 +302,9 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
                 wra[tt * win + x] = A.ah[tt][j];
             }
         }
-        load_stage(kb8, 0);
-        store_stage(0);
-        __syncthreads();
+        bf_dma_stage<TERMS, NB8, NTH>(fh0, fh1, fh2, A.ldF, col0, kb8, t, Bst);
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's copies are in LDS
+        __syncthreads();                                      // and every other wave's
         // ring[tt][slot]: fragment v lives in slot v mod MT; start with v = -(MT-1) .. 0
         bf8 ring[TERMS][MT];
 #pragma unroll
@@ -286,7 +315,6 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
         const int nstages = cb.nk / KS;
         for (int st = 0; st < nstages; ++st) {
             const int buf = st & 1;
-            if (st + 1 < nstages) load_stage(kb8, st + 1);
             const u4* Bs = Bst + buf * kStageU4;
 #pragma unroll
             for (int qq = 0; qq < QS; ++qq) {
@@ -303,6 +331,11 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
 #pragma unroll
                 for (int tt = 0; tt < TERMS; ++tt)
                     bfr[tt] = __builtin_bit_cast(bf8, Bs[(tt * NB8 + 4 * qq + g) * TN + li]);
+                // the stage's last LDS reads are issued: copy the next stage
+                // into the other buffer (read by nobody since the last barrier)
+                if (qq == QS - 1 && st + 1 < nstages)
+                    bf_dma_stage<TERMS, NB8, NTH>(fh0, fh1, fh2, A.ldF, col0, kb8 + (int64_t)(st + 1) * NB8,
+                                                  t, Bst + (buf ^ 1) * kStageU4);
                 // Ordering fence (no instruction): this step's products take their
                 // history operands only after the previous step's double flush, so a
                 // single set of float accumulators is live.  Left alone, the compiler
@@ -330,7 +363,11 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
                 }
                 flush_acc<MT, 1>(acc, acc64);   // one 32-row step per float run
             }
-            if (st + 1 < nstages) store_stage(buf ^ 1);
+            // the next stage is in LDS; the wait takes every tile's sum as an
+            // operand so that the last step's products are issued before it
+            // (they would otherwise be scheduled after the barrier, leaving the
+            // copy nothing to overlap)
+            stage_wait<MT>(acc64);
             __syncthreads();
         }
     }
@@ -380,7 +417,7 @@ size_t far_lp_lds_bytes(int L, int kchunk, int prec)
     if (prec == ABM_FAR_FP32) return (2 * (size_t)(L + kchunk) + 2 * 32 * TN) * sizeof(float);
     const int terms = prec == ABM_FAR_BF16X3 ? 2 : 3;
     // reversed weight windows + two history stages of 128 rows
-    return 2 * (size_t)terms * (L + kchunk) * 2 + 2 * (size_t)terms * (128 / 8) * TN * 16;
+    return 2 * (size_t)terms * (L + kchunk) * 2 + 2 * (size_t)terms * (kBfStageRows / 8) * TN * 16;
 }
 
 hipError_t launch_far_lp(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
