@@ -39,7 +39,7 @@ DEFAULT_PREC = "bf16x6"
 
 def far_source_sha():
     h = hashlib.sha256()
-    for f in ("far.hip", "far_lp.hip"):
+    for f in ("far.hip", "far_lp.hip", "far_common.h"):
         with open(os.path.join(ROOT, "paper_1710_01133_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -162,8 +162,8 @@ def cpu_baseline(inputs, budget_s=20.0):
     import oracle as O
     nthr = O.num_threads()
     sweep = inputs.duffing_sweep()
-    # one trajectory takes ~7 s on one core: sample as many as there are threads
-    idx = list(range(nthr))
+    # one trajectory takes ~5 s on one core: two per thread
+    idx = list(range(2 * nthr))
     sample = [sweep[i] for i in idx]
     t0 = time.perf_counter()
     O.solve_batch([O.RHS_DUFFING] * len(sample), [p.alpha for p in sample],
@@ -241,6 +241,40 @@ def long_leg(abm, torch, inputs, ctx):
     return res
 
 
+def lcr_leg(abm, torch, inputs, ctx, steps=2):
+    """The paper's own workload: the forced fractional LCR circuit swept over
+    its forcing F in [0, 0.2] (B = 1024, N = 65536), commensurate orders
+    (0.9, 0.9) as in its figures and incommensurate (0.9, 0.8), writing the
+    stroboscopic (Poincare) section y(kT) (every 1142nd state, h = T/1142).
+    Error against the oracle on the section points of the first 3600 steps of
+    two members (the circuit is chaotic at some F, so later points measure
+    the dynamics' amplification of rounding, not the method)."""
+    import oracle as O
+    M = inputs.LCR_SECTION_STEPS
+    res = {"workload": "forced fractional LCR circuit, sigma=1.015, omega=0.55, a=-1.02, "
+                       "b=-0.58, B=1024 forcings F in [0, 0.2], N=65536, h=T/1142, "
+                       "Poincare section output (stride 1142)"}
+    for al in ((0.9, 0.9), (0.9, 0.8)):
+        for pr in ("bf16x6", "fp64"):
+            probs = inputs.lcr_sweep(alpha=al, far_prec=pr)
+            plan = abm.Plan(ctx, probs, out_stride=M)
+            plan.graph(True)
+            ys = [abm.alloc_out(p, M) for p in probs]
+            dt, st = time_batch(abm, torch, plan, probs, ys, steps, 1)
+            errs = []
+            for i in (300, 700):
+                p = probs[i]
+                ref = O.solve(O.RHS_LCR, p.alpha, p.h, 3600, p.x0, p.p, out_stride=M)
+                y = ys[i].cpu().numpy()[: ref.shape[0] - 1]
+                errs.append(normerr(y, ref[:-1]))
+            res["alpha=%s,%s %s" % (al[0], al[1], pr)] = {
+                "ms_per_step": dt * 1e3, "history_macs_per_s": st["history_macs"] / dt,
+                "section_points_per_member": int(ys[0].shape[0]),
+                "max_rel_err_vs_oracle_first_3600_steps": max(errs)}
+            plan.close()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -259,6 +293,8 @@ def main():
     ap.add_argument("--no-precisions", action="store_true",
                     help="skip the sweep at the other far-field precisions")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-lcr", action="store_true",
+                    help="skip the LCR forcing sweep (the paper's workload)")
     ap.add_argument("--no-long", action="store_true",
                     help="skip the 1e6 / 3e6-step single-trajectory runs")
     ap.add_argument("--tune-budget", type=float, default=20.0,
@@ -347,6 +383,7 @@ def main():
 
     plain = None if args.no_plain else plain_leg(abm, torch, inputs, ctx)
     longrun = None if args.no_long else long_leg(abm, torch, inputs, ctx)
+    lcr = None if args.no_lcr else lcr_leg(abm, torch, inputs, ctx)
     small = small_batch_leg(abm, torch, inputs, ctx)
 
     serve = None
@@ -399,6 +436,7 @@ def main():
         "eager_ms_per_step": None if eager_dt is None else eager_dt * 1e3,
         "launch_bound_batch": small,
         "long_trajectory": longrun,
+        "lcr_sweep": lcr,
         "max_rel_err_vs_oracle": max_err,
         "err_members": errs,
         "plan_seconds": plan_s,

@@ -16,6 +16,12 @@ three-dimensional chaotic system):
 * ``duffing_sweep``   B=1024 copies of that oscillator with forcing amplitude
   drawn uniform in [0.1, 0.6] (numpy PCG64, seed 1710), alpha=0.95, h=2^-8,
   N=65536.
+* ``lcr_sweep``   the numerical experiment's forced fractional LCR circuit
+  (sigma=1.015, omega=0.55, a=-1.02, b=-0.58, x0=(0.1, 0)) at B forcing
+  amplitudes F evenly spaced in [0, 0.2] (the bifurcation parameter of its
+  figures), orders (0.9, 0.9) or incommensurate (alpha_1, alpha_2), step
+  h = T/M with T = 2 pi / omega and M = 1142 (h ~ 0.01), so that writing every
+  M-th state gives the stroboscopic (Poincare) section y(kT), N=65536.
 * ``serving_stream``  Poisson arrivals (rate 200/s, seed 1710) of requests,
   half Duffing (d=2) and half Lorenz (sigma=10, rho=28, beta=8/3, x0=(1,1,1),
   d=3), alpha uniform in [0.90, 0.99], N log-uniform in [4096, 262144],
@@ -68,6 +74,9 @@ def duffing_single(N: int = 200000, h: float = 1e-3, alpha: float = 0.9, A: floa
     return Problem("DUFFING", alpha, h, N, (0.1, 0.0), (DUFFING_P[0], A, DUFFING_P[2]))
 
 
+LCR_SECTION_STEPS = 1142               # steps per forcing period of the LCR sweep
+
+
 def sweep_amplitudes(B: int = 1024, seed: int = SEED) -> np.ndarray:
     return np.random.default_rng(seed).uniform(0.1, 0.6, B)
 
@@ -79,11 +88,20 @@ def duffing_sweep(B: int = 1024, N: int = 65536, h: float = 2.0 ** -8, alpha: fl
                     far_prec) for A in amps]
 
 
-def lcr_sweep(B: int, N: int, h: float, alpha: float = 0.9, f_lo: float = 0.0,
-              f_hi: float = 0.2, x0=(0.1, 0.0), far_prec: str = "fp64") -> List[Problem]:
-    """Forcing sweep of the fractional LCR circuit (eq. sys.LRC), evenly spaced f."""
+def lcr_section_step(M: int = LCR_SECTION_STEPS) -> float:
+    """Step that puts M steps in one forcing period T = 2 pi / omega."""
+    return 2.0 * np.pi / LCR_P[1] / M
+
+
+def lcr_sweep(B: int = 1024, N: int = 65536, h: float = None, alpha=(0.9, 0.9),
+              f_lo: float = 0.0, f_hi: float = 0.2, x0=(0.1, 0.0),
+              far_prec: str = "fp64") -> List[Problem]:
+    """Forcing sweep of the fractional LCR circuit (eq. sys.LRC), evenly spaced
+    F; h defaults to lcr_section_step()."""
+    h = lcr_section_step() if h is None else h
     fs = np.linspace(f_lo, f_hi, B) if B > 1 else np.array([f_lo])
-    return [Problem("LCR", alpha, h, N, tuple(x0), LCR_P + (float(f),), far_prec) for f in fs]
+    al = tuple(alpha) if isinstance(alpha, (tuple, list)) else alpha
+    return [Problem("LCR", al, h, N, tuple(x0), LCR_P + (float(f),), far_prec) for f in fs]
 
 
 @dataclass
