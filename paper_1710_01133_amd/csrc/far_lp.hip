@@ -258,10 +258,15 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
     static_assert(KS == kBfStageRows && kStageU4 <= kBfStageU4, "stage buffers");
     static_assert((2 * QS) % MT == 0, "ring slots must repeat within a stage");
     extern __shared__ __attribute__((aligned(16))) uint16_t smh[];
+    // Reversed weight windows, two copies each: copy 1 is copy 0 shifted by
+    // one element.  A fragment starts at an element offset whose parity is
+    // fixed per lane; read from the copy where that offset is even, every
+    // 16-byte fragment read is 4-byte aligned (2-byte aligned reads stall
+    // the LDS pipeline).
     const int win = L + A.kchunk;               // multiple of 8
-    uint16_t* wrb = smh;                        // [TERMS][win] reversed b windows
-    uint16_t* wra = smh + TERMS * win;          // [TERMS][win] reversed a windows
-    u4* Bst = reinterpret_cast<u4*>(smh + 2 * TERMS * win);   // [2][TERMS][NB8][TN]
+    uint16_t* wrb = smh;                        // [TERMS][2][win] reversed b windows
+    uint16_t* wra = smh + 2 * TERMS * win;      // [TERMS][2][win] reversed a windows
+    u4* Bst = reinterpret_cast<u4*>(smh + 4 * TERMS * win);   // [2][TERMS][NB8][TN]
 
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int col0 = blockIdx.x * TN;
@@ -270,6 +275,8 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
     const uint16_t* wr = corr ? wra : wrb;
     const int li = lane & 15, g = lane >> 4;
     const int abase = L - 1 - rbase - li + 8 * g;   // fragment v starts at abase + 16 v
+    const int par = abase & 1;                       // copy read by this lane
+    const uint16_t* wrl = wr + par * win + (abase - par);
 
     f4 acc[MT][1];
     d4 acc64[MT][1];
@@ -280,9 +287,15 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
     }
 
     const gptr<const uint16_t> fh0 = A.Fh[0], fh1 = A.Fh[1], fh2 = A.Fh[TERMS - 1];
+    // a fragment as dword reads (dword-aligned through the copy choice): one
+    // 16-byte read at a dword, not 16-byte, boundary would take the LDS's
+    // unaligned path
+    const uint32_t* wrd = reinterpret_cast<const uint32_t*>(wrl);
     auto afrag = [&](int tt, int v) -> bf8 {
+        const uint32_t* q = wrd + tt * win + 8 * v;
         u4 x;
-        __builtin_memcpy(&x, wr + tt * win + abase + 16 * v, 16);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) x[k] = q[k];
         return __builtin_bit_cast(bf8, x);
     };
 
@@ -293,13 +306,16 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
         const ChunkBounds cb = chunk_bounds(A, L, chunk);
         const int64_t kb8 = (cb.k_lo - 1) >> 3;
         __syncthreads();   // previous chunk's readers are done with the LDS
-        // reversed windows: wr[x] = w[jb + wlen - 1 - x]
+        // reversed windows: copy 0 holds w[jb + wlen - 1 - x], copy 1
+        // w[jb + wlen - 2 - x] (jb >= L, so the index stays >= 0)
         for (int x = t; x < cb.wlen; x += NTH) {
             const int64_t j = cb.jb + cb.wlen - 1 - x;
 #pragma unroll
             for (int tt = 0; tt < TERMS; ++tt) {
-                wrb[tt * win + x] = A.bh[tt][j];
-                wra[tt * win + x] = A.ah[tt][j];
+                wrb[2 * tt * win + x] = A.bh[tt][j];
+                wrb[(2 * tt + 1) * win + x] = A.bh[tt][j - 1];
+                wra[2 * tt * win + x] = A.ah[tt][j];
+                wra[(2 * tt + 1) * win + x] = A.ah[tt][j - 1];
             }
         }
         bf_dma_stage<TERMS, NB8, NTH>(fh0, fh1, fh2, A.ldF, col0, kb8, t, Bst);
@@ -416,8 +432,8 @@ size_t far_lp_lds_bytes(int L, int kchunk, int prec)
     const int TN = 16;
     if (prec == ABM_FAR_FP32) return (2 * (size_t)(L + kchunk) + 2 * 32 * TN) * sizeof(float);
     const int terms = prec == ABM_FAR_BF16X3 ? 2 : 3;
-    // reversed weight windows + two history stages of 128 rows
-    return 2 * (size_t)terms * (L + kchunk) * 2 + 2 * (size_t)terms * (kBfStageRows / 8) * TN * 16;
+    // reversed weight windows (two copies) + two history stages of 128 rows
+    return 4 * (size_t)terms * (L + kchunk) * 2 + 2 * (size_t)terms * (kBfStageRows / 8) * TN * 16;
 }
 
 hipError_t launch_far_lp(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
