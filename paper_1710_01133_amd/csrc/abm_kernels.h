@@ -172,9 +172,11 @@ hipError_t launch_far_hankel(const GroupDev* groups, const FarItem* items, int n
                              int max_nsplit, int L, int prec, hipStream_t st);
 
 // ---- K3: near band + predictor/corrector chain -----------------------------
-// One wave per item; all items of a launch share the chain kind.
+// One wave per item; all items of a launch share the chain kind.  spread:
+// one wave per SIMD instead of two (more CUs, faster chains, less room for
+// a far-field launch running beside them).
 hipError_t launch_chain(const GroupDev* groups, const ChainItem* items, int n, int kind, int L,
-                        uint32_t* status, hipStream_t st);
+                        bool spread, uint32_t* status, hipStream_t st);
 // Items of any kinds in one launch (one kernel for all systems); nw is the
 // largest chain_tables over the kinds of the items.
 hipError_t launch_chain_mixed(const GroupDev* groups, const ChainItem* items, int n, int L,

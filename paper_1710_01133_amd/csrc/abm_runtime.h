@@ -113,7 +113,8 @@ struct abm_plan_s {
     abm::ChainItem* init_items_dev = nullptr;
     int64_t ticks = 0;
     std::vector<abm::Span> far_spans;     // [tick][far launch class]
-    std::vector<abm::Span> chain_spans;   // [tick][rhs]
+    std::vector<abm::Span> chain_spans;   // [tick][chain kind]
+    std::vector<char> chain_spread;       // [tick]: chains one wave per SIMD (small far field beside)
     std::vector<abm::Span> init_spans;    // [rhs]
     int64_t far_macs = 0;
     // far field on its own stream, overlapping the chain

@@ -436,15 +436,33 @@ abm_status batch_setup(abm_plan_s* pl)
         (e = hipMemcpy(pl->chain_items_dev, chain_all.data(), chain_all.size() * sizeof(ChainItem), hipMemcpyHostToDevice)) ||
         (e = hipMemcpy(pl->init_items_dev, init_all.data(), init_all.size() * sizeof(ChainItem), hipMemcpyHostToDevice)))
         return hip_fail(e, "schedule upload");
-    // useful far-field MACs of the schedule (reported in abm_stats)
+    // useful far-field MACs of the schedule (reported in abm_stats), per tick
     pl->far_macs = 0;
-    for (const FarItem& it : far_all) {
-        const Group& g = pl->groups[it.group];
-        for (int64_t N : memberN[it.group]) {
-            if (N <= it.mL) continue;
-            pl->far_macs += (int64_t)(g.per_comp ? 1 : g.d) * std::min<int64_t>(L, N - it.mL) * it.kfar;
+    std::vector<int64_t> tick_macs(ticks, 0);
+    for (int64_t t = 0; t < ticks; ++t)
+        for (int cls = 0; cls < kFarClasses; ++cls) {
+            const Span& sp = pl->far_spans[t * kFarClasses + cls];
+            for (int64_t k = sp.offset; k < sp.offset + sp.count; ++k) {
+                const FarItem& it = far_all[k];
+                const Group& g = pl->groups[it.group];
+                for (int64_t N : memberN[it.group]) {
+                    if (N <= it.mL) continue;
+                    tick_macs[t] += (int64_t)(g.per_comp ? 1 : g.d) * std::min<int64_t>(L, N - it.mL) * it.kfar;
+                }
+            }
         }
+    int64_t max_tick = 0;
+    for (int64_t t = 0; t < ticks; ++t) {
+        pl->far_macs += tick_macs[t];
+        max_tick = std::max(max_tick, tick_macs[t]);
     }
+    // Chains are spread one wave per SIMD in the ticks whose far field (the
+    // launch running beside them) is below this share of the largest one:
+    // there the chain is the longer of the two and gets the whole chip.
+    const int spread_pct = env_int("ABM_CHAIN_SPREAD", 70);
+    pl->chain_spread.assign(ticks, 0);
+    for (int64_t t = 0; t < ticks; ++t)
+        pl->chain_spread[t] = (int64_t)100 * tick_macs[t] < (int64_t)spread_pct * max_tick ? 1 : 0;
     pl->overlap = env_int("ABM_OVERLAP", 1) != 0;
     if (pl->overlap) {
         e = hipStreamCreateWithFlags(&pl->far_stream, hipStreamNonBlocking);
@@ -568,7 +586,7 @@ struct TickEnqueuer {
                     if (!sp.count) continue;
                     e = timed(1, st, [&]() {
                         return launch_chain(pl->groups_dev, pl->chain_items_dev + sp.offset, sp.count,
-                                            kind, L, pl->status, st);
+                                            kind, L, pl->chain_spread[t] != 0, pl->status, st);
                     });
                     if (e != hipSuccess) return hip_fail(e, "chain launch");
                     ++chain_launches;

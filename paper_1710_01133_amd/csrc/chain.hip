@@ -442,17 +442,27 @@ hipError_t launch_rdl(const GroupDev* groups, const ChainItem* items, int n, uin
     return hipGetLastError();
 }
 
-// Waves per workgroup: two per SIMD where the registers allow it, and the
-// weight windows of all waves within the CU's LDS.
+// Waves per workgroup: packed, two per SIMD where the registers allow it
+// (the chains then occupy few CUs and leave the rest to the far field), or
+// spread, one per SIMD over more CUs (faster chains while the far field
+// beside them is small); the weight windows of all waves fit the CU's LDS.
 template <int R, int D, bool PC>
-hipError_t launch_rd(const GroupDev* groups, const ChainItem* items, int n, int L, uint32_t* status,
-                     hipStream_t st)
+hipError_t launch_rd(const GroupDev* groups, const ChainItem* items, int n, int L, bool spread,
+                     uint32_t* status, hipStream_t st)
 {
     constexpr bool big = D > 2 || PC;   // more than half a SIMD's registers at L = 256
     switch (L) {
-    case 64: return launch_rdl<R, D, 64, 8, PC>(groups, items, n, status, st);
-    case 128: return launch_rdl<R, D, 128, 8, PC>(groups, items, n, status, st);
-    case 256: return launch_rdl<R, D, 256, (big ? 4 : 8), PC>(groups, items, n, status, st);
+    case 64:
+        return spread ? launch_rdl<R, D, 64, 4, PC>(groups, items, n, status, st)
+                      : launch_rdl<R, D, 64, 8, PC>(groups, items, n, status, st);
+    case 128:
+        return spread ? launch_rdl<R, D, 128, 4, PC>(groups, items, n, status, st)
+                      : launch_rdl<R, D, 128, 8, PC>(groups, items, n, status, st);
+    case 256:
+        if constexpr (big) return launch_rdl<R, D, 256, 4, PC>(groups, items, n, status, st);
+        else
+            return spread ? launch_rdl<R, D, 256, 4, PC>(groups, items, n, status, st)
+                          : launch_rdl<R, D, 256, 8, PC>(groups, items, n, status, st);
     case 512: return launch_rdl<R, D, 512, (PC && D > 2 ? 2 : 4), PC>(groups, items, n, status, st);
     default: return hipErrorInvalidValue;
     }
@@ -516,21 +526,21 @@ int chain_tables(int kind)
 }
 
 hipError_t launch_chain(const GroupDev* groups, const ChainItem* items, int n, int kind, int L,
-                        uint32_t* status, hipStream_t st)
+                        bool spread, uint32_t* status, hipStream_t st)
 {
     if (n <= 0) return hipSuccess;
     constexpr int P = kRhsCount;
     switch (kind) {
-    case ABM_RHS_LINEAR: return launch_rd<ABM_RHS_LINEAR, 1, false>(groups, items, n, L, status, st);
-    case ABM_RHS_DUFFING: return launch_rd<ABM_RHS_DUFFING, 2, false>(groups, items, n, L, status, st);
-    case ABM_RHS_LORENZ: return launch_rd<ABM_RHS_LORENZ, 3, false>(groups, items, n, L, status, st);
-    case ABM_RHS_POLY: return launch_rd<ABM_RHS_POLY, 1, false>(groups, items, n, L, status, st);
-    case ABM_RHS_LCR: return launch_rd<ABM_RHS_LCR, 2, false>(groups, items, n, L, status, st);
-    case ABM_RHS_DIAG: return launch_rd<ABM_RHS_DIAG, 2, false>(groups, items, n, L, status, st);
-    case P + ABM_RHS_DUFFING: return launch_rd<ABM_RHS_DUFFING, 2, true>(groups, items, n, L, status, st);
-    case P + ABM_RHS_LORENZ: return launch_rd<ABM_RHS_LORENZ, 3, true>(groups, items, n, L, status, st);
-    case P + ABM_RHS_LCR: return launch_rd<ABM_RHS_LCR, 2, true>(groups, items, n, L, status, st);
-    case P + ABM_RHS_DIAG: return launch_rd<ABM_RHS_DIAG, 2, true>(groups, items, n, L, status, st);
+    case ABM_RHS_LINEAR: return launch_rd<ABM_RHS_LINEAR, 1, false>(groups, items, n, L, spread, status, st);
+    case ABM_RHS_DUFFING: return launch_rd<ABM_RHS_DUFFING, 2, false>(groups, items, n, L, spread, status, st);
+    case ABM_RHS_LORENZ: return launch_rd<ABM_RHS_LORENZ, 3, false>(groups, items, n, L, spread, status, st);
+    case ABM_RHS_POLY: return launch_rd<ABM_RHS_POLY, 1, false>(groups, items, n, L, spread, status, st);
+    case ABM_RHS_LCR: return launch_rd<ABM_RHS_LCR, 2, false>(groups, items, n, L, spread, status, st);
+    case ABM_RHS_DIAG: return launch_rd<ABM_RHS_DIAG, 2, false>(groups, items, n, L, spread, status, st);
+    case P + ABM_RHS_DUFFING: return launch_rd<ABM_RHS_DUFFING, 2, true>(groups, items, n, L, spread, status, st);
+    case P + ABM_RHS_LORENZ: return launch_rd<ABM_RHS_LORENZ, 3, true>(groups, items, n, L, spread, status, st);
+    case P + ABM_RHS_LCR: return launch_rd<ABM_RHS_LCR, 2, true>(groups, items, n, L, spread, status, st);
+    case P + ABM_RHS_DIAG: return launch_rd<ABM_RHS_DIAG, 2, true>(groups, items, n, L, spread, status, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -503,7 +503,7 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
     } else {
         for (int k = 0; k < kChainKinds; ++k) {
             if (csp[k].count &&
-                (e = launch_chain(S->groups_dev, cd + csp[k].offset, csp[k].count, k, S->L, S->status,
+                (e = launch_chain(S->groups_dev, cd + csp[k].offset, csp[k].count, k, S->L, false, S->status,
                                   S->s0)) != hipSuccess)
                 return hip_fail(e, "chain launch");
         }
