@@ -70,7 +70,9 @@ enum abm_prec {
     ABM_FAR_FP64 = 0,   /* double products, double accumulation */
     ABM_FAR_FP32 = 1,   /* float products (MFMA f32), float accumulation per tile */
     ABM_FAR_BF16X3 = 2, /* two-term bf16 split (hi+lo) of both operands, 3 products */
-    ABM_FAR_BF16X6 = 3  /* three-term bf16 split (hi+mid+lo), 6 products */
+    ABM_FAR_BF16X6 = 3, /* three-term bf16 split (hi+mid+lo), 6 products */
+    ABM_FAR_FP16X3 = 4  /* two-term fp16 split (hi+lo) of operands scaled by powers of two
+                           (history per 32 rows and column, weights per window), 3 products */
 };
 
 typedef struct abm_problem {

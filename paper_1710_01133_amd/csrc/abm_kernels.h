@@ -89,7 +89,9 @@ struct GroupDev {
     float* F32;            // float copy: column-blocked (colblocked_index), or
                            // time-major [k][ldF] in a narrow group
 
-    uint16_t* Fh[3];       // bf16 split terms of the history, k-blocked (kblocked_index)
+    uint16_t* Fh[3];       // bf16 (or fp16) split terms of the history, k-blocked (kblocked_index)
+    float* Fsc;            // fp16 split: 2^-e of the scaling of rows 32g+1 .. 32g+32 of
+                           // column c at [g * ldF + c] (null otherwise)
     int64_t ldF;           // padded columns
     int64_t rows;          // history rows allocated
     double* accn;          // [member][2][d][L] sums carried into the next block
@@ -151,12 +153,12 @@ hipError_t launch_far_lp(const GroupDev* groups, const FarItem* items, int n, in
                          int max_nsplit, int kchunk, int L, int prec, hipStream_t st);
 hipError_t allow_lds(const void* fn, size_t bytes);   // dynamic LDS above 64 KiB
 
-// Far-field launch classes: 0..3 the Toeplitz kernels by precision (abm_prec),
-// 4 and 5 the blocked convolution of narrow groups in double and float.
-constexpr int kFarClasses = 6;
+// Far-field launch classes: 0..4 the Toeplitz kernels by precision (abm_prec),
+// 5 and 6 the blocked convolution of narrow groups in double and float.
+constexpr int kFarClasses = 7;
 inline int far_class(int prec, bool narrow)
 {
-    return narrow ? (prec == 0 ? 4 : 5) : prec;
+    return narrow ? (prec == 0 ? 5 : 6) : prec;
 }
 // Blocked convolution (narrow groups, fp64 / fp32 far field): product tiles
 // of a block for cols columns, whether a group qualifies, its split plan over

@@ -49,6 +49,7 @@ void free_group(Group& g)
     dev_free(g.F);
     dev_free(g.F32);
     for (int i = 0; i < 3; ++i) dev_free(g.Fh[i]);
+    dev_free(g.Fsc);
     dev_free(g.traj_dev);
     dev_free(g.accn);
     dev_free(g.part[0]);
@@ -90,7 +91,7 @@ abm_status ensure_reduced_weights(WeightTable& W, int prec, hipStream_t st)
     abm_status s;
     hipError_t e;
     const int64_t wn = W.n + kWeightPad;
-    if (prec == ABM_FAR_FP32 && !W.b32) {
+    if ((prec == ABM_FAR_FP32 || prec == ABM_FAR_FP16X3) && !W.b32) {
         if ((s = dev_alloc((void**)&W.b32, wn * sizeof(float), "float weights")) ||
             (s = dev_alloc((void**)&W.a32, wn * sizeof(float), "float weights")))
             return s;
@@ -124,12 +125,17 @@ abm_status alloc_group(Group& g, int L, int nsplit_max, hipStream_t st)
         const size_t bytes = (size_t)g.rows * g.ldF * sizeof(float);
         if ((s = dev_alloc((void**)&g.F32, bytes, "float history"))) return s;
         if ((e = hipMemsetAsync(g.F32, 0, bytes, st)) != hipSuccess) return hip_fail(e, "clear");
-    } else if (g.prec == ABM_FAR_BF16X3 || g.prec == ABM_FAR_BF16X6) {
-        const int terms = g.prec == ABM_FAR_BF16X3 ? 2 : 3;
+    } else if (g.prec == ABM_FAR_BF16X3 || g.prec == ABM_FAR_BF16X6 || g.prec == ABM_FAR_FP16X3) {
+        const int terms = g.prec == ABM_FAR_BF16X6 ? 3 : 2;
         const size_t bytes = (size_t)((g.rows + 7) / 8) * g.ldF * 8 * sizeof(uint16_t);
         for (int tt = 0; tt < terms; ++tt) {
-            if ((s = dev_alloc((void**)&g.Fh[tt], bytes, "bf16 history"))) return s;
+            if ((s = dev_alloc((void**)&g.Fh[tt], bytes, "split history"))) return s;
             if ((e = hipMemsetAsync(g.Fh[tt], 0, bytes, st)) != hipSuccess) return hip_fail(e, "clear");
+        }
+        if (g.prec == ABM_FAR_FP16X3) {
+            const size_t sb = (size_t)(g.rows / 32 + 1) * g.ldF * sizeof(float);
+            if ((s = dev_alloc((void**)&g.Fsc, sb, "history scales"))) return s;
+            if ((e = hipMemsetAsync(g.Fsc, 0, sb, st)) != hipSuccess) return hip_fail(e, "clear");
         }
     }
     if ((s = dev_alloc((void**)&g.traj_dev, nm * sizeof(TrajDesc), "descriptors"))) return s;
@@ -163,6 +169,7 @@ GroupDev group_dev(const Group& g, const WeightTable* const W[4])
         w.alpha = W[c]->alpha;
     }
     for (int i = 0; i < 3; ++i) d.Fh[i] = g.Fh[i];
+    d.Fsc = g.Fsc;
     d.F = g.F;
     d.F32 = g.F32;
     d.ldF = g.ldF;
@@ -293,7 +300,7 @@ abm_status choose_blocking(abm_plan_s* pl, const abm_problem* probs, int B)
     if (kchunk < 512 || kchunk % 512 || kchunk > (1 << 20))
         return fail(ABM_EINVAL, "history chunk %d must be a multiple of 512 (at most 2^20)", kchunk);
     // largest chunk whose LDS footprint fits every precision used
-    for (int prec = 0; prec < 4; ++prec)
+    for (int prec = 0; prec <= ABM_FAR_FP16X3; ++prec)
         while (kchunk > 512 && far_lds_bytes(L, kchunk, prec) > kMaxLds) kchunk -= 512;
     pl->L = L;
     pl->kchunk = kchunk;

@@ -38,6 +38,7 @@ struct ChainArgs {
     gptr<uint16_t> Fhi;
     gptr<uint16_t> Fmid;
     gptr<uint16_t> Flo;
+    gptr<float> Fsc;       // non-null: fp16 split (Fhi, Fmid) with per-32-row scales
     int64_t ldF;
     int64_t rows;
     bool narrow;           // F32 time-major [k][ldF] instead of column-blocked
@@ -65,6 +66,7 @@ __device__ __forceinline__ void chain_view(const GroupDev& G, const ChainItem& i
     A.Fhi = as_global(G.Fh[0]);
     A.Fmid = as_global(G.Fh[1]);
     A.Flo = as_global(G.Fh[2]);
+    A.Fsc = as_global(G.Fsc);
     A.ldF = G.ldF;
     A.rows = G.rows;
     A.narrow = G.narrow != 0;
@@ -89,9 +91,22 @@ __device__ __forceinline__ int64_t comp_col(const TrajDesc& T, int i)
     return (int64_t)T.col0 + (int64_t)i * T.cstride;
 }
 
+// Exponents of the fp16 split of the history: rows 32g+1 .. 32g+32 of a
+// column are stored as f * 2^e with e such that the largest |f| of the 32 rows
+// lies in [2^13, 2^14) (e = 0 for an all-zero group; |e| <= 100).  m: that
+// largest |f|.
+__device__ __forceinline__ int f16_exponent(double m)
+{
+    if (!(m > 0.0) || !isfinite(m)) return 0;
+    int ex;
+    (void)frexp(m, &ex);                       // m = f 2^ex, 0.5 <= f < 1
+    int e = 14 - ex;
+    return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+
 template <int D>
 __device__ __forceinline__ void store_history(const ChainArgs& A, const TrajDesc& T, int64_t s,
-                                              const double* fs)
+                                              const double* fs, const int* f16e)
 {
     const int64_t row = s * A.ldF;
 #pragma unroll
@@ -106,12 +121,23 @@ __device__ __forceinline__ void store_history(const ChainArgs& A, const TrajDesc
     if (A.Fhi && s >= 1) {
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            uint16_t t[3];
-            bf16_split3(fs[i], t);
             const int64_t at = kblocked_index(s, comp_col(T, i), A.ldF);
-            A.Fhi[at] = t[0];
-            A.Fmid[at] = t[1];
-            if (A.Flo) A.Flo[at] = t[2];
+            if (A.Fsc) {
+                // fp16 split of the scaled value: hi = fp16(x), lo = fp16(x - hi)
+                const float x = (float)ldexp(fs[i], f16e[i]);
+                const _Float16 hi = (_Float16)x;
+                const _Float16 lo = (_Float16)(x - (float)hi);
+                A.Fhi[at] = __builtin_bit_cast(uint16_t, hi);
+                A.Fmid[at] = __builtin_bit_cast(uint16_t, lo);
+                if (((s - 1) & 31) == 0)          // the group's first row records its scale
+                    A.Fsc[((s - 1) >> 5) * A.ldF + comp_col(T, i)] = ldexpf(1.0f, -f16e[i]);
+            } else {
+                uint16_t t[3];
+                bf16_split3(fs[i], t);
+                A.Fhi[at] = t[0];
+                A.Fmid[at] = t[1];
+                if (A.Flo) A.Flo[at] = t[2];
+            }
         }
     }
 }
@@ -337,6 +363,22 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
         }
     }
 
+    // fp16 split: the scale of each 32-row group (32/Q consecutive lanes)
+    int f16e[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) f16e[i] = 0;
+    if (A.Fsc) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double m = 0.0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (r0 + q < rows) m = fmax(m, fabs(myF[q][i]));
+#pragma unroll
+            for (int x = 1; x < 32 / Q; x <<= 1) m = fmax(m, __shfl_xor(m, x, kWave));
+            f16e[i] = f16_exponent(m);
+        }
+    }
     // history rows, reduced copies and output states of this lane's rows
     bool bad = false;
 #pragma unroll
@@ -344,7 +386,7 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
         const int r = r0 + q;
         if (r < rows) {
             const int64_t s = mL + r + 1;
-            store_history<D>(A, T, s, myF[q]);
+            store_history<D>(A, T, s, myF[q], f16e);
             store_output<D>(T, s, myY[q]);
 #pragma unroll
             for (int i = 0; i < D; ++i) bad |= !isfinite(myY[q][i]);
@@ -484,7 +526,8 @@ __global__ void k_chain_init(const GroupDev* groups, const ChainItem* items, int
 #pragma unroll
     for (int i = 0; i < 8; ++i) p[i] = T.p[i];
     rhs_eval<R, D>(p, 0.0, x0, f0);
-    store_history<D>(A, T, 0, f0);
+    const int none[D] = {};
+    store_history<D>(A, T, 0, f0, none);
     if (T.out_stride > 0) {
 #pragma unroll
         for (int i = 0; i < D; ++i) as_global(T.y_out)[i] = x0[i];

@@ -15,6 +15,7 @@ struct FarArgs {
     gptr<const double> F;
     gptr<const float> F32;
     gptr<const uint16_t> Fh[3];
+    gptr<const float> Fsc;     // fp16 split: per-32-row scales of the history
     int64_t ldF;
     int64_t rows;
     int64_t mL;
@@ -51,6 +52,7 @@ __device__ __forceinline__ bool far_view(const GroupDev* __restrict__ groups,
         A.ah[i] = as_global(W.ah[i]);
         A.Fh[i] = G.Fh[i] ? as_global((const uint16_t*)G.Fh[i]) + coff * 8 : nullptr;
     }
+    A.Fsc = G.Fsc ? as_global((const float*)G.Fsc) + coff : nullptr;
     A.F = as_global((const double*)G.F) + coff;
     A.F32 = G.F32 ? as_global((const float*)G.F32) + (coff >> 4) * G.rows * 16 : nullptr;
     A.ldF = G.ldF;

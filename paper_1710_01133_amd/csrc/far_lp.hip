@@ -41,6 +41,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
 struct ChunkBounds {
@@ -241,12 +242,60 @@ __device__ __forceinline__ void stage_wait(d4 (&acc64)[MT][1])
     }
 }
 
-// MT row tiles per wave, WPR waves per row kind (predictor, corrector); with
-// 4 waves two workgroups share a CU, so each SIMD runs two waves.
-template <int MT, int TERMS, int WPR>
-__global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const GroupDev* groups,
-                                                           const FarItem* items, int kchunk)
+// Copy of the fp16 split's scales of one stage (groups g0 .. g0+3 of 16
+// columns from col0) into LDS at dst, as [group][16] floats: lane l of the
+// first wave copies 4 columns of group l/4.
+__device__ __forceinline__ void f16_dma_scales(gptr<const float> fsc, int64_t ldF, int col0,
+                                               int64_t g0, int t, float* dst)
 {
+    if (t < 16) {
+        const gptr<const float> src = fsc + (g0 + (t >> 2)) * ldF + col0 + 4 * (t & 3);
+        __builtin_amdgcn_global_load_lds((const ABM_GLOBAL void*)src,
+                                         (__attribute__((address_space(3))) void*)dst, 16, 0, 0);
+    }
+}
+
+template <bool F16> struct SplitType;
+template <> struct SplitType<false> {
+    typedef bf8 frag;
+    static __device__ __forceinline__ f4 mfma(frag a, frag b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+    }
+};
+template <> struct SplitType<true> {
+    typedef h8 frag;
+    static __device__ __forceinline__ f4 mfma(frag a, frag b, f4 c)
+    {
+        return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+    }
+};
+
+// Power-of-two exponent e such that the largest |w| of a weight window lies
+// in [2^13, 2^14) after scaling by 2^e; the weights are monotone in their
+// index for every order, so the largest sits at one end of the window.
+__device__ __forceinline__ int f16_window_exponent(float w_first, float w_last)
+{
+    const float m = fmaxf(fabsf(w_first), fabsf(w_last));
+    if (!(m > 0.f) || !isfinite(m)) return 0;
+    int ex;
+    (void)frexpf(m, &ex);
+    const int e = 14 - ex;
+    return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+
+// MT row tiles per wave, WPR waves per row kind (predictor, corrector); with
+// 4 waves two workgroups share a CU, so each SIMD runs two waves.  F16: the
+// operands are a two-term fp16 split of values scaled by powers of two (the
+// history per 32-row group and column, the weights per window), undone when
+// each step's float sums are added into the double accumulators; otherwise a
+// bf16 split with TERMS terms.
+template <int MT, int TERMS, int WPR, bool F16>
+__global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_split(const GroupDev* groups,
+                                                            const FarItem* items, int kchunk)
+{
+    typedef typename SplitType<F16>::frag frag;
+    static_assert(!F16 || TERMS == 2, "the fp16 split has two terms");
     constexpr int L = 16 * MT * WPR, TN = 16;
     constexpr int NTH = 128 * WPR;              // threads
     FarArgs A;
@@ -267,6 +316,7 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
     uint16_t* wrb = smh;                        // [TERMS][2][win] reversed b windows
     uint16_t* wra = smh + 2 * TERMS * win;      // [TERMS][2][win] reversed a windows
     u4* Bst = reinterpret_cast<u4*>(smh + 4 * TERMS * win);   // [2][TERMS][NB8][TN]
+    float* Ssc = reinterpret_cast<float*>(Bst + 2 * kStageU4); // fp16: [2][QS][TN] scales
 
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int col0 = blockIdx.x * TN;
@@ -291,13 +341,15 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
     // 16-byte read at a dword, not 16-byte, boundary would take the LDS's
     // unaligned path
     const uint32_t* wrd = reinterpret_cast<const uint32_t*>(wrl);
-    auto afrag = [&](int tt, int v) -> bf8 {
+    auto afrag = [&](int tt, int v) -> frag {
         const uint32_t* q = wrd + tt * win + 8 * v;
         u4 x;
 #pragma unroll
         for (int k = 0; k < 4; ++k) x[k] = q[k];
-        return __builtin_bit_cast(bf8, x);
+        return __builtin_bit_cast(frag, x);
     };
+    const gptr<const float> fsc_g = A.Fsc;
+    double unscale_w = 1.0;                     // fp16: 2^-e of this wave's weight window
 
     const int c_begin = blockIdx.y * A.chunks_per_split;
     int c_end = c_begin + A.chunks_per_split;
@@ -308,21 +360,43 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
         __syncthreads();   // previous chunk's readers are done with the LDS
         // reversed windows: copy 0 holds w[jb + wlen - 1 - x], copy 1
         // w[jb + wlen - 2 - x] (jb >= L, so the index stays >= 0)
-        for (int x = t; x < cb.wlen; x += NTH) {
-            const int64_t j = cb.jb + cb.wlen - 1 - x;
+        if constexpr (F16) {
+            // split terms of the scaled float weights, made here
+            const int eb = f16_window_exponent(A.b32[cb.jb], A.b32[cb.jb + cb.wlen - 1]);
+            const int ea = f16_window_exponent(A.a32[cb.jb], A.a32[cb.jb + cb.wlen - 1]);
+            const float sb = ldexpf(1.f, eb), sa = ldexpf(1.f, ea);
+            unscale_w = ldexp(1.0, corr ? -ea : -eb);
+            auto put = [&](uint16_t* w, int copy, int x, float v) {
+                const _Float16 hi = (_Float16)v;
+                const _Float16 lo = (_Float16)(v - (float)hi);
+                w[copy * win + x] = __builtin_bit_cast(uint16_t, hi);
+                w[(2 + copy) * win + x] = __builtin_bit_cast(uint16_t, lo);
+            };
+            for (int x = t; x < cb.wlen; x += NTH) {
+                const int64_t j = cb.jb + cb.wlen - 1 - x;
+                put(wrb, 0, x, A.b32[j] * sb);
+                put(wrb, 1, x, A.b32[j - 1] * sb);
+                put(wra, 0, x, A.a32[j] * sa);
+                put(wra, 1, x, A.a32[j - 1] * sa);
+            }
+        } else {
+            for (int x = t; x < cb.wlen; x += NTH) {
+                const int64_t j = cb.jb + cb.wlen - 1 - x;
 #pragma unroll
-            for (int tt = 0; tt < TERMS; ++tt) {
-                wrb[2 * tt * win + x] = A.bh[tt][j];
-                wrb[(2 * tt + 1) * win + x] = A.bh[tt][j - 1];
-                wra[2 * tt * win + x] = A.ah[tt][j];
-                wra[(2 * tt + 1) * win + x] = A.ah[tt][j - 1];
+                for (int tt = 0; tt < TERMS; ++tt) {
+                    wrb[2 * tt * win + x] = A.bh[tt][j];
+                    wrb[(2 * tt + 1) * win + x] = A.bh[tt][j - 1];
+                    wra[2 * tt * win + x] = A.ah[tt][j];
+                    wra[(2 * tt + 1) * win + x] = A.ah[tt][j - 1];
+                }
             }
         }
         bf_dma_stage<TERMS, NB8, NTH>(fh0, fh1, fh2, A.ldF, col0, kb8, t, Bst);
+        if constexpr (F16) f16_dma_scales(fsc_g, A.ldF, col0, kb8 >> 2, t, Ssc);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");   // this wave's copies are in LDS
         __syncthreads();                                      // and every other wave's
         // ring[tt][slot]: fragment v lives in slot v mod MT; start with v = -(MT-1) .. 0
-        bf8 ring[TERMS][MT];
+        frag ring[TERMS][MT];
 #pragma unroll
         for (int tt = 0; tt < TERMS; ++tt)
 #pragma unroll
@@ -343,15 +417,22 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
                         ring[tt][(2 * qq) % MT] = afrag(tt, 2 * q);
                     }
                 }
-                bf8 bfr[TERMS];
+                frag bfr[TERMS];
 #pragma unroll
                 for (int tt = 0; tt < TERMS; ++tt)
-                    bfr[tt] = __builtin_bit_cast(bf8, Bs[(tt * NB8 + 4 * qq + g) * TN + li]);
+                    bfr[tt] = __builtin_bit_cast(frag, Bs[(tt * NB8 + 4 * qq + g) * TN + li]);
+                // fp16: undoes the scaling of this step's rows of column li
+                double unscale = 1.0;
+                if constexpr (F16) unscale = (double)Ssc[(buf * QS + qq) * TN + li] * unscale_w;
                 // the stage's last LDS reads are issued: copy the next stage
                 // into the other buffer (read by nobody since the last barrier)
-                if (qq == QS - 1 && st + 1 < nstages)
+                if (qq == QS - 1 && st + 1 < nstages) {
                     bf_dma_stage<TERMS, NB8, NTH>(fh0, fh1, fh2, A.ldF, col0, kb8 + (int64_t)(st + 1) * NB8,
                                                   t, Bst + (buf ^ 1) * kStageU4);
+                    if constexpr (F16)
+                        f16_dma_scales(fsc_g, A.ldF, col0, (kb8 >> 2) + (int64_t)(st + 1) * QS, t,
+                                       Ssc + (buf ^ 1) * QS * TN);
+                }
                 // Ordering fence (no instruction): this step's products take their
                 // history operands only after the previous step's double flush, so a
                 // single set of float accumulators is live.  Left alone, the compiler
@@ -372,12 +453,21 @@ __global__ __launch_bounds__(128 * WPR, WPR == 2 ? 2 : 1) void k_far_bf16(const 
                 for (int pp = p0; pp < p0 + NP; ++pp) {
 #pragma unroll
                     for (int tm = 0; tm < MT; ++tm) {
-                        const bf8 af = ring[pa[pp]][(2 * qq - tm + 2 * QS * MT) % MT];
-                        acc[tm][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af, bfr[pb[pp]],
-                                                                             acc[tm][0], 0, 0, 0);
+                        const frag af = ring[pa[pp]][(2 * qq - tm + 2 * QS * MT) % MT];
+                        acc[tm][0] = SplitType<F16>::mfma(af, bfr[pb[pp]], acc[tm][0]);
                     }
                 }
-                flush_acc<MT, 1>(acc, acc64);   // one 32-row step per float run
+                if constexpr (F16) {
+#pragma unroll
+                    for (int i = 0; i < MT; ++i) {
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            acc64[i][0][v] = fma((double)acc[i][0][v], unscale, acc64[i][0][v]);
+                        acc[i][0] = f4{0.f, 0.f, 0.f, 0.f};
+                    }
+                } else {
+                    flush_acc<MT, 1>(acc, acc64);   // one 32-row step per float run
+                }
             }
             // the next stage is in LDS; the wait takes every tile's sum as an
             // operand so that the last step's products are issued before it
@@ -410,16 +500,16 @@ hipError_t launch_f32_t(const LpLaunch& P, hipStream_t st)
 
 // Row tiles per wave: 8 where one wave per SIMD can hold them (L <= 256:
 // the history fragment is then read once per 8 tiles), else L/64.
-template <int L, int TERMS>
-hipError_t launch_bf16_t(const LpLaunch& P, hipStream_t st)
+template <int L, int TERMS, bool F16>
+hipError_t launch_split_t(const LpLaunch& P, hipStream_t st)
 {
     constexpr int MT = L <= 256 ? (L / 32 < 8 ? L / 32 : 8) : L / 64;
     constexpr int WPR = L / (16 * MT);
-    const size_t shmem =
-        far_lp_lds_bytes(L, P.kchunk, TERMS == 2 ? ABM_FAR_BF16X3 : ABM_FAR_BF16X6);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_bf16<MT, TERMS, WPR>), shmem);
+    const size_t shmem = far_lp_lds_bytes(
+        L, P.kchunk, F16 ? ABM_FAR_FP16X3 : (TERMS == 2 ? ABM_FAR_BF16X3 : ABM_FAR_BF16X6));
+    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_split<MT, TERMS, WPR, F16>), shmem);
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_far_bf16<MT, TERMS, WPR>),
+    hipLaunchKernelGGL((k_far_split<MT, TERMS, WPR, F16>),
                        dim3((unsigned)P.max_coltiles, (unsigned)P.max_nsplit, (unsigned)P.n),
                        dim3(128 * WPR), shmem, st, P.groups, P.items, P.kchunk);
     return hipGetLastError();
@@ -431,9 +521,11 @@ size_t far_lp_lds_bytes(int L, int kchunk, int prec)
 {
     const int TN = 16;
     if (prec == ABM_FAR_FP32) return (2 * (size_t)(L + kchunk) + 2 * 32 * TN) * sizeof(float);
-    const int terms = prec == ABM_FAR_BF16X3 ? 2 : 3;
+    const int terms = prec == ABM_FAR_BF16X6 ? 3 : 2;
     // reversed weight windows (two copies) + two history stages of 128 rows
-    return 4 * (size_t)terms * (L + kchunk) * 2 + 2 * (size_t)terms * (kBfStageRows / 8) * TN * 16;
+    // (+ their scales for the fp16 split)
+    return 4 * (size_t)terms * (L + kchunk) * 2 + 2 * (size_t)terms * (kBfStageRows / 8) * TN * 16 +
+           (prec == ABM_FAR_FP16X3 ? 2 * (kBfStageRows / 32) * TN * sizeof(float) : 0);
 }
 
 hipError_t launch_far_lp(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
@@ -450,17 +542,25 @@ hipError_t launch_far_lp(const GroupDev* groups, const FarItem* items, int n, in
     }
     if (prec == ABM_FAR_BF16X3) {
         switch (L) {
-        case 128: return launch_bf16_t<128, 2>(A, st);
-        case 256: return launch_bf16_t<256, 2>(A, st);
-        case 512: return launch_bf16_t<512, 2>(A, st);
+        case 128: return launch_split_t<128, 2, false>(A, st);
+        case 256: return launch_split_t<256, 2, false>(A, st);
+        case 512: return launch_split_t<512, 2, false>(A, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
+    if (prec == ABM_FAR_FP16X3) {
+        switch (L) {
+        case 128: return launch_split_t<128, 2, true>(A, st);
+        case 256: return launch_split_t<256, 2, true>(A, st);
+        case 512: return launch_split_t<512, 2, true>(A, st);
         default: return hipErrorInvalidValue;
         }
     }
     if (prec == ABM_FAR_BF16X6) {
         switch (L) {
-        case 128: return launch_bf16_t<128, 3>(A, st);
-        case 256: return launch_bf16_t<256, 3>(A, st);
-        case 512: return launch_bf16_t<512, 3>(A, st);
+        case 128: return launch_split_t<128, 3, false>(A, st);
+        case 256: return launch_split_t<256, 3, false>(A, st);
+        case 512: return launch_split_t<512, 3, false>(A, st);
         default: return hipErrorInvalidValue;
         }
     }

@@ -155,7 +155,7 @@ struct ReqLayout {
     TableLayout tab[4];
     int ntab;
     int tab_of[4];                    // table of each component
-    size_t F, F32, Fh[3], traj, accn, part, total;
+    size_t F, F32, Fh[3], Fsc, traj, accn, part, total;
     int64_t wn, rows, ldF, ldC;
     size_t part_half;
     bool narrow, per_comp;
@@ -196,7 +196,7 @@ ReqLayout layout_of(const abm_problem& p, int L, int kchunk, int max_split)
         T.c = take(r.wn * sizeof(double));
         T.b32 = T.a32 = 0;
         for (int i = 0; i < 3; ++i) T.bh[i] = T.ah[i] = 0;
-        if (p.far_prec == ABM_FAR_FP32) {
+        if (p.far_prec == ABM_FAR_FP32 || p.far_prec == ABM_FAR_FP16X3) {
             T.b32 = take(r.wn * sizeof(float));
             T.a32 = take(r.wn * sizeof(float));
         } else if (p.far_prec != ABM_FAR_FP64) {
@@ -210,10 +210,13 @@ ReqLayout layout_of(const abm_problem& p, int L, int kchunk, int max_split)
     r.F = take((size_t)r.rows * r.ldF * sizeof(double));
     r.F32 = 0;
     if (p.far_prec == ABM_FAR_FP32) r.F32 = take((size_t)r.rows * r.ldF * sizeof(float));
-    if (p.far_prec == ABM_FAR_BF16X3 || p.far_prec == ABM_FAR_BF16X6) {
-        const int terms = p.far_prec == ABM_FAR_BF16X3 ? 2 : 3;
+    r.Fsc = 0;
+    if (p.far_prec == ABM_FAR_BF16X3 || p.far_prec == ABM_FAR_BF16X6 ||
+        p.far_prec == ABM_FAR_FP16X3) {
+        const int terms = p.far_prec == ABM_FAR_BF16X6 ? 3 : 2;
         for (int i = 0; i < terms; ++i)
             r.Fh[i] = take((size_t)((r.rows + 7) / 8) * r.ldF * 8 * sizeof(uint16_t));
+        if (p.far_prec == ABM_FAR_FP16X3) r.Fsc = take((size_t)(r.rows / 32 + 1) * r.ldF * sizeof(float));
     }
     r.traj = take(sizeof(TrajDesc));
     r.accn = take((size_t)2 * p.d * L * sizeof(double));
@@ -245,7 +248,7 @@ abm_status serve_params(int* L, int* kchunk)
     if (*L != 128 && *L != 256 && *L != 512)
         return fail(ABM_EINVAL, "ABM_SERVE_BLOCK_L must be 128, 256 or 512");
     *kchunk = 2048;
-    for (int prec = 0; prec < 4; ++prec)
+    for (int prec = 0; prec <= ABM_FAR_FP16X3; ++prec)
         while (*kchunk > 512 && far_lds_bytes(*L, *kchunk, prec) > kMaxLds) *kchunk -= 512;
     return ABM_OK;
 }
@@ -330,6 +333,7 @@ abm_status admit(ServeState* S, Request* r, size_t off, const ReqLayout& lay)
     g.F = (double*)(base + lay.F);
     g.F32 = lay.F32 ? (float*)(base + lay.F32) : nullptr;
     for (int i = 0; i < 3; ++i) g.Fh[i] = lay.Fh[i] ? (uint16_t*)(base + lay.Fh[i]) : nullptr;
+    g.Fsc = lay.Fsc ? (float*)(base + lay.Fsc) : nullptr;
     g.traj_dev = (TrajDesc*)(base + lay.traj);
     g.accn = (double*)(base + lay.accn);
     g.part_half = lay.part_half;

@@ -1,4 +1,5 @@
-"""Reduced-precision far field (float, bf16 split x3 / x6) of the blocked path
+"""Reduced-precision far field (float, bf16 split x3 / x6, scaled fp16 split
+x3) of the blocked path
 against the double oracle, through the C ABI.  Here the error is the quantity
 measured: each precision has a stated bound on the normwise relative error
 max_s |y_s - yref_s|_inf / max_s |yref_s|_inf."""
@@ -11,7 +12,7 @@ from gpu_common import golden, normerr, oracle_run, run_batch
 pytestmark = pytest.mark.gpu
 
 # stated error bounds of the far-field precisions (near band and state stay double)
-BOUND = {"fp32": 1e-6, "bf16x3": 1e-4, "bf16x6": 1e-6}
+BOUND = {"fp32": 1e-6, "bf16x3": 1e-4, "bf16x6": 1e-6, "fp16x3": 1e-6}
 
 
 @pytest.fixture(scope="module")
@@ -30,7 +31,7 @@ def _sweep(Ns, prec, alpha=0.95, h=2 ** -6, seed=5):
             for N, A in zip(Ns, amps)]
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6", "fp16x3"])
 @pytest.mark.parametrize("L", [128, 256, 512])
 def test_lowp_ragged_vs_oracle(ctx, prec, L, monkeypatch):
     monkeypatch.setenv("ABM_BLOCK_L", str(L))
@@ -43,7 +44,7 @@ def test_lowp_ragged_vs_oracle(ctx, prec, L, monkeypatch):
     assert max(errs) <= BOUND[prec], errs
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6", "fp16x3"])
 def test_lowp_mixed_rhs(ctx, prec):
     probs = [
         inputs.Problem("LORENZ", 0.97, 2 ** -8, 3000, (1.0, 1.0, 1.0), (10.0, 28.0, 8 / 3), prec),
@@ -64,7 +65,7 @@ def test_lowp_needs_block_128(ctx, monkeypatch):
     assert e.value.code == abm.ABM_EINVAL
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6", "fp16x3"])
 def test_lowp_batch_invariance(ctx, prec, monkeypatch):
     # column tiles for the lone trajectory too (a narrow float group would
     # take the blocked convolution, the same sums in another order)
@@ -78,7 +79,7 @@ def test_lowp_batch_invariance(ctx, prec, monkeypatch):
         assert np.array_equal(a, b)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16x6", "fp16x3"])
 def test_lowp_sweep_full_size(ctx, prec):
     """B = 1024, N = 65536: error of sampled members against the stored double
     oracle runs, at the launch shape the benchmark times."""
@@ -92,13 +93,14 @@ def test_lowp_sweep_full_size(ctx, prec):
     assert np.all(np.isfinite(allv)) and np.max(np.abs(allv)) < 10
 
 
-@pytest.mark.parametrize("blocking", [(256, 2048, 4), (512, 2048, 4), (128, 1024, 16)])
-def test_bf16x6_sweep_full_size_at_tuned_blockings(ctx, blocking):
-    """The full sweep in the default far precision at blockings the autotuner
+@pytest.mark.parametrize("prec", ["bf16x6", "fp16x3"])
+@pytest.mark.parametrize("blocking", [(256, 1024, 8), (256, 2048, 4), (512, 2048, 4), (128, 1024, 16)])
+def test_split_sweep_full_size_at_tuned_blockings(ctx, blocking, prec):
+    """The full sweep in the split far precisions at blockings the autotuner
     chooses between (the first is the one the benchmark has been timing):
     sampled members against the stored double oracle runs."""
     L, kchunk, split = blocking
-    probs = inputs.duffing_sweep(far_prec="bf16x6")
+    probs = inputs.duffing_sweep(far_prec=prec)
     tuning = dict(block_L=L, kchunk=kchunk, max_split=split, column_tiles_only=0)
     plan = abm.Plan(ctx, probs, out_stride=1024, tuning=tuning)
     assert plan.config() == tuning
@@ -109,4 +111,21 @@ def test_bf16x6_sweep_full_size_at_tuned_blockings(ctx, blocking):
     g = golden()
     for i in (0, 1, 511, 1023):
         err = normerr(ys[i].cpu().numpy(), np.array(g["duffing_sweep_%d" % i]["y"]))
-        assert err <= BOUND["bf16x6"], (blocking, i, err)
+        assert err <= BOUND[prec], (blocking, i, err)
+
+
+@pytest.mark.parametrize("scale", [1e-6, 1e4])
+def test_fp16x3_scaling_far_from_unit_magnitudes(ctx, scale):
+    """The fp16 split scales the history per 32 rows and column and the
+    weights per window: a linear problem whose state and right-hand side
+    are of order 1e-6 or 1e4 (far outside fp16's normal range of about
+    6e-5 .. 6.5e4 without scaling) keeps the same error."""
+    probs = [inputs.Problem("LINEAR", 0.8, 2 ** -9, 3000, (scale,), (1.0,), "fp16x3"),
+             inputs.Problem("DUFFING", 0.3, 2 ** -6, 3000, (0.1, 0.0), (0.1, 0.45, 1.2), "fp16x3"),
+             inputs.Problem("LCR", 1.5, 0.01, 3000, (1.2, -0.4), (1.015, 0.55, -1.02, -0.58, 0.117),
+                            "fp16x3", x1=(0.0, 0.0))]
+    outs, _ = run_batch(ctx, probs, 1)
+    for p, y in zip(probs, outs):
+        e = normerr(y, oracle_run(p, 1))
+        print(p.rhs, p.alpha, "err %.3e" % e)
+        assert e <= BOUND["fp16x3"], (p.rhs, e)

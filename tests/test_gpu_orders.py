@@ -139,7 +139,7 @@ def test_batch_general_orders_column_tiles_only(ctx, monkeypatch):
         assert e <= TOL_FP64, (p.rhs, p.alpha, p.N, e)
 
 
-@pytest.mark.parametrize("prec", ["fp32", "bf16x6"])
+@pytest.mark.parametrize("prec", ["fp32", "bf16x6", "fp16x3"])
 def test_batch_general_orders_reduced_precision(ctx, prec, monkeypatch):
     monkeypatch.setenv("ABM_BLOCK_L", "256")
     probs = _lcr_sweep(40, (0.9, 0.8), prec, 3000, 9) + _lcr_sweep(8, 0.9, prec, 3000, 10)
@@ -213,7 +213,7 @@ def test_served_general_orders_match_oracle(ctx):
     import torch
     sctx = abm.Context(0, arena_bytes=512 << 20)
     probs = []
-    for prec in ("fp64", "fp32", "bf16x6"):
+    for prec in ("fp64", "fp32", "bf16x6", "fp16x3"):
         probs += [
             inputs.Problem("LCR", (0.9, 0.8), 0.01, 3000, (1.2, -0.4), LCR + (0.117,), prec),
             inputs.Problem("LORENZ", (0.95, 0.9, 0.85), 2 ** -8, 1700, (1.0, 1.0, 1.0),
