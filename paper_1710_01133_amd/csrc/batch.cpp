@@ -543,31 +543,47 @@ struct TickEnqueuer {
         if (!fork) return fail(ABM_EDEVICE, "event pool");
         if ((e = hipEventRecord(fork, st)) != hipSuccess || (e = hipStreamWaitEvent(s1, fork, 0)) != hipSuccess)
             return hip_fail(e, "stream fork");
+        // The two streams swap roles every tick: tick t runs chain(t) on S[t mod 2]
+        // and the far field of block t+1 on the other stream, i.e. after chain(t-1)
+        // (its input) in stream order; chain(t) follows the far field of its block
+        // in stream order and waits for chain(t-1) by event.  Each tick thus has
+        // one cross-stream wait.  The partial slices alternate by block parity, so
+        // far(t+1) overwrites the slices of block t-1 only after chain(t-1), the
+        // stream's previous work, has read them.
+        const bool alt = pl->overlap && env_int("ABM_ALT_STREAMS", 1) != 0;
         hipEvent_t ev_chain_prev = nullptr, ev_far_prev = nullptr;
         for (int64_t t = 0; t < pl->ticks; ++t) {
+            hipStream_t sc = st, sf = s1;
+            if (alt && (t & 1)) std::swap(sc, sf);
             bool any_far = false;
             for (int cls = 0; cls < kFarClasses; ++cls)
                 if (pl->far_spans[t * kFarClasses + cls].count) any_far = true;
             hipEvent_t ev_far = nullptr;
             if (any_far) {
-                if (ev_chain_prev && (e = hipStreamWaitEvent(s1, ev_chain_prev, 0)) != hipSuccess)
+                if (!alt && ev_chain_prev && (e = hipStreamWaitEvent(sf, ev_chain_prev, 0)) != hipSuccess)
                     return hip_fail(e, "stream wait");
                 for (int cls = 0; cls < kFarClasses; ++cls) {
                     const Span& sp = pl->far_spans[t * kFarClasses + cls];
                     if (!sp.count) continue;
-                    e = timed(0, s1, [&]() {
+                    e = timed(0, sf, [&]() {
                         return launch_far(pl->groups_dev, pl->far_items_dev + sp.offset, sp.count,
-                                          sp.max_x, sp.max_y, pl->kchunk, L, cls, s1);
+                                          sp.max_x, sp.max_y, pl->kchunk, L, cls, sf);
                     });
                     if (e != hipSuccess) return hip_fail(e, "far-field launch");
                     ++far_launches;
                 }
-                ev_far = sync_event();
-                if (!ev_far || (e = hipEventRecord(ev_far, s1)) != hipSuccess)
-                    return fail(ABM_EDEVICE, "far event");
+                if (!alt) {
+                    ev_far = sync_event();
+                    if (!ev_far || (e = hipEventRecord(ev_far, sf)) != hipSuccess)
+                        return fail(ABM_EDEVICE, "far event");
+                }
             }
-            if (ev_far_prev && (e = hipStreamWaitEvent(st, ev_far_prev, 0)) != hipSuccess)
+            if (alt) {
+                if (ev_chain_prev && (e = hipStreamWaitEvent(sc, ev_chain_prev, 0)) != hipSuccess)
+                    return hip_fail(e, "stream wait");
+            } else if (ev_far_prev && (e = hipStreamWaitEvent(sc, ev_far_prev, 0)) != hipSuccess) {
                 return hip_fail(e, "stream wait");
+            }
             // chains of every kind: one launch (one kernel switching per wave
             // when the tick mixes systems), so they run side by side
             int nkind = 0, nch = 0, nw = 1;
@@ -581,9 +597,9 @@ struct TickEnqueuer {
                 nw = std::max(nw, chain_tables(kind));
             }
             if (nkind > 1) {
-                e = timed(1, st, [&]() {
+                e = timed(1, sc, [&]() {
                     return launch_chain_mixed(pl->groups_dev, pl->chain_items_dev + off0, nch, L,
-                                              nw, pl->status, st);
+                                              nw, pl->status, sc);
                 });
                 if (e != hipSuccess) return hip_fail(e, "chain launch");
                 ++chain_launches;
@@ -591,16 +607,16 @@ struct TickEnqueuer {
                 for (int kind = 0; kind < kChainKinds; ++kind) {
                     const Span& sp = pl->chain_spans[t * kChainKinds + kind];
                     if (!sp.count) continue;
-                    e = timed(1, st, [&]() {
+                    e = timed(1, sc, [&]() {
                         return launch_chain(pl->groups_dev, pl->chain_items_dev + sp.offset, sp.count,
-                                            kind, L, pl->chain_spread[t] != 0, pl->status, st);
+                                            kind, L, pl->chain_spread[t] != 0, pl->status, sc);
                     });
                     if (e != hipSuccess) return hip_fail(e, "chain launch");
                     ++chain_launches;
                 }
             }
             ev_chain_prev = sync_event();
-            if (!ev_chain_prev || (e = hipEventRecord(ev_chain_prev, st)) != hipSuccess)
+            if (!ev_chain_prev || (e = hipEventRecord(ev_chain_prev, sc)) != hipSuccess)
                 return fail(ABM_EDEVICE, "chain event");
             ev_far_prev = ev_far;
         }
