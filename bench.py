@@ -47,10 +47,11 @@ def far_source_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prec, launches):
+def measured_traffic(prec, blocking):
     """HBM bytes per far-field launch from the committed rocprofv3 counter
     runs (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel calibration);
-    None when the kernel sources changed since the counters were taken."""
+    None when the kernel sources changed since the counters were taken, or
+    when they were taken at another blocking (L, kchunk, max_split)."""
     path = os.path.join(ROOT, "profiles", "far_traffic.json")
     if not os.path.exists(path):
         return None
@@ -58,6 +59,8 @@ def measured_traffic(prec, launches):
         t = json.load(f)
     e = t.get(prec)
     if not e or e.get("source_sha") != far_source_sha():
+        return None
+    if e.get("blocking") != [blocking["block_L"], blocking["kchunk"], blocking["max_split"]]:
         return None
     return e["bytes_per_launch"]
 
@@ -243,7 +246,7 @@ def long_leg(abm, torch, inputs, ctx):
     return res
 
 
-def lcr_leg(abm, torch, inputs, ctx, prec, steps=2):
+def lcr_leg(abm, torch, inputs, ctx, prec, tuning, steps=2):
     """The paper's own workload: the forced fractional LCR circuit swept over
     its forcing F in [0, 0.2] (B = 1024, N = 65536), commensurate orders
     (0.9, 0.9) as in its figures and incommensurate (0.9, 0.8), in the
@@ -251,7 +254,9 @@ def lcr_leg(abm, torch, inputs, ctx, prec, steps=2):
     stroboscopic (Poincare) section y(kT) (every 1142nd state, h = T/1142).
     Error against the oracle on the section points of the first 3600 steps of
     two members (the circuit is chaotic at some F, so later points measure
-    the dynamics' amplification of rounding, not the method)."""
+    the dynamics' amplification of rounding, not the method).  Reduced
+    precisions run at the blocking chosen for the headline sweep (the same
+    shape), double at the library's default."""
     import oracle as O
     M = inputs.LCR_SECTION_STEPS
     res = {"workload": "forced fractional LCR circuit, sigma=1.015, omega=0.55, a=-1.02, "
@@ -260,7 +265,7 @@ def lcr_leg(abm, torch, inputs, ctx, prec, steps=2):
     for al in ((0.9, 0.9), (0.9, 0.8)):
         for pr in (prec, "fp64"):
             probs = inputs.lcr_sweep(alpha=al, far_prec=pr)
-            plan = abm.Plan(ctx, probs, out_stride=M)
+            plan = abm.Plan(ctx, probs, out_stride=M, tuning=None if pr == "fp64" else tuning)
             plan.graph(True)
             ys = [abm.alloc_out(p, M) for p in probs]
             dt, st = time_batch(abm, torch, plan, probs, ys, steps, 1)
@@ -272,7 +277,7 @@ def lcr_leg(abm, torch, inputs, ctx, prec, steps=2):
                 errs.append(normerr(y, ref[:-1]))
             res["alpha=%s,%s %s" % (al[0], al[1], pr)] = {
                 "ms_per_step": dt * 1e3, "history_macs_per_s": st["history_macs"] / dt,
-                "section_points_per_member": int(ys[0].shape[0]),
+                "section_points_per_member": int(ys[0].shape[0]), "blocking": plan.config(),
                 "max_rel_err_vs_oracle_first_3600_steps": max(errs)}
             plan.close()
     return res
@@ -377,7 +382,7 @@ def main():
     achieved = far_flop / far_s / 1e12
     peak = PEAK_TFLOPS[args.prec]
     roof = {"bound": "mfma", "achieved": achieved, "peak": peak, "unit": "TFLOP/s",
-            "frac": achieved / peak, "traffic": measured_traffic(args.prec, stt["far_launches"]),
+            "frac": achieved / peak, "traffic": measured_traffic(args.prec, plan.config()),
             "kernel": "far-field Toeplitz x history product (%s)" % args.prec,
             "launches": stt["far_launches"], "avg_launch_ms": stt["far_ms"] / stt["far_launches"],
             "flop_per_launch": far_flop / stt["far_launches"],
@@ -386,7 +391,7 @@ def main():
 
     plain = None if args.no_plain else plain_leg(abm, torch, inputs, ctx)
     longrun = None if args.no_long else long_leg(abm, torch, inputs, ctx)
-    lcr = None if args.no_lcr else lcr_leg(abm, torch, inputs, ctx, args.prec)
+    lcr = None if args.no_lcr else lcr_leg(abm, torch, inputs, ctx, args.prec, plan.config())
     small = small_batch_leg(abm, torch, inputs, ctx)
 
     serve = None
@@ -403,7 +408,8 @@ def main():
             if pr == args.prec:
                 continue
             pp = inputs.duffing_sweep(far_prec=pr)
-            pl2 = abm.Plan(ctx, pp, out_stride=stride)
+            # reduced precisions at the headline's blocking, double at the default
+            pl2 = abm.Plan(ctx, pp, out_stride=stride, tuning=None if pr == "fp64" else plan.config())
             pl2.graph(not args.eager)
             dt2, st2 = time_batch(abm, torch, pl2, pp, ys, 2, 1)
             e2 = {}
@@ -413,6 +419,7 @@ def main():
                     if key in g:
                         e2[i] = normerr(ys[i].cpu().numpy(), np.array(g[key]["y"]))
             others[pr] = {"value": st2["history_macs"] / dt2, "ms_per_step": dt2 * 1e3,
+                          "blocking": pl2.config(),
                           "max_rel_err_vs_oracle": max(e2.values()) if e2 else None}
             pl2.close()
 

@@ -464,9 +464,12 @@ abm_status batch_setup(abm_plan_s* pl)
         max_tick = std::max(max_tick, tick_macs[t]);
     }
     // Chains are spread one wave per SIMD in the ticks whose far field (the
-    // launch running beside them) is below this share of the largest one:
-    // there the chain is the longer of the two and gets the whole chip.
-    const int spread_pct = env_int("ABM_CHAIN_SPREAD", 70);
+    // launch running beside them) is below this share (percent) of the
+    // largest one, and packed two waves per SIMD in the others.  With the far
+    // fields of consecutive ticks overlapping (the streams alternate), a chain
+    // wave beside one far-field wave on every SIMD measured best in every
+    // tick, so by default (101) every tick spreads.
+    const int spread_pct = env_int("ABM_CHAIN_SPREAD", 101);
     pl->chain_spread.assign(ticks, 0);
     for (int64_t t = 0; t < ticks; ++t)
         pl->chain_spread[t] = (int64_t)100 * tick_macs[t] < (int64_t)spread_pct * max_tick ? 1 : 0;
