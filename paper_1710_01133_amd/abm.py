@@ -208,8 +208,9 @@ class Context:
             load().abm_ctx_destroy(self._h)
             self._h = ctypes.c_void_p()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may already be gone at exit)
+        if not getattr(self, "_h", None) or _finalizing():
             return
         try:
             self.close()
@@ -274,8 +275,9 @@ class Plan:
             load().abm_plan_destroy(self._h)
             self._h = ctypes.c_void_p()
 
-    def __del__(self):
-        if sys.is_finalizing():
+    def __del__(self, _finalizing=sys.is_finalizing):
+        # (bound at definition: module globals may already be gone at exit)
+        if not getattr(self, "_h", None) or _finalizing():
             return
         try:
             self.close()
