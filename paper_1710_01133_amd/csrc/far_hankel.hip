@@ -35,6 +35,7 @@ typedef float f4 __attribute__((ext_vector_type(4)));
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kDch = 64;          // shifts per chunk (1024 history rows)
+constexpr int64_t kMinChunks = 8; // least chunks per split slice
 constexpr int kHWaves = 4;
 constexpr int kRedSlots = 4;      // tiles reduced per round
 constexpr int kHMaxTiles = 4;     // product tiles per item (16 columns of row blocks each)
@@ -344,7 +345,6 @@ int hankel_split_plan(int64_t kfar, int L, int max_split, int* nchunks, int* chu
     // short beside its chain anyway, so fewer, longer slices pay while the
     // history is short (one 10^6-step trajectory: 0.59 -> 0.47 s; 3·10^6 steps:
     // 2.24 -> 2.04 s, measured against 1, 4 and 16 chunks per slice).
-    constexpr int64_t kMinChunks = 8;
     const int64_t rows = kfar + L - 16, chunk = 16 * kDch;
     const int64_t want = ((rows + chunk - 1) / chunk + kMinChunks - 1) / kMinChunks;
     const int cap = (int)(want < max_split ? want : max_split);
@@ -354,7 +354,11 @@ int hankel_split_plan(int64_t kfar, int L, int max_split, int* nchunks, int* chu
 int hankel_split_bound(int64_t kfar_max, int L, int max_split)
 {
     if (kfar_max < 1) return 0;
-    return far_split_bound(kfar_max + L - 16, 16 * kDch, max_split);
+    // hankel_split_plan gives at most min(ceil(chunks / kMinChunks), max_split)
+    // slices, and its chunk count only grows with kfar
+    const int64_t nc = (kfar_max + L - 16 + 16 * kDch - 1) / (16 * kDch);
+    const int64_t want = (nc + kMinChunks - 1) / kMinChunks;
+    return (int)(want < max_split ? want : max_split);
 }
 
 size_t hankel_lds_bytes(int L, int max_tiles, int prec)

@@ -73,8 +73,10 @@ struct Request {
 
 }  // namespace
 
-// far partial slices per request and block (ABM_SERVE_MAX_SPLIT overrides)
-int serve_max_split() { return std::max(1, std::min(256, env_int("ABM_SERVE_MAX_SPLIT", 16))); }
+// most far partial slices per request and block (ABM_SERVE_MAX_SPLIT
+// overrides); a slice takes at least 8 history chunks, so a request of up to
+// 262144 steps never needs more
+int serve_max_split() { return std::max(1, std::min(256, env_int("ABM_SERVE_MAX_SPLIT", 32))); }
 
 struct ServeState {
     abm_ctx* ctx = nullptr;
