@@ -215,43 +215,70 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
     // carried sums of block m (written by the previous block's chain)
     const gptr<double> accn = A.accn;
     double accP[Q][D], accC[Q][D], nxtP[Q][D], nxtC[Q][D];
+    const size_t sstride = (size_t)A.ldP * (2 * L);
 #pragma unroll
-    for (int q = 0; q < Q; ++q) {
-        const int r = r0 + q;
-        const int64_t n = mL + r;
+    for (int i = 0; i < D; ++i) {
+        // Partial slices added in slice order.  A lane's Q rows are adjacent
+        // in a slice (Q even: 16-byte aligned pairs), so a slice is Q/2 pair
+        // loads for the predictor rows and Q/2 for the corrector rows, four
+        // slices in flight at a time.
+        double sp[Q], sc[Q];
 #pragma unroll
-        for (int i = 0; i < D; ++i) {
-            // partial slices added in slice order; loaded 8 at a time so the
-            // loads are in flight together instead of waiting one by one
-            double sp = 0.0, sc = 0.0;
-            const gptr<const double> pc0 = A.part + (size_t)comp_col(T, i) * (2 * L) + r;
-            const size_t sstride = (size_t)A.ldP * (2 * L);
-            int ch = 0;
-            for (; ch + 8 <= A.nchunks; ch += 8) {
-                double vp[8], vc[8];
+        for (int q = 0; q < Q; ++q) sp[q] = sc[q] = 0.0;
+        const gptr<const double> pc0 = A.part + (size_t)comp_col(T, i) * (2 * L) + r0;
+        auto load_rows = [&](size_t off, double* v) {
+            if constexpr (Q % 2 == 0) {
+                typedef double d2 __attribute__((ext_vector_type(2)));
+                const gptr<const d2> src = (gptr<const d2>)(pc0 + off);
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    vp[u] = pc0[(ch + u) * sstride];
-                    vc[u] = pc0[(ch + u) * sstride + L];
+                for (int q = 0; q < Q / 2; ++q) {
+                    const d2 x = src[q];
+                    v[2 * q] = x[0];
+                    v[2 * q + 1] = x[1];
                 }
+            } else {
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    sp += vp[u];
-                    sc += vc[u];
+                for (int q = 0; q < Q; ++q) v[q] = pc0[off + q];
+            }
+        };
+        int ch = 0;
+        for (; ch + 4 <= A.nchunks; ch += 4) {
+            double vp[4][Q], vc[4][Q];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                load_rows((ch + u) * sstride, vp[u]);
+                load_rows((ch + u) * sstride + L, vc[u]);
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) {
+                    sp[q] += vp[u][q];
+                    sc[q] += vc[u][q];
                 }
+        }
+        for (; ch < A.nchunks; ++ch) {
+            double vp[Q], vc[Q];
+            load_rows(ch * sstride, vp);
+            load_rows(ch * sstride + L, vc);
+#pragma unroll
+            for (int q = 0; q < Q; ++q) {
+                sp[q] += vp[q];
+                sc[q] += vc[q];
             }
-            for (; ch < A.nchunks; ++ch) {
-                sp += pc0[ch * sstride];
-                sc += pc0[ch * sstride + L];
-            }
-            sp += A.b[PC ? i : 0][n] * F0[i];
-            sc += A.c[PC ? i : 0][n] * F0[i];
+        }
+#pragma unroll
+        for (int q = 0; q < Q; ++q) {
+            const int r = r0 + q;
+            const int64_t n = mL + r;
+            sp[q] += A.b[PC ? i : 0][n] * F0[i];
+            sc[q] += A.c[PC ? i : 0][n] * F0[i];
             if (mL > 0) {
-                sp += accn[i * L + r];
-                sc += accn[(D + i) * L + r];
+                sp[q] += accn[i * L + r];
+                sc[q] += accn[(D + i) * L + r];
             }
-            accP[q][i] = sp;
-            accC[q][i] = sc;
+            accP[q][i] = sp[q];
+            accC[q][i] = sc[q];
             nxtP[q][i] = 0.0;
             nxtC[q][i] = 0.0;
         }
