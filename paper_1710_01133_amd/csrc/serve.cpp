@@ -107,7 +107,6 @@ struct ServeState {
     hipEvent_t ring_ev[kRing] = {};
     bool ring_live[kRing] = {};
     int64_t tick = 0;
-    hipEvent_t ev_chain_prev = nullptr, ev_far_prev = nullptr;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_next = 0;
     uint32_t* status = nullptr;
@@ -464,35 +463,33 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
     FarItem* fd = S->far_dev + (size_t)ring * kMaxFar;
     ChainItem* cd = S->chain_dev + (size_t)ring * kMaxActive;
     ChainItem* id = S->init_dev + (size_t)ring * kMaxActive;
-    // items reach s1 through s0: upload on s0, then s1 waits for it
-    if (nf && (e = hipMemcpyAsync(fd, fh, nf * sizeof(FarItem), hipMemcpyHostToDevice, S->s0)))
+    // The two streams swap roles every tick (as in the batched path): the
+    // chains of tick t run on sc = S[t mod 2]; the item uploads and the far
+    // field of the next blocks go to the other stream sf, after the chains of
+    // tick t-1 (the far field's input) in stream order.  The chains wait for
+    // one event on sf recorded after the uploads, which also covers the
+    // previous chains and any admission set-up enqueued on sf; the far field
+    // of their own blocks, launched a tick earlier, precedes them on sc.
+    hipStream_t sc = (S->tick & 1) ? S->s1 : S->s0;
+    hipStream_t sf = (S->tick & 1) ? S->s0 : S->s1;
+    if (nf && (e = hipMemcpyAsync(fd, fh, nf * sizeof(FarItem), hipMemcpyHostToDevice, sf)))
         return hip_fail(e, "item upload");
-    if (nc && (e = hipMemcpyAsync(cd, ch, nc * sizeof(ChainItem), hipMemcpyHostToDevice, S->s0)))
+    if (nc && (e = hipMemcpyAsync(cd, ch, nc * sizeof(ChainItem), hipMemcpyHostToDevice, sf)))
         return hip_fail(e, "item upload");
-    if (ni && (e = hipMemcpyAsync(id, ih, ni * sizeof(ChainItem), hipMemcpyHostToDevice, S->s0)))
+    if (ni && (e = hipMemcpyAsync(id, ih, ni * sizeof(ChainItem), hipMemcpyHostToDevice, sf)))
         return hip_fail(e, "item upload");
     hipEvent_t up = pooled_event(S);
-    if ((e = hipEventRecord(up, S->s0)) != hipSuccess) return hip_fail(e, "event");
-
-    hipEvent_t ev_far = nullptr;
-    if (nf) {
-        if ((e = hipStreamWaitEvent(S->s1, up, 0)) != hipSuccess) return hip_fail(e, "wait");
-        if (S->ev_chain_prev && (e = hipStreamWaitEvent(S->s1, S->ev_chain_prev, 0)) != hipSuccess)
-            return hip_fail(e, "wait");
-        for (int k = 0; k < kFarClasses; ++k) {
-            if (!fsp[k].count) continue;
-            e = launch_far(S->groups_dev, fd + fsp[k].offset, fsp[k].count, fsp[k].max_x,
-                           fsp[k].max_y, S->kchunk, S->L, k, S->s1);
-            if (e != hipSuccess) return hip_fail(e, "far-field launch");
-        }
-        ev_far = pooled_event(S);
-        if ((e = hipEventRecord(ev_far, S->s1)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventRecord(up, sf)) != hipSuccess) return hip_fail(e, "event");
+    for (int k = 0; k < kFarClasses; ++k) {
+        if (!fsp[k].count) continue;
+        e = launch_far(S->groups_dev, fd + fsp[k].offset, fsp[k].count, fsp[k].max_x, fsp[k].max_y,
+                       S->kchunk, S->L, k, sf);
+        if (e != hipSuccess) return hip_fail(e, "far-field launch");
     }
-    if (S->ev_far_prev && (e = hipStreamWaitEvent(S->s0, S->ev_far_prev, 0)) != hipSuccess)
-        return hip_fail(e, "wait");
+    if ((e = hipStreamWaitEvent(sc, up, 0)) != hipSuccess) return hip_fail(e, "wait");
     for (int k = 0; k < kRhsCount; ++k) {
         if (isp[k].count &&
-            (e = launch_chain_init(S->groups_dev, id + isp[k].offset, isp[k].count, k, S->s0)) != hipSuccess)
+            (e = launch_chain_init(S->groups_dev, id + isp[k].offset, isp[k].count, k, sc)) != hipSuccess)
             return hip_fail(e, "init launch");
     }
     // chains of every kind: one launch (one kernel switching per wave when
@@ -504,13 +501,13 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
             nw = std::max(nw, chain_tables(k));
         }
     if (nkind > 1) {
-        if ((e = launch_chain_mixed(S->groups_dev, cd, nc, S->L, nw, S->status, S->s0)) != hipSuccess)
+        if ((e = launch_chain_mixed(S->groups_dev, cd, nc, S->L, nw, S->status, sc)) != hipSuccess)
             return hip_fail(e, "chain launch");
     } else {
         for (int k = 0; k < kChainKinds; ++k) {
             if (csp[k].count &&
                 (e = launch_chain(S->groups_dev, cd + csp[k].offset, csp[k].count, k, S->L, false, S->status,
-                                  S->s0)) != hipSuccess)
+                                  sc)) != hipSuccess)
                 return hip_fail(e, "chain launch");
         }
     }
@@ -519,7 +516,7 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
         if (r->finishing) continue;
         if (r->cancel_seen) {
             // no more work for it; done once what was already issued has run
-            if ((e = hipEventRecord(r->done_ev, S->s0)) != hipSuccess) return hip_fail(e, "event");
+            if ((e = hipEventRecord(r->done_ev, sc)) != hipSuccess) return hip_fail(e, "event");
             r->finishing = true;
             continue;
         }
@@ -527,16 +524,13 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
         if (r->m >= r->nblocks) {
             const int64_t nout = n_out(r->prob.N, r->prob.out_stride);
             if ((e = hipMemcpyAsync(r->final_host, r->y_out + (nout - 1) * r->prob.d,
-                                    r->prob.d * sizeof(double), hipMemcpyDeviceToHost, S->s0)))
+                                    r->prob.d * sizeof(double), hipMemcpyDeviceToHost, sc)))
                 return hip_fail(e, "result copy");
-            if ((e = hipEventRecord(r->done_ev, S->s0)) != hipSuccess) return hip_fail(e, "event");
+            if ((e = hipEventRecord(r->done_ev, sc)) != hipSuccess) return hip_fail(e, "event");
             r->finishing = true;
         }
     }
-    S->ev_chain_prev = pooled_event(S);
-    if ((e = hipEventRecord(S->ev_chain_prev, S->s0)) != hipSuccess) return hip_fail(e, "event");
-    S->ev_far_prev = ev_far;
-    if ((e = hipEventRecord(S->ring_ev[ring], S->s0)) != hipSuccess) return hip_fail(e, "event");
+    if ((e = hipEventRecord(S->ring_ev[ring], sc)) != hipSuccess) return hip_fail(e, "event");
     S->ring_live[ring] = true;
     ++S->tick;
     return ABM_OK;
