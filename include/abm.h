@@ -174,8 +174,10 @@ abm_status abm_plan_config(abm_plan_t *plan, abm_tuning *out);
  * tiles instead of the blocked convolution if the problems have narrow
  * groups.  Stops starting new trials once budget_s seconds have passed (the
  * block-length stage always runs at least one).  Device memory for one plan
- * at a time plus scratch outputs.  best receives the fastest configuration;
- * trials (may be NULL) receives up to max_trials of the trials made, in
+ * at a time plus scratch outputs.  best receives the fastest configuration,
+ * where a trial replaces an earlier, slower one only if it is more than 2%
+ * faster (so that run-to-run noise does not decide); trials (may be NULL)
+ * receives up to max_trials of the trials made, in
  * order, and n_trials their count.  Synchronises the context's stream.
  * Errors: ABM_EINVAL, ABM_EDEVICE (no configuration could be run). */
 abm_status abm_autotune(abm_ctx *ctx, const abm_problem *probs, int32_t B, double budget_s,

@@ -65,11 +65,16 @@ struct Tuner {
         return s;
     }
 
+    // The fastest trial, in trial order, where a later trial replaces the
+    // incumbent only when it is faster by more than kMargin: repeated solves
+    // of one blocking differ by about 1%, and a choice made on noise would
+    // change from run to run.
     const abm_tune_trial* best() const
     {
+        constexpr double kMargin = 0.02;
         const abm_tune_trial* b = nullptr;
         for (const abm_tune_trial& t : trials)
-            if (t.status == ABM_OK && (!b || t.ms < b->ms)) b = &t;
+            if (t.status == ABM_OK && (!b || t.ms < b->ms * (1.0 - kMargin))) b = &t;
         return b;
     }
 };

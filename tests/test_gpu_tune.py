@@ -67,7 +67,13 @@ def test_autotune_measures_and_picks_a_valid_blocking(ctx):
     ok = [t for t in trials if t["status"] == abm.ABM_OK]
     assert {t["cfg"]["block_L"] for t in ok} >= {128, 256, 512}
     assert all(t["ms"] > 0 for t in ok)
-    assert best == min(ok, key=lambda t: t["ms"])["cfg"]
+    # the fastest in trial order, a later trial winning only by more than 2%
+    inc = None
+    for t in ok:
+        if inc is None or t["ms"] < inc["ms"] * (1.0 - 0.02):
+            inc = t
+    assert best == inc["cfg"]
+    assert inc["ms"] <= min(t["ms"] for t in ok) / (1.0 - 0.02)
     # the narrow Lorenz group makes the tuner also try column tiles only
     assert any(t["cfg"]["column_tiles_only"] == 1 for t in ok)
     outs, cfg, _ = _solve(ctx, probs, best)
