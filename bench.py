@@ -113,6 +113,14 @@ def serving(abm, torch, inputs, n_req, arena_bytes, prec):
     starts = np.array([done[j]["t_start"] for j in range(n_req)])
     ends = np.array([done[j]["t_done"] for j in range(n_req)])
     conc = [int(np.sum((starts <= t) & (ends > t))) for t in starts]
+    # final states against the stored oracle runs of a subset (the first 16
+    # Duffing requests of at most 8192 steps of the 2000-request stream)
+    errs = []
+    if n_req == 2000:
+        for key, g in load_golden().items():
+            if key.startswith("serving_") and g["index"] < n_req and done[g["index"]]["status"] == 0:
+                y = ys[g["index"]].cpu().numpy()
+                errs.append(float(np.max(np.abs(y - np.array(g["final"])))) / g["max_abs_y"])
     ctx.close()
     return {"requests": n_req, "ok": ok, "rate_per_s": 200.0, "arena_bytes": arena_bytes,
             "far_prec": prec, "p50_s": float(np.percentile(lat, 50)),
@@ -120,6 +128,8 @@ def serving(abm, torch, inputs, n_req, arena_bytes, prec):
             "p50_queue_s": float(np.percentile(queue, 50)),
             "p99_queue_s": float(np.percentile(queue, 99)),
             "mean_concurrent": float(np.mean(conc)), "max_concurrent": int(max(conc)),
+            "max_rel_err_vs_oracle_final_state": max(errs) if errs else None,
+            "err_requests": len(errs),
             "wall_s": wall,
             "throughput_req_per_s": n_req / wall, "history_macs_per_s": macs / wall,
             "workload": "Poisson 200/s, half Duffing (d=2) half Lorenz (d=3), alpha~U[0.90,0.99], "
@@ -128,6 +138,15 @@ def serving(abm, torch, inputs, n_req, arena_bytes, prec):
 
 def normerr(y, ref):
     return float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+
+
+def load_golden():
+    """Stored oracle values (written by tests/golden/make_golden.py), or {}."""
+    path = os.path.join(ROOT, "tests", "golden", "oracle_fullsize.json")
+    if not os.path.exists(path):
+        return {}
+    with open(path) as f:
+        return json.load(f)
 
 
 def time_batch(abm, torch, plan, probs, ys, steps, warmup):
@@ -252,12 +271,12 @@ def lcr_leg(abm, torch, inputs, ctx, prec, tuning, steps=2):
     (0.9, 0.9) as in its figures and incommensurate (0.9, 0.8), in the
     benchmark's far precision and in double, writing the
     stroboscopic (Poincare) section y(kT) (every 1142nd state, h = T/1142).
-    Error against the oracle on the section points of the first 3600 steps of
-    two members (the circuit is chaotic at some F, so later points measure
-    the dynamics' amplification of rounding, not the method).  Reduced
-    precisions run at the blocking chosen for the headline sweep (the same
-    shape), double at the library's default."""
-    import oracle as O
+    Error against the stored oracle values (tests/golden) on the section
+    points of the first 3600 steps of two members (the circuit is chaotic at
+    some F, so later points measure the dynamics' amplification of rounding,
+    not the method).  Reduced precisions run at the blocking chosen for the
+    headline sweep (the same shape), double at the library's default."""
+    gold = load_golden()
     M = inputs.LCR_SECTION_STEPS
     res = {"workload": "forced fractional LCR circuit, sigma=1.015, omega=0.55, a=-1.02, "
                        "b=-0.58, B=1024 forcings F in [0, 0.2], N=65536, h=T/1142, "
@@ -271,14 +290,16 @@ def lcr_leg(abm, torch, inputs, ctx, prec, tuning, steps=2):
             dt, st = time_batch(abm, torch, plan, probs, ys, steps, 1)
             errs = []
             for i in (300, 700):
-                p = probs[i]
-                ref = O.solve(O.RHS_LCR, p.alpha, p.h, 3600, p.x0, p.p, out_stride=M)
+                key = "lcr_sweep_%g_%g_%d" % (al[0], al[1], i)
+                if key not in gold:
+                    continue
+                ref = np.array(gold[key]["y"])
                 y = ys[i].cpu().numpy()[: ref.shape[0] - 1]
                 errs.append(normerr(y, ref[:-1]))
             res["alpha=%s,%s %s" % (al[0], al[1], pr)] = {
                 "ms_per_step": dt * 1e3, "history_macs_per_s": st["history_macs"] / dt,
                 "section_points_per_member": int(ys[0].shape[0]), "blocking": plan.config(),
-                "max_rel_err_vs_oracle_first_3600_steps": max(errs)}
+                "max_rel_err_vs_oracle_first_3600_steps": max(errs) if errs else None}
             plan.close()
     return res
 

@@ -44,6 +44,31 @@ def main():
         out["duffing_sweep_%d" % idx] = {"problem": q.__dict__, "index": idx, "out_stride": 1024,
                                          "y": y.tolist(), "oracle_seconds": dt}
         print("sweep", idx, dt, flush=True)
+    # the LCR forcing sweep (eq. sys.LRC): two members at both order pairs, the
+    # Poincare section points (every 1142nd state) of the first 3600 steps
+    M = inputs.LCR_SECTION_STEPS
+    for al in ((0.9, 0.9), (0.9, 0.8)):
+        sweep = inputs.lcr_sweep(alpha=al)
+        for idx in (300, 700):
+            q = sweep[idx]
+            t = time.time()
+            y = O.solve(RID["LCR"], q.alpha, q.h, 3600, q.x0, q.p, out_stride=M)
+            out["lcr_sweep_%g_%g_%d" % (al[0], al[1], idx)] = {
+                "problem": q.__dict__, "index": idx, "steps": 3600, "out_stride": M,
+                "y": y.tolist(), "oracle_seconds": time.time() - t}
+            print("lcr", al, idx, flush=True)
+    # the serving stream (2000 requests, seed 1710): the first 16 Duffing
+    # requests of at most 8192 steps, final state and largest |y|
+    reqs = inputs.serving_stream()
+    picked = [i for i, r in enumerate(reqs) if r.problem.rhs == "DUFFING" and r.problem.N <= 8192][:16]
+    for i in picked:
+        q = reqs[i].problem
+        t = time.time()
+        y = O.solve(RID["DUFFING"], q.alpha, q.h, q.N, q.x0, q.p, out_stride=1)
+        out["serving_%d" % i] = {"problem": q.__dict__, "index": i, "final": y[-1].tolist(),
+                                 "max_abs_y": float(np.max(np.abs(y))),
+                                 "oracle_seconds": time.time() - t}
+    print("serving", picked, flush=True)
     with open(os.path.join(HERE, "oracle_fullsize.json"), "w") as f:
         json.dump(out, f, indent=1)
 
