@@ -160,6 +160,7 @@ inline int far_class(int prec, bool narrow)
 {
     return narrow ? (prec == 0 ? 5 : 6) : prec;
 }
+inline bool is_narrow_class(int cls) { return cls >= 5; }
 // Blocked convolution (narrow groups, fp64 / fp32 far field): product tiles
 // of a block for cols columns, whether a group qualifies, its split plan over
 // the K + L - 16 rows of shifts and the bound of that plan's slice count.
@@ -170,6 +171,10 @@ int hankel_chunk_rows();
 int hankel_split_plan(int64_t kfar, int L, int max_split, int* nchunks, int* chunks_per_split);
 int hankel_split_bound(int64_t kfar_max, int L, int max_split);
 size_t hankel_lds_bytes(int L, int max_tiles, int prec);
+// Sums the partial slices of each narrow far item into its first slice (in
+// slice order); the chain items of those blocks then read one slice.
+hipError_t launch_far_reduce(const GroupDev* groups, const FarItem* items, int n, int max_cols,
+                             int L, hipStream_t st);
 hipError_t launch_far_hankel(const GroupDev* groups, const FarItem* items, int n, int max_tiles,
                              int max_nsplit, int L, int prec, hipStream_t st);
 

@@ -76,6 +76,7 @@ struct Span {
     int32_t count = 0;
     int32_t max_x = 0;
     int32_t max_y = 0;
+    int32_t max_cols = 0;   // far spans: the widest item (columns)
 };
 
 }  // namespace abm

@@ -391,15 +391,23 @@ abm_status batch_setup(abm_plan_s* pl)
             for (int64_t k = sp.offset; k < (int64_t)far_all.size(); ++k) {
                 sp.max_x = std::max(sp.max_x, far_all[k].ncoltiles);
                 sp.max_y = std::max(sp.max_y, far_all[k].nsplit);
+                sp.max_cols = std::max(sp.max_cols, far_all[k].ncols);
             }
         }
         for (int kind = 0; kind < kChainKinds; ++kind) {
             Span& sp = pl->chain_spans[t * kChainKinds + kind];
             sp.offset = (int64_t)chain_all.size();
             for (int gi = 0; gi < ngroups; ++gi)
-                if (chain_kind(pl->groups[gi].rhs, pl->groups[gi].per_comp) == kind)
+                if (chain_kind(pl->groups[gi].rhs, pl->groups[gi].per_comp) == kind) {
+                    const size_t c0 = chain_all.size();
                     block_items(pl->groups[gi], gi, t, L, kchunk, pl->max_split, memberN[gi],
                                 nullptr, &chain_all);
+                    // a narrow group's slices are summed into the first one
+                    // after its far field (launch_far_reduce)
+                    if (pl->groups[gi].narrow)
+                        for (size_t k = c0; k < chain_all.size(); ++k)
+                            chain_all[k].nsplit = std::min(chain_all[k].nsplit, 1);
+                }
             sp.count = (int32_t)((int64_t)chain_all.size() - sp.offset);
         }
     }
@@ -574,6 +582,10 @@ struct TickEnqueuer {
                     });
                     if (e != hipSuccess) return hip_fail(e, "far-field launch");
                     ++far_launches;
+                    if (is_narrow_class(cls) && sp.max_y > 1 &&
+                        (e = launch_far_reduce(pl->groups_dev, pl->far_items_dev + sp.offset, sp.count,
+                                               sp.max_cols, L, sf)) != hipSuccess)
+                        return hip_fail(e, "partial reduction launch");
                 }
                 if (!alt) {
                     ev_far = sync_event();

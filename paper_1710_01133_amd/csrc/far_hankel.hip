@@ -373,6 +373,43 @@ size_t hankel_lds_bytes(int L, int max_tiles, int prec)
     return stage > red ? stage : red;
 }
 
+// The partial slices of a narrow far item summed into its first slice, in
+// slice order (the order in which the chain would add them).  One thread per
+// (column, row) of the item; the chain of the block then reads one slice.
+// Many threads share the loads that one chain wave would otherwise make one
+// lane at a time.
+__global__ __launch_bounds__(256) void k_far_reduce(const GroupDev* groups, const FarItem* items,
+                                                    int L)
+{
+    const FarItem it = items[blockIdx.y];
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;   // col * 2L + row
+    if (it.nsplit < 2 || e >= (int64_t)it.ncols * 2 * L) return;
+    const GroupDev& G = groups[it.group];
+    const gptr<double> base = as_global(G.part[(it.mL / L) & 1]) + (int64_t)it.coff * (2 * L) + e;
+    const size_t ss = (size_t)it.ldP * (2 * L);
+    double acc = base[0];
+    int sl = 1;
+    for (; sl + 8 <= it.nsplit; sl += 8) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) v[u] = base[(size_t)(sl + u) * ss];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; sl < it.nsplit; ++sl) acc += base[(size_t)sl * ss];
+    base[0] = acc;
+}
+
+hipError_t launch_far_reduce(const GroupDev* groups, const FarItem* items, int n, int max_cols,
+                             int L, hipStream_t st)
+{
+    if (n < 1 || max_cols < 1) return hipSuccess;
+    const int64_t elems = (int64_t)max_cols * 2 * L;
+    hipLaunchKernelGGL(k_far_reduce, dim3((unsigned)((elems + 255) / 256), (unsigned)n), dim3(256), 0, st,
+                       groups, items, L);
+    return hipGetLastError();
+}
+
 hipError_t launch_far_hankel(const GroupDev* groups, const FarItem* items, int n, int max_tiles,
                              int max_nsplit, int L, int prec, hipStream_t st)
 {
