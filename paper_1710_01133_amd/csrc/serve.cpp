@@ -424,9 +424,13 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
                 (r->g.narrow && !hankel_fits(r->g.prec, it.ncols, S->L)))
                 return fail(ABM_EDEVICE, "internal: far item exceeds a request's partial buffer");
         }
-        for (size_t k = c0; k < chain[kind].size(); ++k)
+        for (size_t k = c0; k < chain[kind].size(); ++k) {
             if (chain[kind][k].nsplit > r->g.nsplit_cap)
                 return fail(ABM_EDEVICE, "internal: chain item exceeds a request's partial buffer");
+            // a narrow request's slices are summed into the first one after
+            // its far field (launch_far_reduce)
+            if (r->g.narrow) chain[kind][k].nsplit = std::min(chain[kind][k].nsplit, 1);
+        }
     }
     for (Request* r : fresh) {
         ChainItem c{};
@@ -447,6 +451,7 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
         for (const FarItem& it : far[k]) {
             fsp[k].max_x = std::max(fsp[k].max_x, it.ncoltiles);
             fsp[k].max_y = std::max(fsp[k].max_y, it.nsplit);
+            fsp[k].max_cols = std::max(fsp[k].max_cols, it.ncols);
             fh[nf++] = it;
         }
     }
@@ -485,6 +490,10 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
         e = launch_far(S->groups_dev, fd + fsp[k].offset, fsp[k].count, fsp[k].max_x, fsp[k].max_y,
                        S->kchunk, S->L, k, sf);
         if (e != hipSuccess) return hip_fail(e, "far-field launch");
+        if (is_narrow_class(k) && fsp[k].max_y > 1 &&
+            (e = launch_far_reduce(S->groups_dev, fd + fsp[k].offset, fsp[k].count, fsp[k].max_cols,
+                                   S->L, sf)) != hipSuccess)
+            return hip_fail(e, "partial reduction launch");
     }
     if ((e = hipStreamWaitEvent(sc, up, 0)) != hipSuccess) return hip_fail(e, "wait");
     for (int k = 0; k < kRhsCount; ++k) {
