@@ -378,6 +378,8 @@ size_t hankel_lds_bytes(int L, int max_tiles, int prec)
 // (column, row) of the item; the chain of the block then reads one slice.
 // Many threads share the loads that one chain wave would otherwise make one
 // lane at a time.
+namespace {
+
 __global__ __launch_bounds__(256) void k_far_reduce(const GroupDev* groups, const FarItem* items,
                                                     int L)
 {
@@ -399,6 +401,8 @@ __global__ __launch_bounds__(256) void k_far_reduce(const GroupDev* groups, cons
     for (; sl < it.nsplit; ++sl) acc += base[(size_t)sl * ss];
     base[0] = acc;
 }
+
+}  // namespace
 
 hipError_t launch_far_reduce(const GroupDev* groups, const FarItem* items, int n, int max_cols,
                              int L, hipStream_t st)
