@@ -39,6 +39,9 @@ namespace {
 constexpr int kMaxActive = 1024;     // group slots on the device
 constexpr int kMaxFar = 4 * kMaxActive;   // far items per tick (one per component at most)
 constexpr int kRing = 8;             // ticks in flight (item staging ring)
+// one ring slot: a tick's far, chain and init items, packed in that order
+constexpr size_t kSlotBytes = kMaxFar * sizeof(FarItem) + 2 * kMaxActive * sizeof(ChainItem);
+static_assert(sizeof(FarItem) % alignof(ChainItem) == 0, "packed item staging");
 constexpr size_t kAlign = 256;
 
 double now_s()
@@ -98,12 +101,8 @@ struct ServeState {
     hipStream_t s0 = nullptr, s1 = nullptr;
     GroupDev* groups_dev = nullptr;
     GroupDev* groups_host = nullptr;      // pinned staging, one entry per slot
-    FarItem* far_dev = nullptr;           // [kRing][kMaxFar]
-    ChainItem* chain_dev = nullptr;       // [kRing][kMaxActive]
-    ChainItem* init_dev = nullptr;        // [kRing][kMaxActive]
-    FarItem* far_host = nullptr;
-    ChainItem* chain_host = nullptr;
-    ChainItem* init_host = nullptr;
+    char* stage_dev = nullptr;            // [kRing][kSlotBytes] items of a tick
+    char* stage_host = nullptr;           // pinned, the same
     hipEvent_t ring_ev[kRing] = {};
     bool ring_live[kRing] = {};
     int64_t tick = 0;
@@ -270,15 +269,11 @@ abm_status server_init(ServeState* S)
 
     abm_status s;
     if ((s = dev_alloc((void**)&S->groups_dev, kMaxActive * sizeof(GroupDev), "group slots")) ||
-        (s = dev_alloc((void**)&S->far_dev, (size_t)kRing * kMaxFar * sizeof(FarItem), "far ring")) ||
-        (s = dev_alloc((void**)&S->chain_dev, (size_t)kRing * kMaxActive * sizeof(ChainItem), "chain ring")) ||
-        (s = dev_alloc((void**)&S->init_dev, (size_t)kRing * kMaxActive * sizeof(ChainItem), "init ring")) ||
+        (s = dev_alloc((void**)&S->stage_dev, (size_t)kRing * kSlotBytes, "item ring")) ||
         (s = dev_alloc((void**)&S->status, sizeof(uint32_t), "status")))
         return s;
     if ((e = hipHostMalloc((void**)&S->groups_host, kMaxActive * sizeof(GroupDev), hipHostMallocDefault)) ||
-        (e = hipHostMalloc((void**)&S->far_host, (size_t)kRing * kMaxFar * sizeof(FarItem), hipHostMallocDefault)) ||
-        (e = hipHostMalloc((void**)&S->chain_host, (size_t)kRing * kMaxActive * sizeof(ChainItem), hipHostMallocDefault)) ||
-        (e = hipHostMalloc((void**)&S->init_host, (size_t)kRing * kMaxActive * sizeof(ChainItem), hipHostMallocDefault)))
+        (e = hipHostMalloc((void**)&S->stage_host, (size_t)kRing * kSlotBytes, hipHostMallocDefault)))
         return hip_fail(e, "pinned staging");
     for (int i = 0; i < kRing; ++i)
         if ((e = hipEventCreateWithFlags(&S->ring_ev[i], hipEventDisableTiming)) != hipSuccess)
@@ -402,9 +397,6 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
     hipError_t e;
     if (S->ring_live[ring] && (e = hipEventSynchronize(S->ring_ev[ring])) != hipSuccess)
         return hip_fail(e, "ring wait");
-    FarItem* fh = S->far_host + (size_t)ring * kMaxFar;
-    ChainItem* ch = S->chain_host + (size_t)ring * kMaxActive;
-    ChainItem* ih = S->init_host + (size_t)ring * kMaxActive;
     // items grouped by class: far by launch class, chain by kind, init by rhs
     std::vector<FarItem> far[kFarClasses];
     std::vector<ChainItem> chain[kChainKinds], init[kRhsCount];
@@ -442,8 +434,18 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
     size_t nfar = 0, nchain = 0;
     for (const auto& v : far) nfar += v.size();
     for (const auto& v : chain) nchain += v.size();
-    if (nfar > (size_t)kMaxFar || nchain > (size_t)kMaxActive)
+    size_t ninit = 0;
+    for (const auto& v : init) ninit += v.size();
+    if (nfar > (size_t)kMaxFar || nchain > (size_t)kMaxActive || ninit > (size_t)kMaxActive)
         return fail(ABM_EDEVICE, "internal: more items than the staging ring holds");
+    // the slot holds far, chain and init items back to back, uploaded by one copy
+    char* hb = S->stage_host + (size_t)ring * kSlotBytes;
+    char* db = S->stage_dev + (size_t)ring * kSlotBytes;
+    const size_t off_c = nfar * sizeof(FarItem), off_i = off_c + nchain * sizeof(ChainItem);
+    const size_t used = off_i + ninit * sizeof(ChainItem);
+    FarItem* fh = reinterpret_cast<FarItem*>(hb);
+    ChainItem* ch = reinterpret_cast<ChainItem*>(hb + off_c);
+    ChainItem* ih = reinterpret_cast<ChainItem*>(hb + off_i);
     Span fsp[kFarClasses], csp[kChainKinds], isp[kRhsCount];
     for (int k = 0; k < kFarClasses; ++k) {
         fsp[k].offset = nf;
@@ -465,9 +467,9 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
         isp[k].count = (int32_t)init[k].size();
         for (const ChainItem& it : init[k]) ih[ni++] = it;
     }
-    FarItem* fd = S->far_dev + (size_t)ring * kMaxFar;
-    ChainItem* cd = S->chain_dev + (size_t)ring * kMaxActive;
-    ChainItem* id = S->init_dev + (size_t)ring * kMaxActive;
+    FarItem* fd = reinterpret_cast<FarItem*>(db);
+    ChainItem* cd = reinterpret_cast<ChainItem*>(db + off_c);
+    ChainItem* id = reinterpret_cast<ChainItem*>(db + off_i);
     // The two streams swap roles every tick (as in the batched path): the
     // chains of tick t run on sc = S[t mod 2]; the item uploads and the far
     // field of the next blocks go to the other stream sf, after the chains of
@@ -477,11 +479,7 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
     // of their own blocks, launched a tick earlier, precedes them on sc.
     hipStream_t sc = (S->tick & 1) ? S->s1 : S->s0;
     hipStream_t sf = (S->tick & 1) ? S->s0 : S->s1;
-    if (nf && (e = hipMemcpyAsync(fd, fh, nf * sizeof(FarItem), hipMemcpyHostToDevice, sf)))
-        return hip_fail(e, "item upload");
-    if (nc && (e = hipMemcpyAsync(cd, ch, nc * sizeof(ChainItem), hipMemcpyHostToDevice, sf)))
-        return hip_fail(e, "item upload");
-    if (ni && (e = hipMemcpyAsync(id, ih, ni * sizeof(ChainItem), hipMemcpyHostToDevice, sf)))
+    if (used && (e = hipMemcpyAsync(db, hb, used, hipMemcpyHostToDevice, sf)))
         return hip_fail(e, "item upload");
     hipEvent_t up = pooled_event(S);
     if ((e = hipEventRecord(up, sf)) != hipSuccess) return hip_fail(e, "event");
@@ -667,14 +665,10 @@ void serve_shutdown(abm_ctx* ctx)
         if (S->all.find(r->ticket) == S->all.end()) delete r;
     if (S->arena) (void)hipFree(S->arena);
     dev_free(S->groups_dev);
-    dev_free(S->far_dev);
-    dev_free(S->chain_dev);
-    dev_free(S->init_dev);
+    dev_free(S->stage_dev);
     dev_free(S->status);
     if (S->groups_host) (void)hipHostFree(S->groups_host);
-    if (S->far_host) (void)hipHostFree(S->far_host);
-    if (S->chain_host) (void)hipHostFree(S->chain_host);
-    if (S->init_host) (void)hipHostFree(S->init_host);
+    if (S->stage_host) (void)hipHostFree(S->stage_host);
     for (auto ev : S->ring_ev)
         if (ev) (void)hipEventDestroy(ev);
     for (auto ev : S->ev_pool) (void)hipEventDestroy(ev);
