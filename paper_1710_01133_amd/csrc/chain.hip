@@ -498,12 +498,20 @@ hipError_t launch_mixed_l(const GroupDev* groups, const ChainItem* items, int n,
     return hipGetLastError();
 }
 
+constexpr int kFewChains = 32;            // chain items of a launch
+constexpr size_t kOwnCuLds = 150000;      // bytes: no far-field workgroup fits beside
+
 template <int R, int D, int L, int W, bool PC>
 hipError_t launch_rdl(const GroupDev* groups, const ChainItem* items, int n, uint32_t* status,
                       hipStream_t st)
 {
     const dim3 grid((unsigned)((n + W - 1) / W));
-    const size_t shmem = (size_t)W * (PC ? D : 1) * 4 * L * sizeof(double);
+    // A tick with few chains is bound by them: each chain workgroup then
+    // asks for (nearly) the CU's whole LDS, so that no far-field workgroup
+    // shares its CU (a far-field wave beside a chain wave slowed one long
+    // trajectory's chain from 24 to ~110 µs per block).
+    const size_t need = (size_t)W * (PC ? D : 1) * 4 * L * sizeof(double);
+    const size_t shmem = n <= kFewChains && need < kOwnCuLds ? kOwnCuLds : need;
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_chain<R, D, L, W, PC>), shmem);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_chain<R, D, L, W, PC>), grid, dim3(64 * W), shmem, st, groups, items, n,
