@@ -61,7 +61,7 @@ def _load():
     lib.oracle_steps_from_states_gen.argtypes = [ctypes.c_int, ctypes.c_int, c_dp,
                                                  ctypes.c_double, c_dp, c_dp, c_dp, c_dp,
                                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
-                                                 c_dp]
+                                                 c_dp, c_dp]
     lib.oracle_steps_from_states_gen.restype = ctypes.c_int
     lib.oracle_solve_batch_gen.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32), c_dp, c_dp,
@@ -69,6 +69,8 @@ def _load():
                                            ctypes.c_int64, ctypes.POINTER(c_dp),
                                            ctypes.POINTER(ctypes.c_int32), ctypes.c_int]
     lib.oracle_solve_batch_gen.restype = ctypes.c_int
+    lib.oracle_history_sum.argtypes = [c_dp, c_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
+    lib.oracle_history_sum.restype = ctypes.c_double
     lib.oracle_num_threads.argtypes = []
     lib.oracle_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -148,8 +150,11 @@ def solve(rhs: int, alpha, h: float, N: int, x0, p, out_stride: int = 1,
 
 
 def steps_from_states(rhs: int, alpha, h: float, x0, p, y_hist: np.ndarray,
-                      s_list, x1=None) -> np.ndarray:
-    """y_s recomputed for each s in s_list from the given states y_0..y_{s-1}."""
+                      s_list, x1=None, return_scale: bool = False):
+    """y_s recomputed for each s in s_list from the given states y_0..y_{s-1}.
+    With return_scale, also the size of each step's history terms per
+    component, h^alpha (sum |b_{n-k} F_k| + |c_n F_0| + sum |a_{n-k} F_k|):
+    rounding inside the sums moves y_s by a small multiple of eps times it."""
     lib = _load()
     d = RHS_DIM[rhs]
     x, pp = _params(rhs, d, x0, p)
@@ -159,13 +164,15 @@ def steps_from_states(rhs: int, alpha, h: float, x0, p, y_hist: np.ndarray,
     if s_arr.size and (s_arr.min() < 1 or s_arr.max() > yh.shape[0]):
         raise ValueError("s out of range of the given history")
     out = np.zeros((s_arr.size, d), np.float64)
+    scale = np.zeros((s_arr.size, d), np.float64) if return_scale else None
     rc = lib.oracle_steps_from_states_gen(rhs, d, _dp(al), float(h), _dp(x), _dp(v), _dp(pp),
                                           _dp(yh),
                                           s_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
-                                          int(s_arr.size), _dp(out))
+                                          int(s_arr.size), _dp(out),
+                                          _dp(scale) if return_scale else None)
     if rc != 0:
         raise ValueError("oracle_steps_from_states failed: %d" % rc)
-    return out
+    return (out, scale) if return_scale else out
 
 
 def solve_batch(rhs, alpha, h, N, x0, p, out_stride: int = 0, compensated: bool = False,
@@ -198,6 +205,17 @@ def solve_batch(rhs, alpha, h, N, x0, p, out_stride: int = 0, compensated: bool 
     if rc != 0:
         raise ValueError("oracle_solve_batch failed: %s" % st)
     return outs
+
+
+def history_sum(w, F, k_lo: int, n: int, compensated: bool) -> float:
+    """sum_{k=k_lo..n} w[n-k] F[k] with the solver's summation (plain
+    ascending or Neumaier-compensated)."""
+    w = np.ascontiguousarray(np.asarray(w, np.float64))
+    F = np.ascontiguousarray(np.asarray(F, np.float64))
+    if not (0 <= k_lo <= n < F.size and n - k_lo < w.size):
+        raise ValueError("index range outside the arrays")
+    return float(_load().oracle_history_sum(_dp(w), _dp(F), int(k_lo), int(n),
+                                            1 if compensated else 0))
 
 
 def num_threads() -> int:

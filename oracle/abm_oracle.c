@@ -129,6 +129,8 @@ int oracle_weights_at(double alpha, int64_t k0, int64_t n, double *b, double *a,
     const __float128 al = (__float128)alpha;
     const __float128 g1 = (__float128)tgamma(alpha + 1.0);
     const __float128 g2 = (__float128)tgamma(alpha + 2.0);
+    /* every index is independent of the others */
+#pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; ++i) {
         const int64_t k = k0 + i;
         const __float128 kq = (__float128)k;
@@ -171,6 +173,15 @@ static double hist_sum(const double *w, const double *F, int d, int comp_idx,
         }
     }
     return s + e;
+}
+
+/* The history sum sum_{k=k_lo..n} w[n-k] F[k] of one scalar sequence, with
+ * the summation the solver uses (comp = 0 plain ascending, comp = 1
+ * Neumaier-compensated); exported so that the tests can pin both variants on
+ * ill-conditioned sums. */
+double oracle_history_sum(const double *w, const double *F, int64_t k_lo, int64_t n, int comp)
+{
+    return hist_sum(w, F, 1, 0, k_lo, n, comp);
 }
 
 /* Weight tables and scalar factors of one component of order alpha. */
@@ -310,17 +321,31 @@ int oracle_solve(int rhs, int d, double alpha, double h, int64_t N,
     return oracle_solve_gen(rhs, d, al, h, N, x0, NULL, p, out_stride, y_out, comp);
 }
 
+/* sum_{k=k_lo..n} |w[n-k] F[k]| of one component: the size of the terms of
+ * a history sum, which bounds what rounding inside the sum can change. */
+static double hist_abs_sum(const double *w, const double *F, int d, int comp_idx,
+                           int64_t k_lo, int64_t n)
+{
+    double s = 0.0;
+    for (int64_t k = k_lo; k <= n; ++k)
+        s += fabs(w[n - k] * F[k * d + comp_idx]);
+    return s;
+}
+
 /*
  * Single steps recomputed from a given state history, for checking outputs of
  * a long run one by one.  y_hist holds y_0 .. y_{smax-1} (d doubles each,
  * smax = max over s_list); for every s in s_list the oracle forms
  * F_k = f(t_k, y_hist_k) for k < s and applies one predictor-corrector step
  * (the same formulas as oracle_solve_gen), writing y_s to y_out + i*d.
+ * scale_out (may be NULL) receives, per listed step and component, the size
+ * of the history terms entering y_s:
+ *   h^alpha * ( sum_{k=0..n} |b_{n-k} F_k| + |c_n F_0| + sum_{k=1..n} |a_{n-k} F_k| ).
  */
 int oracle_steps_from_states_gen(int rhs, int d, const double *alphas, double h,
                                  const double *x0, const double *x1, const double *p,
                                  const double *y_hist, const int64_t *s_list, int32_t ns,
-                                 double *y_out)
+                                 double *y_out, double *scale_out)
 {
     if (rhs_dim(rhs) != d || !alphas || !orders_ok(d, alphas) || !(h > 0.0) || ns < 0)
         return ORC_EINVAL;
@@ -345,10 +370,13 @@ int oracle_steps_from_states_gen(int rhs, int d, const double *alphas, double h,
         free(F);
         return rc;
     }
+#pragma omp parallel for schedule(static)
     for (int64_t k = 0; k < smax; ++k)
         rhs_eval(rhs, p, (double)k * h, y_hist + k * d, F + k * d);
-    double yp[8], fp[8];
+    /* the listed steps are independent of each other */
+#pragma omp parallel for schedule(dynamic, 1)
     for (int32_t j = 0; j < ns; ++j) {
+        double yp[8], fp[8];
         const int64_t s = s_list[j], n = s - 1;
         const double t = (double)s * h;
         for (int i = 0; i < d; ++i)
@@ -359,6 +387,10 @@ int oracle_steps_from_states_gen(int rhs, int d, const double *alphas, double h,
             double hs = hist_sum(T[i].a, F, d, i, 1, n, 0);
             y_out[j * d + i] = start_term(alphas[i], x0[i], x1, i, t) +
                                T[i].ha * ((T[i].c[n] * F[i] + hs) + fp[i] / T[i].g2);
+            if (scale_out)
+                scale_out[j * d + i] = T[i].ha * (hist_abs_sum(T[i].b, F, d, i, 0, n) +
+                                                  fabs(T[i].c[n] * F[i]) +
+                                                  hist_abs_sum(T[i].a, F, d, i, 1, n));
         }
     }
     free_tables(T, d);
@@ -375,7 +407,8 @@ int oracle_steps_from_states(int rhs, int d, double alpha, double h, const doubl
     double al[8];
     for (int i = 0; i < d; ++i)
         al[i] = alpha;
-    return oracle_steps_from_states_gen(rhs, d, al, h, x0, NULL, p, y_hist, s_list, ns, y_out);
+    return oracle_steps_from_states_gen(rhs, d, al, h, x0, NULL, p, y_hist, s_list, ns, y_out,
+                                        NULL);
 }
 
 /*

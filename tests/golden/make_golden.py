@@ -2,8 +2,18 @@
 
 Calls only the CPU oracle (oracle/) on the seeded workloads of
 paper_1710_01133_amd.inputs; nothing here touches the GPU library.  Run from
-the repository root:  python tests/golden/make_golden.py
+the repository root:  python tests/golden/make_golden.py [--parts base sweep serving]
+
+  base     oracle_fullsize.json: the single 200000-step oscillator, four sweep
+           members, the LCR sweep members, 16 short serving requests
+  sweep    duffing_sweep_all.npy: every one of the 1024 members of the forcing
+           sweep, every 1024th state, shape (1024, 65, 2)
+  serving  serving_first64.json: the first 64 requests of the 2000-request
+           serving stream (Duffing and Lorenz, N up to 262144): final state,
+           largest |y_s| over the run, and the noise floor of the final state
+           (its change when x0 is scaled by 1 + 1e-14)
 """
+import argparse
 import json
 import os
 import sys
@@ -28,7 +38,53 @@ def run(p, stride):
     return y, time.time() - t
 
 
+def sweep_all():
+    """Every member of the forcing sweep, OpenMP over trajectories."""
+    sweep = inputs.duffing_sweep()
+    t = time.time()
+    ys = O.solve_batch([RID[q.rhs] for q in sweep], [q.alpha for q in sweep], [q.h for q in sweep],
+                       [q.N for q in sweep], [q.x0 for q in sweep], [q.p for q in sweep],
+                       out_stride=1024)
+    arr = np.stack(ys).astype(np.float64)
+    np.save(os.path.join(HERE, "duffing_sweep_all.npy"), arr, allow_pickle=False)
+    print("sweep_all", arr.shape, time.time() - t, flush=True)
+
+
+def serving_first64():
+    """The first 64 requests of the serving stream, and each one's noise floor."""
+    reqs = inputs.serving_stream()[:64]
+    probs = [r.problem for r in reqs]
+    t = time.time()
+    args = ([RID[q.rhs] for q in probs], [q.alpha for q in probs], [q.h for q in probs],
+            [q.N for q in probs])
+    ys = O.solve_batch(*args, [q.x0 for q in probs], [q.p for q in probs], out_stride=1)
+    nudged = O.solve_batch(*args, [tuple(v * (1 + 1e-14) for v in q.x0) for q in probs],
+                           [q.p for q in probs], out_stride=0)
+    out = {}
+    for i, (q, y, yn) in enumerate(zip(probs, ys, nudged)):
+        mx = float(np.max(np.abs(y)))
+        out[str(i)] = {"problem": q.__dict__, "index": i, "final": y[-1].tolist(),
+                       "max_abs_y": mx,
+                       "noise_floor": float(np.max(np.abs(yn[-1] - y[-1]))) / mx}
+    with open(os.path.join(HERE, "serving_first64.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print("serving_first64", time.time() - t, flush=True)
+
+
 def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--parts", nargs="+", default=["base", "sweep", "serving"],
+                    choices=["base", "sweep", "serving"])
+    parts = ap.parse_args().parts
+    if "sweep" in parts:
+        sweep_all()
+    if "serving" in parts:
+        serving_first64()
+    if "base" in parts:
+        base()
+
+
+def base():
     out = {}
     # forced Duffing oscillator, alpha=0.9, h=1e-3, N=200000: every 1000th state
     p = inputs.duffing_single()

@@ -509,3 +509,79 @@ def test_invalid_arguments_rejected():
         O.solve(O.RHS_LINEAR, 0.5, -0.1, 10, [1.0], [1.0])
     with pytest.raises(ValueError):
         O.solve(O.RHS_LINEAR, 0.5, 0.1, 0, [1.0], [1.0])
+
+
+def _ill_conditioned_sum(seed, n):
+    """Weights that are powers of two (so every product w[n-k] F[k] is exact
+    in double) and a history of large terms that cancel, plus a small
+    remainder: the exact sum is tiny beside the terms."""
+    rng = np.random.default_rng(seed)
+    w = np.ldexp(1.0, rng.integers(-3, 4, n + 1)).astype(np.float64)
+    # products in groups of four: two full-precision terms of order one,
+    # then +B_j and -B_j (B_j ~ 2^40, an integer).  Adding B_j to a running
+    # sum that carries fine bits drops them to B_j's grid (2^-12), and the
+    # term added is then the larger one, the case that separates Neumaier's
+    # compensation from Kahan's
+    big = np.ldexp(rng.integers(1 << 19, 1 << 20, n // 4 + 1).astype(np.float64), 20)
+    k = np.arange(n + 1)
+    prod = rng.uniform(-1.0, 1.0, n + 1)
+    prod[k % 4 == 2] = big[k[k % 4 == 2] // 4]
+    prod[k % 4 == 3] = -big[k[k % 4 == 3] // 4]
+    F = prod / w[n - k]                     # exact: w is a power of two
+    terms = [float(w[n - j]) * float(F[j]) for j in range(n + 1)]
+    return w, F, terms
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_compensated_history_sum_matches_exactly_rounded_sum(seed):
+    """The compensated history sum (Neumaier's variant of Kahan summation) on a
+    sum whose terms reach ~2^40 and cancel to ~10: the plain ascending sum
+    loses at least six digits, the compensated one stays within a few ulp of
+    the exactly rounded sum (math.fsum, Shewchuk's algorithm).  A wrong sign
+    in the compensation, Kahan's single branch in place of Neumaier's two, or
+    a compensation that is never added back fails the second assertion."""
+    n = 399                                  # 100 groups of four terms
+    w, F, terms = _ill_conditioned_sum(seed, n)
+    exact = math.fsum(terms)
+    # the condition number sum|t| / |sum t|
+    assert sum(abs(t) for t in terms) / abs(exact) > 1e9
+    plain = O.history_sum(w, F, 0, n, compensated=False)
+    comp = O.history_sum(w, F, 0, n, compensated=True)
+    assert abs(plain - exact) / abs(exact) > 1e-10
+    assert abs(comp - exact) <= 4 * np.spacing(abs(exact)), (comp, exact)
+
+
+def test_history_sum_index_order_and_lower_limit():
+    """sum_{k=k_lo..n} w[n-k] F[k]: the weight index runs against the history
+    index, and k_lo = 1 drops F[0] (the corrector's sum, whose k = 0 term
+    enters through c_n).  Both variants, checked against a 50-digit sum."""
+    rng = np.random.default_rng(7)
+    n = 37
+    w = rng.uniform(0.1, 1.0, n + 1)
+    F = rng.uniform(-1.0, 1.0, n + 1)
+    for k_lo in (0, 1):
+        with mp.workdps(50):
+            ref = mp.fsum(mp.mpf(float(w[n - k])) * mp.mpf(float(F[k])) for k in range(k_lo, n + 1))
+        for comp in (False, True):
+            got = O.history_sum(w, F, k_lo, n, compensated=comp)
+            assert abs(got - float(ref)) <= 1e-14 * float(mp.fsum(abs(x) for x in F)), (k_lo, comp)
+
+
+@pytest.mark.parametrize("alpha", [0.45, 0.9, 1.0])
+def test_step_recompute_term_size_closed_form(alpha):
+    """With f = c0 > 0 every history term is positive, so the size of the
+    terms equals the sums themselves: h^a sum b_{n-k} c0 = c0 t^a / Gamma(a+1)
+    (the product-rectangle rule is exact for constants) and
+    h^a (c_n c0 + sum a_{n-k} c0) = c0 t^a / Gamma(a+1) - h^a c0 / Gamma(a+2)
+    (the product-trapezoid rule too, less the weight of f at t_s itself).
+    A missing |c_n F_0| term, a missing sum or a wrong h^a fails this."""
+    c0, h, N = 0.7, 2.0 ** -6, 500
+    y = O.solve(O.RHS_POLY, alpha, h, N, [0.3], [c0, 0.0], out_stride=1)
+    s_list = [1, 2, 17, 256, 499, 500]
+    ys, scale = O.steps_from_states(O.RHS_POLY, alpha, h, [0.3], [c0, 0.0], y[:-1], s_list,
+                                    return_scale=True)
+    assert np.array_equal(ys, y[s_list])
+    for j, s in enumerate(s_list):
+        t = s * h
+        ref = 2 * c0 * t ** alpha / math.gamma(alpha + 1) - h ** alpha * c0 / math.gamma(alpha + 2)
+        assert abs(scale[j, 0] - ref) <= 1e-13 * ref, (s, scale[j, 0], ref)
