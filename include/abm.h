@@ -105,11 +105,14 @@ typedef struct abm_stats {
 } abm_stats;
 
 typedef struct abm_result {
-    abm_status status;    /* ABM_OK, ABM_EDEVICE (non-finite state), ABM_ECANCELED */
+    abm_status status;    /* ABM_OK; ABM_EDEVICE: a state of this request became non-finite
+                             (the chains raise a status word of the request's own, so its
+                             batch-mates are not affected), or the server stopped after a
+                             device error; ABM_ENOMEM: larger than the arena; ABM_ECANCELED */
     double t_submit;      /* seconds, library monotonic clock, when abm_submit accepted it */
     double t_start;       /* when its first kernel was enqueued */
     double t_done;        /* when its completion was observed */
-    double max_abs_y;     /* max |y_s| over the written states */
+    double max_abs_y;     /* max |y_N| over the components of the final state */
 } abm_result;
 
 /* Blocking of the batched method.  A zero field takes the default (or the
@@ -139,9 +142,11 @@ typedef struct abm_plan_s abm_plan_t;
  * memory pool of the serving loop (abm_submit); 0 means 1 GiB.
  * Errors: ABM_EINVAL (bad device), ABM_ENOMEM, ABM_EDEVICE. */
 abm_status abm_ctx_create(int device, void *hip_stream, size_t arena_bytes, abm_ctx **out);
-/* Stops the context's server (cancelling queued requests) and frees it.
- * Every plan made on the context must be destroyed before: a plan keeps a
- * pointer to its context. */
+/* Stops the context's server (cancelling queued requests, letting running
+ * ones finish) and frees it, with every request not yet collected by
+ * abm_poll.  Every plan made on the context must be destroyed before: a plan
+ * keeps a pointer to its context.  No other thread may be inside a call on
+ * this context meanwhile. */
 void abm_ctx_destroy(abm_ctx *ctx);
 
 /* Validate and size B problems, allocate their device state, generate their
@@ -240,8 +245,10 @@ abm_status abm_plan_weights(abm_plan_t *plan, int32_t idx, int64_t n, double *b,
  * its history memory fits the arena, batches it with the requests already
  * running and writes y_out (device pointer, sized as for abm_solve).  The
  * problem struct is copied; y_out must stay valid until abm_poll reports it
- * done.  Thread-safe.  Errors: ABM_EINVAL, ABM_ENOMEM (larger than the whole
- * arena). */
+ * done.  Thread-safe: any number of threads may submit, poll and cancel on
+ * one context at once (the serving state is made with the context; tickets
+ * are unique).  Errors: ABM_EINVAL, ABM_ENOMEM (larger than the whole arena),
+ * ABM_EDEVICE (the server stopped after a device error). */
 abm_status abm_submit(abm_ctx *ctx, const abm_problem *prob, double *y_out, uint64_t *ticket);
 
 /* Device memory the serving loop takes from the context's arena for one

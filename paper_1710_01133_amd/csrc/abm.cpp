@@ -198,6 +198,14 @@ abm_status abm_ctx_create(int device, void* hip_stream, size_t arena_bytes, abm_
         return hip_fail(e, "hipGetDeviceProperties");
     }
     c->n_cu = prop.multiProcessorCount;
+    // the serving state exists from the start (its thread and device memory
+    // only from the first submit), so concurrent first submits and polls
+    // never race to create it
+    abm_status s = serve_create(c);
+    if (s != ABM_OK) {
+        delete c;
+        return s;
+    }
     *out = c;
     return ABM_OK;
 }
@@ -389,8 +397,11 @@ abm_status plain_setup(abm_plan_s* pl)
     if (gmin > gcap)
         return fail(ABM_EINVAL, "N=%lld too long for the plain path (history does not fit the LDS of %d workgroups)",
                     (long long)p.N, gcap);
+    // default: the fewest workgroups whose local chunks all fit the
+    // kernel's register prefetch (no weight load on a step's dependent path)
+    const int pref = plain_prefetch_chunks(orders_differ(p) ? p.d : 1);
     int G = env_int("ABM_PLAIN_G", 0);
-    if (G <= 0) G = (int)std::min<int64_t>(nchunks, kPlainDefaultG);
+    if (G <= 0) G = (int)((nchunks + pref - 1) / pref);
     G = std::max(G, gmin);
     G = std::min(G, gcap);
     pl->plain_G = G;

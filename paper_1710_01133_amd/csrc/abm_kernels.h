@@ -46,6 +46,9 @@ struct PlainArgs {
 };
 int plain_max_local_chunks(int d);
 int plain_chunk();
+// Local chunks per workgroup whose weights the kernel prefetches into
+// registers (tables: weight tables in use, 1 or d); beyond it, in-step loads.
+int plain_prefetch_chunks(int tables);
 int plain_part_doubles(int G);
 // kind: chain_kind(rhs, components have their own orders)
 hipError_t launch_plain(const PlainArgs& A, int kind, hipStream_t st);
@@ -103,6 +106,8 @@ struct GroupDev {
     int32_t per_comp;      // 1: components have orders of their own; columns are
                            // component-major (component i of member j at i*cstride + j)
     int32_t deriv;         // bit i: component i has order above 1 (start term x0 + t x1)
+    uint32_t* status;      // status word of this group's own (kStatus* bits), or null: the
+                           // chain then raises the launch's word
 };
 
 // Far field of one group (or of one component of a group whose components

@@ -14,7 +14,6 @@ namespace abm {
 
 constexpr int64_t kMaxSteps = (int64_t)1 << 30;   // step counters are 32-bit on the device
 constexpr int64_t kWeightPad = 2048;                // weight tables extend this far past N
-constexpr int kPlainDefaultG = 32;       // measured: per-step sync cost grows beyond ~32 workgroups
 constexpr size_t kMaxLds = 160 * 1024;              // LDS of one gfx950 CU
 constexpr uint32_t kSpinLimit = 1u << 22;           // a few seconds of polling (each poll is a memory round trip)
 
@@ -67,6 +66,7 @@ struct Group {
     TrajDesc* traj_host = nullptr;  // pinned staging copy of the descriptors
     hipEvent_t traj_ev = nullptr;   // recorded after the last upload from traj_host
     bool traj_ev_live = false;
+    uint32_t* status = nullptr;     // the group's own status word (serving), or null
 };
 
 // A run of work items of one launch: offset/count in an item array and the
@@ -166,6 +166,7 @@ void block_items(const Group& g, int gi, int64_t m, int L, int kchunk, int max_s
                  std::vector<ChainItem>* chain);
 int64_t group_far_split_max(const Group& g, int L, int kchunk, int max_split);
 abm_status choose_blocking(abm_plan_s* pl, const abm_problem* probs, int B);
+abm_status serve_create(abm_ctx* ctx);
 void serve_shutdown(abm_ctx* ctx);
 
 }  // namespace abm

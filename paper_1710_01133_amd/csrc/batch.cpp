@@ -182,6 +182,7 @@ GroupDev group_dev(const Group& g, const WeightTable* const W[4])
     d.narrow = g.narrow ? 1 : 0;
     d.per_comp = g.per_comp ? 1 : 0;
     d.deriv = g.deriv;
+    d.status = g.status;
     return d;
 }
 

@@ -430,7 +430,7 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
             }
         }
     }
-    if (bad) raise_status(status, kStatusNonFinite);
+    if (bad) raise_status(G.status ? G.status : status, kStatusNonFinite);
 }
 
 template <int R, int D, int L, int W, bool PC>

@@ -24,6 +24,7 @@
 #include <deque>
 #include <map>
 #include <mutex>
+#include <new>
 #include <thread>
 #include <unordered_map>
 #include <vector>
@@ -70,9 +71,19 @@ struct Request {
     bool finishing = false;           // last work enqueued; waiting for done_ev
     bool cancel_seen = false;         // cancellation observed by the server thread
     hipEvent_t done_ev = nullptr;
-    double* final_host = nullptr;     // pinned: last state (4 doubles), then the descriptor
+    double* final_host = nullptr;     // pinned: last state (4 doubles), the descriptor, then
+                                      // the request's device status word (final_status)
     double max_abs_y = 0;
 };
+
+// Pinned staging of one request: its final state, the descriptor it uploads
+// and the copy of its status word read at completion.
+constexpr size_t kFinalHostBytes = 4 * sizeof(double) + sizeof(TrajDesc) + sizeof(uint64_t);
+uint32_t* final_status(Request* r)
+{
+    return reinterpret_cast<uint32_t*>(reinterpret_cast<char*>(r->final_host) + 4 * sizeof(double) +
+                                       sizeof(TrajDesc));
+}
 
 }  // namespace
 
@@ -155,7 +166,7 @@ struct ReqLayout {
     TableLayout tab[4];
     int ntab;
     int tab_of[4];                    // table of each component
-    size_t F, F32, Fh[3], Fsc, traj, accn, part, total;
+    size_t F, F32, Fh[3], Fsc, traj, accn, part, status, total;
     int64_t wn, rows, ldF, ldC;
     size_t part_half;
     bool narrow, per_comp;
@@ -226,6 +237,7 @@ ReqLayout layout_of(const abm_problem& p, int L, int kchunk, int max_split)
                                          : far_split_bound(kfar_max, kchunk, max_split));
     r.part_half = (size_t)nsp * r.ldF * 2 * L;
     r.part = take(2 * r.part_half * sizeof(double));
+    r.status = take(sizeof(uint32_t));
     r.total = o;
     return r;
 }
@@ -336,10 +348,11 @@ abm_status admit(ServeState* S, Request* r, size_t off, const ReqLayout& lay)
     g.nsplit_cap = (int)(lay.part_half / ((size_t)lay.ldF * 2 * S->L));
     g.part[0] = (double*)(base + lay.part);
     g.part[1] = g.part[0] + lay.part_half;
+    g.status = (uint32_t*)(base + lay.status);
     r->m = 0;
     r->nblocks = (p.N + S->L - 1) / S->L;
 
-    hipError_t e = hipSuccess;
+    hipError_t e = launch_fill_u32(g.status, 0, 1, S->s0);
     for (int t = 0; t < lay.ntab && e == hipSuccess; ++t) {
         WeightTable& W = r->W[t];
         e = launch_weights(W.alpha, lay.wn, W.gam, W.b, W.a, W.c, S->s0);
@@ -349,8 +362,8 @@ abm_status admit(ServeState* S, Request* r, size_t off, const ReqLayout& lay)
     if (e != hipSuccess) return hip_fail(e, "request weights");
     // descriptor and group slot through pinned staging (the slot's staging
     // entry is only rewritten when the slot is reused, long after this copy)
-    if ((e = hipHostMalloc((void**)&r->final_host, 4 * sizeof(double) + sizeof(TrajDesc),
-                           hipHostMallocDefault)) != hipSuccess)
+    if ((e = hipHostMalloc((void**)&r->final_host, kFinalHostBytes, hipHostMallocDefault)) !=
+        hipSuccess)
         return hip_fail(e, "pinned staging");
     const WeightTable* Wc[4];
     for (int c = 0; c < 4; ++c) Wc[c] = &r->W[lay.tab_of[c]];
@@ -382,7 +395,7 @@ abm_status admit(ServeState* S, Request* r, size_t off, const ReqLayout& lay)
 void release(ServeState* S, Request* r)
 {
     arena_free(S, r->off, r->bytes);
-    S->free_slots.push_back(r->slot);
+    if (r->slot >= 0) S->free_slots.push_back(r->slot);
     if (r->done_ev) (void)hipEventDestroy(r->done_ev);
     if (r->final_host) (void)hipHostFree(r->final_host);
     r->done_ev = nullptr;
@@ -531,7 +544,9 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
         if (r->m >= r->nblocks) {
             const int64_t nout = n_out(r->prob.N, r->prob.out_stride);
             if ((e = hipMemcpyAsync(r->final_host, r->y_out + (nout - 1) * r->prob.d,
-                                    r->prob.d * sizeof(double), hipMemcpyDeviceToHost, sc)))
+                                    r->prob.d * sizeof(double), hipMemcpyDeviceToHost, sc)) ||
+                (e = hipMemcpyAsync(final_status(r), r->g.status, sizeof(uint32_t),
+                                    hipMemcpyDeviceToHost, sc)))
                 return hip_fail(e, "result copy");
             if ((e = hipEventRecord(r->done_ev, sc)) != hipSuccess) return hip_fail(e, "event");
             r->finishing = true;
@@ -543,16 +558,30 @@ abm_status enqueue_tick(ServeState* S, const std::vector<Request*>& fresh)
     return ABM_OK;
 }
 
+// Fail every queued and running request (the server stops after a device
+// error).  Called with S->mu held.  The requests stay owned by S->all until
+// polled; pending and active are emptied so that nothing else refers to them.
+void fail_all(ServeState* S)
+{
+    const double t = now_s();
+    for (auto& kv : S->all) {
+        Request* r = kv.second;
+        if (r->state == kDone) continue;
+        r->state = kDone;
+        r->status = ABM_EDEVICE;
+        r->t_done = t;
+    }
+    S->pending.clear();
+    S->active.clear();
+    S->stop = true;
+}
+
 void server_loop(ServeState* S)
 {
     if (server_init(S) != ABM_OK) {
         std::lock_guard<std::mutex> lk(S->mu);
         S->error = abm_last_error();
-        for (auto& kv : S->all) {
-            kv.second->state = kDone;
-            kv.second->status = ABM_EDEVICE;
-        }
-        S->stop = true;
+        fail_all(S);
         return;
     }
     for (;;) {
@@ -586,7 +615,10 @@ void server_loop(ServeState* S)
                 if (!arena_alloc(S, lay.total, &off)) break;   // head waits for memory
                 S->pending.pop_front();
                 if (admit(S, r, off, lay) != ABM_OK) {
-                    arena_free(S, off, lay.total);
+                    // whatever admission enqueued has run before its memory,
+                    // slot, event and staging are given back
+                    (void)hipStreamSynchronize(S->s0);
+                    release(S, r);
                     r->state = kDone;
                     r->status = ABM_EDEVICE;
                     r->t_done = now_s();
@@ -604,12 +636,7 @@ void server_loop(ServeState* S)
         if (any_work && enqueue_tick(S, fresh) != ABM_OK) {
             std::lock_guard<std::mutex> lk(S->mu);
             S->error = abm_last_error();
-            for (Request* r : S->active) {
-                r->state = kDone;
-                r->status = ABM_EDEVICE;
-            }
-            S->active.clear();
-            S->stop = true;
+            fail_all(S);
             break;
         }
         // completions
@@ -618,7 +645,9 @@ void server_loop(ServeState* S)
             if (r->finishing && hipEventQuery(r->done_ev) == hipSuccess) {
                 const double t = now_s();
                 double mx = 0;
-                bool bad = false;
+                // the chains raised the request's own status word if any of
+                // its states became non-finite
+                bool bad = !r->cancel_seen && *final_status(r) != 0;
                 for (int i = 0; i < r->prob.d && !r->cancel_seen; ++i) {
                     bad |= !std::isfinite(r->final_host[i]);
                     mx = std::max(mx, std::fabs(r->final_host[i]));
@@ -643,6 +672,15 @@ void server_loop(ServeState* S)
 
 }  // namespace
 
+abm_status serve_create(abm_ctx* ctx)
+{
+    ServeState* S = new (std::nothrow) ServeState();
+    if (!S) return fail(ABM_ENOMEM, "server state");
+    S->ctx = ctx;
+    ctx->serve = S;
+    return ABM_OK;
+}
+
 void serve_shutdown(abm_ctx* ctx)
 {
     ServeState* S = ctx->serve;
@@ -656,13 +694,16 @@ void serve_shutdown(abm_ctx* ctx)
     }
     S->cv.notify_all();
     if (S->th.joinable()) S->th.join();
+    // every request not yet polled is in S->all (and only there once the
+    // thread has ended: pending and active hold a subset of it)
+    S->pending.clear();
+    S->active.clear();
     for (auto& kv : S->all) {
         if (kv.second->final_host) (void)hipHostFree(kv.second->final_host);
         if (kv.second->done_ev) (void)hipEventDestroy(kv.second->done_ev);
         delete kv.second;
     }
-    for (Request* r : S->pending)
-        if (S->all.find(r->ticket) == S->all.end()) delete r;
+    S->all.clear();
     if (S->arena) (void)hipFree(S->arena);
     dev_free(S->groups_dev);
     dev_free(S->stage_dev);
@@ -690,11 +731,7 @@ abm_status abm_submit(abm_ctx* ctx, const abm_problem* prob, double* y_out, uint
     if (!ctx || !prob || !y_out || !ticket) return fail(ABM_EINVAL, "NULL argument");
     abm_status s = validate(*prob, 0);
     if (s) return s;
-    if (!ctx->serve) {
-        ctx->serve = new ServeState();
-        ctx->serve->ctx = ctx;
-    }
-    ServeState* S = ctx->serve;
+    ServeState* S = ctx->serve;   // made with the context, fixed until it is destroyed
     int L = 0, kchunk = 0;
     if ((s = serve_params(&L, &kchunk))) return s;
     const ReqLayout lay = layout_of(*prob, L, kchunk, S->max_split);
@@ -731,7 +768,7 @@ abm_status abm_request_bytes(abm_ctx* ctx, const abm_problem* prob, size_t* byte
     if (s) return s;
     int L = 0, kchunk = 0;
     if ((s = serve_params(&L, &kchunk))) return s;
-    *bytes = layout_of(*prob, L, kchunk, ctx->serve ? ctx->serve->max_split : serve_max_split()).total;
+    *bytes = layout_of(*prob, L, kchunk, ctx->serve->max_split).total;
     return ABM_OK;
 }
 
@@ -739,7 +776,6 @@ abm_status abm_poll(abm_ctx* ctx, uint64_t ticket, abm_result* res)
 {
     if (!ctx || !res) return fail(ABM_EINVAL, "NULL argument");
     ServeState* S = ctx->serve;
-    if (!S) return fail(ABM_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->all.find(ticket);
     if (it == S->all.end()) return fail(ABM_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
@@ -759,7 +795,6 @@ abm_status abm_cancel(abm_ctx* ctx, uint64_t ticket)
 {
     if (!ctx) return fail(ABM_EINVAL, "NULL argument");
     ServeState* S = ctx->serve;
-    if (!S) return fail(ABM_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
     std::lock_guard<std::mutex> lk(S->mu);
     auto it = S->all.find(ticket);
     if (it == S->all.end()) return fail(ABM_ENOENT, "unknown ticket %llu", (unsigned long long)ticket);
