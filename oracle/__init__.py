@@ -61,7 +61,7 @@ def _load():
     lib.oracle_steps_from_states_gen.argtypes = [ctypes.c_int, ctypes.c_int, c_dp,
                                                  ctypes.c_double, c_dp, c_dp, c_dp, c_dp,
                                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
-                                                 c_dp, c_dp]
+                                                 c_dp, c_dp, ctypes.c_int]
     lib.oracle_steps_from_states_gen.restype = ctypes.c_int
     lib.oracle_solve_batch_gen.argtypes = [ctypes.c_int32, ctypes.POINTER(ctypes.c_int32),
                                            ctypes.POINTER(ctypes.c_int32), c_dp, c_dp,
@@ -69,6 +69,17 @@ def _load():
                                            ctypes.c_int64, ctypes.POINTER(c_dp),
                                            ctypes.POINTER(ctypes.c_int32), ctypes.c_int]
     lib.oracle_solve_batch_gen.restype = ctypes.c_int
+    lib.oracle_solve_quad.argtypes = [ctypes.c_int, ctypes.c_int, c_dp, ctypes.c_double,
+                                      ctypes.c_int64, c_dp, c_dp, c_dp, ctypes.c_int64, c_dp]
+    lib.oracle_solve_quad.restype = ctypes.c_int
+    lib.oracle_steps_from_states_quad.argtypes = [ctypes.c_int, ctypes.c_int, c_dp,
+                                                  ctypes.c_double, c_dp, c_dp, c_dp, c_dp,
+                                                  ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                                  c_dp]
+    lib.oracle_steps_from_states_quad.restype = ctypes.c_int
+    lib.oracle_weights_quad.argtypes = [ctypes.c_double, ctypes.c_int64, ctypes.c_int64, c_dp,
+                                        c_dp, c_dp]
+    lib.oracle_weights_quad.restype = ctypes.c_int
     lib.oracle_history_sum.argtypes = [c_dp, c_dp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int]
     lib.oracle_history_sum.restype = ctypes.c_double
     lib.oracle_num_threads.argtypes = []
@@ -150,11 +161,12 @@ def solve(rhs: int, alpha, h: float, N: int, x0, p, out_stride: int = 1,
 
 
 def steps_from_states(rhs: int, alpha, h: float, x0, p, y_hist: np.ndarray,
-                      s_list, x1=None, return_scale: bool = False):
+                      s_list, x1=None, return_scale: bool = False, compensated: bool = False):
     """y_s recomputed for each s in s_list from the given states y_0..y_{s-1}.
     With return_scale, also the size of each step's history terms per
     component, h^alpha (sum |b_{n-k} F_k| + |c_n F_0| + sum |a_{n-k} F_k|):
-    rounding inside the sums moves y_s by a small multiple of eps times it."""
+    rounding inside the sums moves y_s by a small multiple of eps times it.
+    compensated: Neumaier-compensated history sums (nearly free of rounding)."""
     lib = _load()
     d = RHS_DIM[rhs]
     x, pp = _params(rhs, d, x0, p)
@@ -169,7 +181,8 @@ def steps_from_states(rhs: int, alpha, h: float, x0, p, y_hist: np.ndarray,
                                           _dp(yh),
                                           s_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
                                           int(s_arr.size), _dp(out),
-                                          _dp(scale) if return_scale else None)
+                                          _dp(scale) if return_scale else None,
+                                          1 if compensated else 0)
     if rc != 0:
         raise ValueError("oracle_steps_from_states failed: %d" % rc)
     return (out, scale) if return_scale else out
@@ -205,6 +218,55 @@ def solve_batch(rhs, alpha, h, N, x0, p, out_stride: int = 0, compensated: bool 
     if rc != 0:
         raise ValueError("oracle_solve_batch failed: %s" % st)
     return outs
+
+
+def solve_quad(rhs: int, alpha, h: float, N: int, x0, p, out_stride: int = 1,
+               x1=None) -> np.ndarray:
+    """One trajectory of the scheme in __float128 (weights, Gamma, h^alpha,
+    right-hand side, sums and state); returns (n_out, d, 2): the (hi, lo)
+    double pair of every component of every written state."""
+    lib = _load()
+    d = RHS_DIM[rhs]
+    x, pp = _params(rhs, d, x0, p)
+    al, v = _orders(alpha, d, x1)
+    y = np.zeros((n_out(N, out_stride), d, 2), np.float64)
+    rc = lib.oracle_solve_quad(rhs, d, _dp(al), float(h), int(N), _dp(x), _dp(v), _dp(pp),
+                               int(out_stride), _dp(y))
+    if rc != 0:
+        raise ValueError("oracle_solve_quad failed: %d" % rc)
+    return y
+
+
+def steps_from_states_quad(rhs: int, alpha, h: float, x0, p, y_hist: np.ndarray, s_list,
+                           x1=None) -> np.ndarray:
+    """Quad y_s for each s in s_list from the given states y_0..y_{s-1}, each
+    a (hi, lo) pair: y_hist of shape (>= max s, d, 2); returns (len, d, 2)."""
+    lib = _load()
+    d = RHS_DIM[rhs]
+    x, pp = _params(rhs, d, x0, p)
+    al, v = _orders(alpha, d, x1)
+    s_arr = np.ascontiguousarray(np.asarray(s_list, np.int64))
+    yh = np.ascontiguousarray(np.asarray(y_hist, np.float64).reshape(-1, d, 2))
+    if s_arr.size and (s_arr.min() < 1 or s_arr.max() > yh.shape[0]):
+        raise ValueError("s out of range of the given history")
+    out = np.zeros((s_arr.size, d, 2), np.float64)
+    rc = lib.oracle_steps_from_states_quad(rhs, d, _dp(al), float(h), _dp(x), _dp(v), _dp(pp),
+                                           _dp(yh),
+                                           s_arr.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                                           int(s_arr.size), _dp(out))
+    if rc != 0:
+        raise ValueError("oracle_steps_from_states_quad failed: %d" % rc)
+    return out
+
+
+def weights_quad(alpha: float, n: int, k0: int = 0):
+    """Quad b_k, a_k, c_k for k = k0..k0+n-1 as (n, 2) arrays of (hi, lo)."""
+    lib = _load()
+    out = [np.zeros((n, 2), np.float64) for _ in range(3)]
+    rc = lib.oracle_weights_quad(float(alpha), int(k0), int(n), *[_dp(o) for o in out])
+    if rc != 0:
+        raise ValueError("oracle_weights_quad failed: %d" % rc)
+    return tuple(out)
 
 
 def history_sum(w, F, k_lo: int, n: int, compensated: bool) -> float:

@@ -36,7 +36,8 @@
  * differences of powers costs nothing visible, then rounded once to double.
  * Gamma(alpha+1), Gamma(alpha+2) and h^alpha are taken in double (tgamma,
  * pow).  History sums run in double, ascending k, plain or (optionally)
- * Neumaier-compensated.
+ * Neumaier-compensated.  A second form (oracle_solve_quad) runs the whole
+ * scheme in __float128: the oracle of the library's double-double mode.
  *
  * Right-hand sides (a fixed set, numbered here on their own):
  *   0 LINEAR   f = -lambda * y                          p = {lambda}
@@ -341,11 +342,14 @@ static double hist_abs_sum(const double *w, const double *F, int d, int comp_idx
  * scale_out (may be NULL) receives, per listed step and component, the size
  * of the history terms entering y_s:
  *   h^alpha * ( sum_{k=0..n} |b_{n-k} F_k| + |c_n F_0| + sum_{k=1..n} |a_{n-k} F_k| ).
+ * comp != 0 takes the two history sums Neumaier-compensated, so that the
+ * recomputed step carries almost none of the rounding a plain sum of n terms
+ * accumulates.
  */
 int oracle_steps_from_states_gen(int rhs, int d, const double *alphas, double h,
                                  const double *x0, const double *x1, const double *p,
                                  const double *y_hist, const int64_t *s_list, int32_t ns,
-                                 double *y_out, double *scale_out)
+                                 double *y_out, double *scale_out, int comp)
 {
     if (rhs_dim(rhs) != d || !alphas || !orders_ok(d, alphas) || !(h > 0.0) || ns < 0)
         return ORC_EINVAL;
@@ -381,10 +385,10 @@ int oracle_steps_from_states_gen(int rhs, int d, const double *alphas, double h,
         const double t = (double)s * h;
         for (int i = 0; i < d; ++i)
             yp[i] = start_term(alphas[i], x0[i], x1, i, t) +
-                    T[i].ha * hist_sum(T[i].b, F, d, i, 0, n, 0);
+                    T[i].ha * hist_sum(T[i].b, F, d, i, 0, n, comp);
         rhs_eval(rhs, p, t, yp, fp);
         for (int i = 0; i < d; ++i) {
-            double hs = hist_sum(T[i].a, F, d, i, 1, n, 0);
+            double hs = hist_sum(T[i].a, F, d, i, 1, n, comp);
             y_out[j * d + i] = start_term(alphas[i], x0[i], x1, i, t) +
                                T[i].ha * ((T[i].c[n] * F[i] + hs) + fp[i] / T[i].g2);
             if (scale_out)
@@ -408,7 +412,278 @@ int oracle_steps_from_states(int rhs, int d, double alpha, double h, const doubl
     for (int i = 0; i < d; ++i)
         al[i] = alpha;
     return oracle_steps_from_states_gen(rhs, d, al, h, x0, NULL, p, y_hist, s_list, ns, y_out,
-                                        NULL);
+                                        NULL, 0);
+}
+
+/* ---------------------------------------------------------------------
+ * The scheme in quad precision: the oracle of the library's double-double
+ * mode, the counterpart of the paper's long-double runs (Section "Memory
+ * saving improves computing time": the same computation with a wider type).
+ * Every quantity is __float128 (113-bit significand): the weights from their
+ * literal formulas (not rounded to double), Gamma(alpha+1), Gamma(alpha+2) by
+ * tgammaq, h^alpha by powq, t_s = s h (exact: s and h are integers and
+ * doubles), the right-hand side with cosq / sinq, the history sums (plain
+ * ascending) and the state.  Inputs are the same doubles as for the double
+ * oracle; each written state leaves as d pairs (hi, lo) of doubles with
+ * hi = (double)y and lo = (double)(y - hi).
+ * --------------------------------------------------------------------- */
+
+typedef __float128 quad;
+
+static void rhs_eval_q(int rhs, const double *pd, quad t, const quad *y, quad *f)
+{
+    quad p[8];
+    for (int i = 0; i < 8; ++i)
+        p[i] = (quad)pd[i];
+    switch (rhs) {
+    case 0:
+        f[0] = -p[0] * y[0];
+        break;
+    case 1:
+        f[0] = y[1];
+        f[1] = -p[0] * y[1] - y[0] - y[0] * y[0] * y[0] + p[1] * cosq(p[2] * t);
+        break;
+    case 2:
+        f[0] = p[0] * (y[1] - y[0]);
+        f[1] = y[0] * (p[1] - y[2]) - y[1];
+        f[2] = y[0] * y[1] - p[2] * y[2];
+        break;
+    case 3:
+        f[0] = p[0] + p[1] * t;
+        break;
+    case 4: {
+        quad x = y[0], g;
+        if (x <= -1)
+            g = p[3] * x - p[2] + p[3];
+        else if (x >= 1)
+            g = p[3] * x + p[2] - p[3];
+        else
+            g = p[2] * x;
+        f[0] = y[1] - g;
+        f[1] = -p[0] * y[1] - y[0] + p[4] * sinq(p[1] * t);
+        break;
+    }
+    case 5:
+        f[0] = -p[0] * y[0] + p[2];
+        f[1] = -p[1] * y[1] + p[3];
+        break;
+    }
+}
+
+/* Quad weights b_k, a_k, c_k for k = 0..n-1 of order alpha, literal formulas
+ * with quad Gamma factors. */
+static void weights_q(double alpha, int64_t n, quad *b, quad *a, quad *c)
+{
+    const quad al = (quad)alpha;
+    const quad g1 = tgammaq(al + 1), g2 = tgammaq(al + 2);
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < n; ++k) {
+        const quad kq = (quad)k;
+        const quad pk0 = (k == 0) ? 0 : powq(kq, al);
+        const quad pk1 = powq(kq + 1, al);
+        const quad qk0 = (k == 0) ? 0 : powq(kq, al + 1);
+        const quad qk1 = powq(kq + 1, al + 1);
+        const quad qk2 = powq(kq + 2, al + 1);
+        b[k] = (pk1 - pk0) / g1;
+        a[k] = (qk2 - 2 * qk1 + qk0) / g2;
+        c[k] = (qk0 - (kq - al) * pk1) / g2;
+    }
+}
+
+struct comp_tables_q {
+    quad *b, *a, *c;
+    quad ha, g2;
+};
+
+static void free_tables_q(struct comp_tables_q *T, int d)
+{
+    for (int i = 0; i < d; ++i) {
+        free(T[i].b);
+        free(T[i].a);
+        free(T[i].c);
+        T[i].b = T[i].a = T[i].c = NULL;
+    }
+}
+
+static int make_tables_q(struct comp_tables_q *T, int d, const double *alphas, double h,
+                         int64_t n)
+{
+    for (int i = 0; i < d; ++i)
+        T[i].b = T[i].a = T[i].c = NULL;
+    for (int i = 0; i < d; ++i) {
+        const size_t bytes = sizeof(quad) * (size_t)(n > 0 ? n : 1);
+        T[i].b = malloc(bytes);
+        T[i].a = malloc(bytes);
+        T[i].c = malloc(bytes);
+        if (!T[i].b || !T[i].a || !T[i].c) {
+            free_tables_q(T, d);
+            return ORC_ENOMEM;
+        }
+        weights_q(alphas[i], n, T[i].b, T[i].a, T[i].c);
+        T[i].ha = powq((quad)h, (quad)alphas[i]);
+        T[i].g2 = tgammaq((quad)alphas[i] + 2);
+    }
+    return ORC_OK;
+}
+
+static quad hist_sum_q(const quad *w, const quad *F, int d, int comp_idx, int64_t k_lo, int64_t n)
+{
+    quad s = 0;
+    for (int64_t k = k_lo; k <= n; ++k)
+        s += w[n - k] * F[k * d + comp_idx];
+    return s;
+}
+
+static quad start_term_q(double alpha, double x0, const double *x1, int i, quad t)
+{
+    return alpha > 1.0 ? (quad)x0 + t * (quad)x1[i] : (quad)x0;
+}
+
+static void put_pair(double *dst, quad v)
+{
+    const double hi = (double)v;
+    dst[0] = hi;
+    dst[1] = (double)(v - (quad)hi);
+}
+
+/* Quad weights of order alpha for k = k0..k0+n-1, as (hi, lo) pairs. */
+int oracle_weights_quad(double alpha, int64_t k0, int64_t n, double *b, double *a, double *c)
+{
+    if (!order_ok(alpha) || n < 0 || k0 < 0)
+        return ORC_EINVAL;
+    quad *w = malloc(sizeof(quad) * 3 * (size_t)(k0 + n > 0 ? k0 + n : 1));
+    if (!w)
+        return ORC_ENOMEM;
+    quad *wb = w, *wa = w + (k0 + n), *wc = w + 2 * (k0 + n);
+    weights_q(alpha, k0 + n, wb, wa, wc);
+    for (int64_t i = 0; i < n; ++i) {
+        if (b) put_pair(b + 2 * i, wb[k0 + i]);
+        if (a) put_pair(a + 2 * i, wa[k0 + i]);
+        if (c) put_pair(c + 2 * i, wc[k0 + i]);
+    }
+    free(w);
+    return ORC_OK;
+}
+
+/*
+ * One trajectory of the scheme in quad precision (arguments as for
+ * oracle_solve_gen; no compensated variant).  y_out: 2d doubles per written
+ * state, the (hi, lo) pair of each component.
+ */
+int oracle_solve_quad(int rhs, int d, const double *alphas, double h, int64_t N,
+                      const double *x0, const double *x1, const double *p, int64_t out_stride,
+                      double *y_out)
+{
+    if (rhs_dim(rhs) != d || !alphas || !orders_ok(d, alphas) || !(h > 0.0) ||
+        !isfinite(h) || N < 1 || out_stride < 0 || !x0 || !p || !y_out)
+        return ORC_EINVAL;
+    for (int i = 0; i < d; ++i)
+        if (alphas[i] > 1.0 && !x1)
+            return ORC_EINVAL;
+    struct comp_tables_q T[8];
+    quad *F = malloc(sizeof(quad) * (size_t)(N + 1) * (size_t)d);
+    if (!F)
+        return ORC_ENOMEM;
+    int rc = make_tables_q(T, d, alphas, h, N);
+    if (rc != ORC_OK) {
+        free(F);
+        return rc;
+    }
+    quad y0[8], y[8], yp[8], fp[8];
+    for (int i = 0; i < d; ++i)
+        y0[i] = y[i] = (quad)x0[i];
+    rhs_eval_q(rhs, p, 0, y0, F);
+    int64_t w = 0;
+    if (out_stride > 0) {
+        for (int i = 0; i < d; ++i)
+            put_pair(y_out + 2 * i, y0[i]);
+        w = 1;
+    }
+    for (int64_t s = 1; s <= N; ++s) {
+        const int64_t n = s - 1;
+        const quad t = (quad)s * (quad)h;
+        for (int i = 0; i < d; ++i)
+            yp[i] = start_term_q(alphas[i], x0[i], x1, i, t) +
+                    T[i].ha * hist_sum_q(T[i].b, F, d, i, 0, n);
+        rhs_eval_q(rhs, p, t, yp, fp);
+        for (int i = 0; i < d; ++i) {
+            const quad C = T[i].c[n] * F[i] + hist_sum_q(T[i].a, F, d, i, 1, n);
+            y[i] = start_term_q(alphas[i], x0[i], x1, i, t) + T[i].ha * (C + fp[i] / T[i].g2);
+        }
+        rhs_eval_q(rhs, p, t, y, F + s * d);
+        if (out_stride > 0 && (s % out_stride == 0 || s == N)) {
+            for (int i = 0; i < d; ++i)
+                put_pair(y_out + 2 * (w * d + i), y[i]);
+            ++w;
+        }
+    }
+    if (out_stride == 0)
+        for (int i = 0; i < d; ++i)
+            put_pair(y_out + 2 * i, y[i]);
+    free_tables_q(T, d);
+    free(F);
+    return ORC_OK;
+}
+
+/*
+ * Single quad steps from a given state history: y_hist holds y_0..y_{smax-1}
+ * as (hi, lo) pairs (2d doubles per state, the value hi + lo); for every s in
+ * s_list one predictor-corrector step in quad from f_k = f(t_k, y_k), k < s,
+ * written to y_out as (hi, lo) pairs.
+ */
+int oracle_steps_from_states_quad(int rhs, int d, const double *alphas, double h,
+                                  const double *x0, const double *x1, const double *p,
+                                  const double *y_hist, const int64_t *s_list, int32_t ns,
+                                  double *y_out)
+{
+    if (rhs_dim(rhs) != d || !alphas || !orders_ok(d, alphas) || !(h > 0.0) || ns < 0)
+        return ORC_EINVAL;
+    for (int i = 0; i < d; ++i)
+        if (alphas[i] > 1.0 && !x1)
+            return ORC_EINVAL;
+    int64_t smax = 0;
+    for (int32_t i = 0; i < ns; ++i) {
+        if (s_list[i] < 1)
+            return ORC_EINVAL;
+        if (s_list[i] > smax)
+            smax = s_list[i];
+    }
+    if (smax == 0)
+        return ORC_OK;
+    struct comp_tables_q T[8];
+    quad *F = malloc(sizeof(quad) * (size_t)smax * (size_t)d);
+    if (!F)
+        return ORC_ENOMEM;
+    int rc = make_tables_q(T, d, alphas, h, smax);
+    if (rc != ORC_OK) {
+        free(F);
+        return rc;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t k = 0; k < smax; ++k) {
+        quad yk[8];
+        for (int i = 0; i < d; ++i)
+            yk[i] = (quad)y_hist[2 * (k * d + i)] + (quad)y_hist[2 * (k * d + i) + 1];
+        rhs_eval_q(rhs, p, (quad)k * (quad)h, yk, F + k * d);
+    }
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int32_t j = 0; j < ns; ++j) {
+        quad yp[8], fp[8];
+        const int64_t s = s_list[j], n = s - 1;
+        const quad t = (quad)s * (quad)h;
+        for (int i = 0; i < d; ++i)
+            yp[i] = start_term_q(alphas[i], x0[i], x1, i, t) +
+                    T[i].ha * hist_sum_q(T[i].b, F, d, i, 0, n);
+        rhs_eval_q(rhs, p, t, yp, fp);
+        for (int i = 0; i < d; ++i) {
+            const quad C = T[i].c[n] * F[i] + hist_sum_q(T[i].a, F, d, i, 1, n);
+            put_pair(y_out + 2 * (j * d + i),
+                     start_term_q(alphas[i], x0[i], x1, i, t) + T[i].ha * (C + fp[i] / T[i].g2));
+        }
+    }
+    free_tables_q(T, d);
+    free(F);
+    return ORC_OK;
 }
 
 /*

@@ -290,10 +290,16 @@ def _quad_rules(al, n):
 
 
 def _brute_force(name, alpha, h, N, x0, p, x1=None):
+    """_brute_force_mp rounded to double."""
+    return np.array([[float(v) for v in y] for y in _brute_force_mp(name, alpha, h, N, x0, p, x1)])
+
+
+def _brute_force_mp(name, alpha, h, N, x0, p, x1=None):
     """50-digit ABM for tiny N with weights from quadrature of the
     product-integration rules (no closed-form weight is used).  alpha is one
     order or one per component; components of order above 1 start from
-    x0 + t x1 (the Taylor sum over the ceil(alpha) initial values)."""
+    x0 + t x1 (the Taylor sum over the ceil(alpha) initial values).  Returns
+    the states as lists of 50-digit values."""
     d = len(x0)
     alphas = list(alpha) if np.ndim(alpha) else [alpha] * d
     with mp.workdps(50):
@@ -321,7 +327,7 @@ def _brute_force(name, alpha, h, N, x0, p, x1=None):
                                           + cw[n + 1] * fP[i]))
             ys.append(y1)
             F.append(fn(t1, y1))
-        return np.array([[float(v) for v in y] for y in ys])
+        return ys
 
 
 @pytest.mark.parametrize("name,alpha,h,x0,p", [
@@ -473,6 +479,12 @@ def test_steps_from_states_reproduce_a_run():
     s_list = [1, 2, 63, 64, 65, 699, 700]
     ys = O.steps_from_states(pr["rhs"], pr["alpha"], pr["h"], pr["x0"], pr["p"], y, s_list)
     assert np.array_equal(ys, y[s_list])
+    # the compensated recompute reproduces the compensated run
+    yc = O.solve(pr["rhs"], pr["alpha"], pr["h"], N, pr["x0"], pr["p"], out_stride=1,
+                 compensated=True)
+    ys = O.steps_from_states(pr["rhs"], pr["alpha"], pr["h"], pr["x0"], pr["p"], yc, s_list,
+                             compensated=True)
+    assert np.array_equal(ys, yc[s_list])
 
 
 def test_rounding_noise_floor_is_far_below_parity_tolerance():
@@ -585,3 +597,103 @@ def test_step_recompute_term_size_closed_form(alpha):
         t = s * h
         ref = 2 * c0 * t ** alpha / math.gamma(alpha + 1) - h ** alpha * c0 / math.gamma(alpha + 2)
         assert abs(scale[j, 0] - ref) <= 1e-13 * ref, (s, scale[j, 0], ref)
+
+
+
+# ------------------------------------------------- the scheme in quad precision
+# oracle_solve_quad runs every quantity in __float128 (the oracle of the
+# double-double mode); its pins are the double oracle's, at quad tolerances.
+def _pairs_mp(y):
+    """(hi, lo) pairs as 50-digit values."""
+    with mp.workdps(50):
+        return [[mp.mpf(float(c[0])) + mp.mpf(float(c[1])) for c in st] for st in y]
+
+
+def _max_rel_mp(a, b):
+    with mp.workdps(50):
+        scale = max(max(abs(v) for v in st) for st in b)
+        return float(max(abs(x - y) for sa, sb in zip(a, b) for x, y in zip(sa, sb)) / max(scale, 1))
+
+
+@pytest.mark.parametrize("name,alpha,h,x0,p,x1", [
+    ("LINEAR", 0.7, 0.125, [1.0], [1.3], None),
+    ("DUFFING", 0.9, 0.05, [0.1, 0.0], [0.1, 0.3, 1.2], None),
+    ("LORENZ", 0.95, 0.01, [1.0, 1.0, 1.0], [10.0, 28.0, 8.0 / 3.0], None),
+    ("LCR", 0.9, 0.25, [1.2, -0.4], [1.015, 0.55, -1.02, -0.58, 0.117], None),
+    ("LCR", (0.9, 0.8), 0.25, [1.2, -0.4], [1.015, 0.55, -1.02, -0.58, 0.117], None),
+    ("LINEAR", 1.5, 0.125, [1.0], [1.3], [0.5]),
+])
+def test_quad_tiny_n_brute_force(name, alpha, h, x0, p, x1):
+    """The quad scheme against the 50-digit brute force with quadrature
+    weights, to 1e-30 (quad rounding is ~1e-34 per operation; a double-rounded
+    weight, Gamma factor, h^alpha or cos/sin would show at 1e-16)."""
+    N = 10
+    y = O.solve_quad(_RID[name], alpha, h, N, x0, p, out_stride=1, x1=x1)
+    ref = _brute_force_mp(name, alpha, h, N, x0, p, x1)
+    assert _max_rel_mp(_pairs_mp(y), ref) <= 1e-30
+
+
+@pytest.mark.parametrize("alpha", [0.35, 0.8, 1.0])
+def test_quad_linear_in_t_forcing_is_exact(alpha):
+    """f = c0 + c1 t is integrated exactly by the product-trapezoid corrector,
+    so y_s = x0 + c0 t^a / Gamma(a+1) + c1 t^(a+1) / Gamma(a+2) to quad
+    rounding over 400 steps."""
+    c0, c1, h, N, x0 = 0.7, -0.3, 1.0 / 64, 400, 0.25
+    y = O.solve_quad(O.RHS_POLY, alpha, h, N, [x0], [c0, c1], out_stride=1)
+    got = _pairs_mp(y)
+    with mp.workdps(50):
+        a = mp.mpf(alpha)
+        ref = [[mp.mpf(x0) + mp.mpf(c0) * (s * mp.mpf(h)) ** a / mp.gamma(a + 1)
+                + mp.mpf(c1) * (s * mp.mpf(h)) ** (a + 1) / mp.gamma(a + 2)] for s in range(N + 1)]
+    assert _max_rel_mp(got, ref) <= 1e-30
+
+
+@pytest.mark.parametrize("alpha", [0.3, 0.95, 1.5])
+@pytest.mark.parametrize("k0", [0, 1000, 262144])
+def test_quad_weights_50_digits(alpha, k0):
+    """Quad weights against 50-digit evaluations of the same formulas: the
+    literal differences of powers lose about log10(k) digits for b (its two
+    powers agree to ~1/k) and 2 log10(k) for a and c (their leading k^(a+1)
+    terms cancel down to ~k^(a-1)); with libquadmath's powq / tgammaq good to
+    a few quad ulp, the bounds are 2e-32 (k+2) relative for b and
+    2e-32 (k+2)^2 for a and c (about 1e-21 at k = 262144)."""
+    n = 6
+    b, a, c = O.weights_quad(alpha, n, k0=k0)
+    with mp.workdps(50):
+        al = mp.mpf(alpha)
+        g1, g2 = mp.gamma(al + 1), mp.gamma(al + 2)
+        for i in range(n):
+            k = mp.mpf(k0 + i)
+            rb = ((k + 1) ** al - (k ** al if k0 + i else 0)) / g1
+            ra = ((k + 2) ** (al + 1) - 2 * (k + 1) ** (al + 1) + (k ** (al + 1) if k0 + i else 0)) / g2
+            rc = ((k ** (al + 1) if k0 + i else 0) - (k - al) * (k + 1) ** al) / g2
+            kk = float(k0 + i + 2)
+            for got, ref, tol in ((b[i], rb, 2e-32 * kk), (a[i], ra, 2e-32 * kk * kk),
+                                  (c[i], rc, 2e-32 * kk * kk)):
+                v = mp.mpf(float(got[0])) + mp.mpf(float(got[1]))
+                assert abs(v - ref) <= tol * abs(ref), (k0 + i, float(abs(v - ref) / abs(ref)))
+
+
+def test_quad_steps_from_states_reproduce_a_run():
+    pr = dict(rhs=O.RHS_LCR, alpha=(0.9, 0.8), h=0.05, x0=[1.2, -0.4],
+              p=[1.015, 0.55, -1.02, -0.58, 0.117])
+    N = 600
+    y = O.solve_quad(pr["rhs"], pr["alpha"], pr["h"], N, pr["x0"], pr["p"], out_stride=1)
+    s_list = [1, 2, 63, 64, 65, 599, 600]
+    ys = O.steps_from_states_quad(pr["rhs"], pr["alpha"], pr["h"], pr["x0"], pr["p"], y, s_list)
+    # the history enters as (hi, lo) pairs, 106 of its 113 bits
+    assert _max_rel_mp(_pairs_mp(ys), _pairs_mp(y[s_list])) <= 1e-30
+
+
+@pytest.mark.parametrize("rhs,alpha,h,N,x0,p", [
+    (O.RHS_DUFFING, 0.95, 2.0 ** -8, 3000, [0.1, 0.0], [0.1, 0.45, 1.2]),
+    (O.RHS_LORENZ, 0.93, 2.0 ** -8, 1500, [1.0, 1.0, 1.0], [10.0, 28.0, 8.0 / 3.0]),
+    (O.RHS_LCR, (0.9, 0.8), 0.01, 2000, [1.2, -0.4], [1.015, 0.55, -1.02, -0.58, 0.117]),
+])
+def test_quad_and_double_schemes_agree(rhs, alpha, h, N, x0, p):
+    """The quad and double schemes differ only by rounding (the double
+    oracle's is ~1e-15 here): a wrong right-hand side or weight in either
+    would differ at order one."""
+    yq = O.solve_quad(rhs, alpha, h, N, x0, p, out_stride=7)
+    yd = O.solve(rhs, alpha, h, N, x0, p, out_stride=7)
+    assert np.max(np.abs(yq[..., 0] + yq[..., 1] - yd)) <= 1e-13 * np.max(np.abs(yd))
