@@ -5,16 +5,23 @@
 //   * a "process" is a workgroup; there are G of them, all co-resident
 //     (cooperative launch), each owning a fixed slice of the history;
 //   * the slice is block-cyclic: chunk c = indices [256c, 256c+256) belongs to
-//     workgroup c mod G, one index per thread, kept in LDS, so every workgroup
-//     holds an equal share of the history at every step (the paper's static
-//     contiguous slices would leave most of them idle early in the run);
-//   * per step every workgroup sums b_{n-k} f_k and a_{n-k} f_k over its
-//     indices (thread -> wavefront butterfly -> LDS), publishes the 2d partial
-//     sums and raises its step flag (the all-reduce of Algorithm 1);
-//   * every workgroup waits for all G flags, adds the G partials in a fixed
-//     order and takes the predictor/corrector update itself, bit-identically
-//     (every process computes the update, as in Algorithm 1); the owner of
-//     index s keeps f_s in its LDS slice.
+//     workgroup c mod G, one index per thread of its four work waves, kept in
+//     LDS, so every workgroup holds an equal share of the history at every
+//     step (the paper's static contiguous slices would leave most of them
+//     idle early in the run);
+//   * per step every work thread sums b_{n-k} f_k and a_{n-k} f_k over its
+//     indices; the weights were loaded into registers during the previous
+//     step's synchronisation (they depend only on n - k), so no global load
+//     waits on the step's dependent path;
+//   * a fifth wave reduces the work waves' partials (DPP row operations, then
+//     LDS), publishes the workgroup's 2d sums and raises its step flag (the
+//     all-reduce of Algorithm 1), waits for all G flags, adds the G partials
+//     in a fixed order and takes the predictor/corrector update itself,
+//     bit-identically in every workgroup (every process computes the update,
+//     as in Algorithm 1); the owner of index s keeps f_s in its LDS slice.
+//     The work waves never wait on that wave's flag traffic, and it issues no
+//     weight loads, so its memory fences never wait on theirs;
+//   * with G = 1 there is nothing to publish: the step is two barriers.
 // Partial slots are double-buffered by step parity: a workgroup can only
 // overwrite slot s+2 after every workgroup has published s+1, which each does
 // after reading slot s.
@@ -25,25 +32,66 @@ namespace abm {
 
 namespace {
 
-constexpr int kCh = 256;          // history indices per chunk (= threads per workgroup)
-constexpr int kPartStride = 8;    // doubles per partial slot (2d <= 6 used)
+constexpr int kCh = 256;                  // history indices per chunk (= work threads per workgroup)
+constexpr int kWorkWaves = kCh / kWave;
+constexpr int kThreads = kCh + kWave;     // + the wave that synchronises and updates
+constexpr int kPartStride = 8;            // doubles per partial slot (2d <= 6 used)
 constexpr size_t kPlainLds = 160 * 1024 - 256;   // LDS of one gfx950 CU, less the static flag
+constexpr int kMaxPrefetch = 16;          // register-prefetched (local chunk, weight table) pairs
+
+// v moved across lanes by one DPP control (rows outside ROWS read 0).
+template <int CTRL, int ROWS>
+__device__ __forceinline__ double dpp_f64(double v)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)u, CTRL, ROWS, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(uint32_t)(u >> 32), CTRL, ROWS, 0xF, false);
+    return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
+}
+
+// Sum over the 64 lanes of a full wave by DPP row operations in a fixed order
+// (pairs, quads, half rows, rows, then the two row broadcasts that carry the
+// row sums into the last row); every lane gets lane 63's total.
+__device__ __forceinline__ double wave_sum_dpp(double v)
+{
+    v += dpp_f64<0xB1, 0xF>(v);     // quad_perm [1,0,3,2]
+    v += dpp_f64<0x4E, 0xF>(v);     // quad_perm [2,3,0,1]
+    v += dpp_f64<0x141, 0xF>(v);    // row_half_mirror
+    v += dpp_f64<0x140, 0xF>(v);    // row_mirror
+    v += dpp_f64<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
+    v += dpp_f64<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
 
 // PC: the components have orders of their own (a weight table each);
-// otherwise every component uses component 0's table.
-template <int R, int D, bool PC>
-__global__ __launch_bounds__(256) void k_plain(PlainArgs A)
+// otherwise every component uses component 0's table.  NL > 0: at most NL
+// local chunks, their weights prefetched into registers; NL = 0: any number,
+// weights loaded in the step (long histories).
+template <int R, int D, bool PC, int NL>
+__global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
 {
     extern __shared__ double sm[];
     double* Fl = sm;                                   // [nloc][256][D] history slice
-    double* red = sm + (size_t)A.nloc * kCh * D;       // [4][2D] per-wave partials
+    double* red = sm + (size_t)A.nloc * kCh * D;       // [4][2D] work-wave partials
     __shared__ int s_abort;
     constexpr int NW = PC ? D : 1;                     // weight tables in use
+    constexpr int NLR = NL > 0 ? NL : 1;
 
     const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    const int G = A.G;
+    const bool sync_wave = wid == kWorkWaves;
+    const int G = A.G, nloc = A.nloc;
     const int64_t N = A.N;
-    double ha[D], g2[D];
+    gptr<const double> bw[NW], aw[NW], cw[NW];
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        bw[w] = as_global(A.b[w]);
+        aw[w] = as_global(A.a[w]);
+        cw[w] = as_global(A.c[w]);
+    }
+    double ha[D], g2[D], x0[D], x1[D], F0[D];
     bool deriv[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -51,18 +99,13 @@ __global__ __launch_bounds__(256) void k_plain(PlainArgs A)
         ha[i] = pow(A.h, A.alpha[w]);
         g2[i] = A.gam[w][1];
         deriv[i] = A.alpha[w] > 1.0;
-    }
-
-    double x0[D], x1[D], F0[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
         x0[i] = A.x0[i];
         x1[i] = A.x1[i];
     }
     rhs_eval<R, D>(A.p, 0.0, x0, F0);
 
     if (t == 0) s_abort = 0;
-    if (g == 0 && t == 0) {
+    if (sync_wave && lane == 0 && g == 0) {
 #pragma unroll
         for (int i = 0; i < D; ++i) Fl[i] = F0[i];     // f_0: chunk 0, local chunk 0, thread 0
         if (A.out_stride > 0) {
@@ -70,132 +113,197 @@ __global__ __launch_bounds__(256) void k_plain(PlainArgs A)
             for (int i = 0; i < D; ++i) A.y_out[i] = x0[i];
         }
     }
+
+    // weights b_{n-k}, a_{n-k} of this thread's indices k for step n + 1
+    // (index clamped at 0 where k > n: those are not used)
+    double wb[NLR][NW], wa[NLR][NW];
+    auto fetch = [&](int64_t n) {
+#pragma unroll
+        for (int l = 0; l < NL; ++l) {
+            const int64_t k = (int64_t)(g + l * G) * kCh + t;
+            const int64_t idx = n - k < 0 ? 0 : n - k;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                wb[l][w] = bw[w][idx];
+                wa[l][w] = aw[w][idx];
+            }
+        }
+    };
+    double cn[NW];                                     // c_n of the coming step (sync wave)
+    if (!sync_wave) {
+        if constexpr (NL > 0) fetch(0);
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) cn[w] = cw[w][0];
+    }
     __syncthreads();
 
     for (int64_t s = 1; s <= N; ++s) {
         const int64_t n = s - 1;
-        double P[D], C[D];
+        if (!sync_wave) {
+            double P[D], C[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) P[i] = C[i] = 0.0;
-        for (int lc = 0; lc < A.nloc; ++lc) {
-            const int64_t k = (int64_t)(g + lc * G) * kCh + t;
-            if (k > n) break;               // later local chunks lie further out
-            double wb[NW], wa[NW];
+            for (int i = 0; i < D; ++i) P[i] = C[i] = 0.0;
+            if constexpr (NL > 0) {
 #pragma unroll
-            for (int w = 0; w < NW; ++w) {
-                wb[w] = A.b[w][n - k];
-                wa[w] = (k >= 1) ? A.a[w][n - k] : 0.0;   // k = 0 enters through c_n
+                for (int l = 0; l < NL; ++l) {
+                    const int64_t k = (int64_t)(g + l * G) * kCh + t;
+                    if (l < nloc && k <= n) {
+                        const double* f = Fl + ((size_t)l * kCh + t) * D;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            const double fa = k >= 1 ? f[i] : 0.0;   // k = 0 enters through c_n
+                            P[i] = fma(wb[l][PC ? i : 0], f[i], P[i]);
+                            C[i] = fma(wa[l][PC ? i : 0], fa, C[i]);
+                        }
+                    }
+                }
+                fetch(n + 1);      // in flight while the step is reduced and synchronised
+            } else {
+                for (int l = 0; l < nloc; ++l) {
+                    const int64_t k = (int64_t)(g + l * G) * kCh + t;
+                    if (k > n) break;               // later local chunks lie further out
+                    const double* f = Fl + ((size_t)l * kCh + t) * D;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        const int w = PC ? i : 0;
+                        P[i] = fma(bw[w][n - k], f[i], P[i]);
+                        C[i] = fma((k >= 1) ? aw[w][n - k] : 0.0, f[i], C[i]);
+                    }
+                }
             }
-            const double* f = Fl + ((size_t)lc * kCh + t) * D;
 #pragma unroll
             for (int i = 0; i < D; ++i) {
-                P[i] = fma(wb[PC ? i : 0], f[i], P[i]);
-                C[i] = fma(wa[PC ? i : 0], f[i], C[i]);
-            }
-        }
-        // workgroup partial: wavefront butterfly, then the 4 waves in order
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const double ps = wave_sum(P[i]);
-            const double cs = wave_sum(C[i]);
-            if (lane == 0) {
-                red[wid * 2 * D + i] = ps;
-                red[wid * 2 * D + D + i] = cs;
-            }
-        }
-        __syncthreads();
-        double* slot_base = A.part + (size_t)(s & 1) * G * kPartStride;
-        if (t == 0) {
-            double* slot = slot_base + (size_t)g * kPartStride;
-#pragma unroll
-            for (int j = 0; j < 2 * D; ++j)
-                slot[j] = ((red[j] + red[2 * D + j]) + red[4 * D + j]) + red[6 * D + j];
-            st_release(&A.flags[g], (uint32_t)s);
-        }
-        // wait until every workgroup has published step s
-        if (t < G) {
-            uint32_t spins = 0;
-            while (ld_relaxed(&A.flags[t]) < (uint32_t)s) {
-                if (++spins > A.spin_limit) {
-                    raise_status(A.status, kStatusTimeout);
-                    s_abort = 1;
-                    break;
+                const double ps = wave_sum_dpp(P[i]);
+                const double cs = wave_sum_dpp(C[i]);
+                if (lane == 0) {
+                    red[wid * 2 * D + i] = ps;
+                    red[wid * 2 * D + D + i] = cs;
                 }
-                spin_pause();
             }
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
-        __syncthreads();
-        if (s_abort) return;
-
-        if (wid == 0) {
+        __syncthreads();                           // work-wave partials are in LDS
+        if (sync_wave) {
             double tot[2 * D];
 #pragma unroll
-            for (int j = 0; j < 2 * D; ++j) {
-                double acc = 0.0;
-                for (int q = lane; q < G; q += kWave) acc += slot_base[(size_t)q * kPartStride + j];
-                tot[j] = wave_sum(acc);
-            }
-            // predictor / corrector (eq. abm and the corrector after it),
-            // from the start term x0 (+ t x1 for orders above 1)
-            const double td = (double)s * A.h;
-            double base[D], cn[D];
+            for (int j = 0; j < 2 * D; ++j)
+                tot[j] = ((red[j] + red[2 * D + j]) + red[4 * D + j]) + red[6 * D + j];
+            bool ok = true;
+            if (G > 1) {
+                double* slot_base = A.part + (size_t)(s & 1) * G * kPartStride;
+                if (lane == 0) {
+                    double* slot = slot_base + (size_t)g * kPartStride;
 #pragma unroll
-            for (int i = 0; i < D; ++i) {
-                base[i] = deriv[i] ? x0[i] + td * x1[i] : x0[i];
-                cn[i] = A.c[PC ? i : 0][n];
-            }
-            double yP[D], fP[D], y[D], fs[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) yP[i] = base[i] + ha[i] * tot[i];
-            rhs_eval<R, D>(A.p, td, yP, fP);
-#pragma unroll
-            for (int i = 0; i < D; ++i)
-                y[i] = base[i] + ha[i] * ((tot[D + i] + cn[i] * F0[i]) + fP[i] / g2[i]);
-            rhs_eval<R, D>(A.p, td, y, fs);
-            if (lane == 0) {
-                if (s < N) {
-                    const int64_t cs = s / kCh;
-                    if ((int)(cs % G) == g) {
-                        double* dst = Fl + ((size_t)(cs / G) * kCh + (s % kCh)) * D;
-#pragma unroll
-                        for (int i = 0; i < D; ++i) dst[i] = fs[i];
+                    for (int j = 0; j < 2 * D; ++j) slot[j] = tot[j];
+                    st_release(&A.flags[g], (uint32_t)s);
+                }
+                // wait until every workgroup has published step s
+                for (int q = lane; q < G; q += kWave) {
+                    uint32_t spins = 0;
+                    while (ld_relaxed(&A.flags[q]) < (uint32_t)s) {
+                        if (++spins > A.spin_limit) {
+                            ok = false;
+                            break;
+                        }
+                        spin_pause();
                     }
                 }
-                if (g == 0) {
-                    bool bad = false;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
 #pragma unroll
-                    for (int i = 0; i < D; ++i) bad |= !isfinite(y[i]);
-                    if (bad) raise_status(A.status, kStatusNonFinite);
-                    int64_t w = -1;
-                    if (A.out_stride == 0) {
-                        if (s == N) w = 0;
-                    } else if (s % A.out_stride == 0) {
-                        w = s / A.out_stride;
-                    } else if (s == N) {
-                        w = s / A.out_stride + 1;
+                for (int j = 0; j < 2 * D; ++j) {
+                    double acc = 0.0;
+                    for (int q = lane; q < G; q += kWave) acc += slot_base[(size_t)q * kPartStride + j];
+                    tot[j] = wave_sum_dpp(acc);
+                }
+            }
+            if (!ok) {
+                raise_status(A.status, kStatusTimeout);
+                s_abort = 1;
+            } else {
+                // predictor / corrector (eq. abm and the corrector after it),
+                // from the start term x0 (+ t x1 for orders above 1)
+                const double td = (double)s * A.h;
+                double base[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) base[i] = deriv[i] ? x0[i] + td * x1[i] : x0[i];
+                double yP[D], fP[D], y[D], fs[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) yP[i] = base[i] + ha[i] * tot[i];
+                rhs_eval<R, D>(A.p, td, yP, fP);
+#pragma unroll
+                for (int i = 0; i < D; ++i)
+                    y[i] = base[i] + ha[i] * ((tot[D + i] + cn[PC ? i : 0] * F0[i]) + fP[i] / g2[i]);
+                rhs_eval<R, D>(A.p, td, y, fs);
+                if (s < N) {
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) cn[w] = cw[w][s];   // c_n of the next step
+                }
+                if (lane == 0) {
+                    if (s < N) {
+                        const int64_t cs = s / kCh;
+                        if ((int)(cs % G) == g) {
+                            double* dst = Fl + ((size_t)(cs / G) * kCh + (s % kCh)) * D;
+#pragma unroll
+                            for (int i = 0; i < D; ++i) dst[i] = fs[i];
+                        }
                     }
-                    if (w >= 0) {
+                    if (g == 0) {
+                        bool bad = false;
 #pragma unroll
-                        for (int i = 0; i < D; ++i) A.y_out[w * D + i] = y[i];
+                        for (int i = 0; i < D; ++i) bad |= !isfinite(y[i]);
+                        if (bad) raise_status(A.status, kStatusNonFinite);
+                        int64_t w = -1;
+                        if (A.out_stride == 0) {
+                            if (s == N) w = 0;
+                        } else if (s % A.out_stride == 0) {
+                            w = s / A.out_stride;
+                        } else if (s == N) {
+                            w = s / A.out_stride + 1;
+                        }
+                        if (w >= 0) {
+#pragma unroll
+                            for (int i = 0; i < D; ++i) A.y_out[w * D + i] = y[i];
+                        }
                     }
                 }
             }
         }
-        __syncthreads();
+        __syncthreads();                           // f_s stored, partials consumed
+        if (s_abort) return;
     }
 }
 
-template <int R, int D, bool PC>
-hipError_t launch_plain_t(const PlainArgs& A, hipStream_t st)
+template <int R, int D, bool PC, int NL>
+hipError_t launch_plain_nl(const PlainArgs& A, hipStream_t st)
 {
-    const size_t shmem = ((size_t)A.nloc * kCh * D + 4 * 2 * D) * sizeof(double);
-    hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_plain<R, D, PC>), shmem);
+    const size_t shmem = ((size_t)A.nloc * kCh * D + kWorkWaves * 2 * D) * sizeof(double);
+    const void* fn = reinterpret_cast<const void*>(&k_plain<R, D, PC, NL>);
+    hipError_t e = allow_lds(fn, shmem);
     if (e != hipSuccess) return e;
     PlainArgs a = A;
     void* args[] = {&a};
-    return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&k_plain<R, D, PC>), dim3(A.G),
-                                      dim3(kCh), args, (unsigned)shmem, st);
+    return hipLaunchCooperativeKernel(fn, dim3(A.G), dim3(kThreads), args, (unsigned)shmem, st);
+}
+
+// Smallest register-prefetch size that holds the workgroup's local chunks.
+template <int R, int D, bool PC>
+hipError_t launch_plain_t(const PlainArgs& A, hipStream_t st)
+{
+    constexpr int NW = PC ? D : 1;
+    const int nl = A.nloc * NW <= kMaxPrefetch ? A.nloc : 0;
+    if (nl == 0) return launch_plain_nl<R, D, PC, 0>(A, st);
+    if (nl <= 1) return launch_plain_nl<R, D, PC, 1>(A, st);
+    if (nl <= 2) return launch_plain_nl<R, D, PC, 2>(A, st);
+    if constexpr (kMaxPrefetch / NW >= 4) {
+        if (nl <= 4) return launch_plain_nl<R, D, PC, 4>(A, st);
+    }
+    if constexpr (kMaxPrefetch / NW >= 8) {
+        if (nl <= 8) return launch_plain_nl<R, D, PC, 8>(A, st);
+    }
+    if constexpr (kMaxPrefetch / NW >= 16) {
+        if (nl <= 16) return launch_plain_nl<R, D, PC, 16>(A, st);
+    }
+    return launch_plain_nl<R, D, PC, 0>(A, st);
 }
 
 }  // namespace
@@ -207,6 +315,8 @@ int plain_max_local_chunks(int d)
 }
 
 int plain_chunk() { return kCh; }
+
+int plain_prefetch_chunks(int tables) { return kMaxPrefetch / tables; }
 
 int plain_part_doubles(int G) { return 2 * G * kPartStride; }
 

@@ -66,10 +66,28 @@ def test_plain_small_vs_oracle(ctx, case, N):
         assert normerr(y, oracle_run(p, stride)) <= TOL_FP64, (rhs, N, stride)
 
 
-@pytest.mark.parametrize("G", [1, 3, 64, 256])
-def test_plain_workgroup_counts(ctx, G, monkeypatch):
+@pytest.mark.parametrize("G,N", [(1, 4000), (3, 4000), (64, 4000), (256, 4000),
+                                 (1, 8192), (2, 8192), (5, 9000), (1, 300)])
+def test_plain_workgroup_counts(ctx, G, N, monkeypatch):
+    """Workgroup counts from one (no cross-workgroup synchronisation) to more
+    than there are history chunks, so that each register-prefetch size
+    (1..16 local chunks) and the in-step loads of more than 16 local chunks
+    (G = 1 at N = 8192: 32 chunks) all run."""
     monkeypatch.setenv("ABM_PLAIN_G", str(G))
-    p = inputs.duffing_single(N=4000)
+    p = inputs.duffing_single(N=N)
+    y = run_plain(ctx, p, 1)
+    assert normerr(y, oracle_run(p, 1)) <= TOL_FP64
+
+
+@pytest.mark.parametrize("G", [1, 2, 7])
+def test_plain_workgroup_counts_per_component_orders(ctx, G, monkeypatch):
+    """Two weight tables (incommensurate orders) halve the register prefetch:
+    local chunk counts of 3, 8 and 15 (in-step loads) at N = 3600 (t = 36,
+    inside the span where the chaotic circuit's rounding noise stays below
+    1e-13)."""
+    monkeypatch.setenv("ABM_PLAIN_G", str(G))
+    p = inputs.Problem("LCR", (0.9, 0.8), 0.01, 3600, (1.2, -0.4),
+                       (1.015, 0.55, -1.02, -0.58, 0.117))
     y = run_plain(ctx, p, 1)
     assert normerr(y, oracle_run(p, 1)) <= TOL_FP64
 
