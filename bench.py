@@ -32,11 +32,14 @@ DTYPE = {"fp64": "f64", "fp32": "f32 far field, f64 near/state",
          "fp16x3": "fp16x3 far field (scaled fp16 split, f32 accumulate), f64 near/state"}
 
 
-# Fastest far-field precision whose measured error on this workload stays
-# within the 1e-6 bar (see the precision tests): the scaled two-term fp16
-# split with three products (error 6e-7 against the double oracle; the
-# six-product bf16 split gives 3e-7 at about 1.3x the time).
-DEFAULT_PREC = "fp16x3"
+# Far-field precision of the headline: the bf16 split with split-precision
+# compensation (three bf16 terms of each operand, six products, float
+# accumulation per 32 rows), whose largest error over all 1024 sweep members
+# against the double oracle stays within the 1e-6 bar (4.9e-7).  The scaled
+# two-term fp16 split (fp16x3, three products) is faster but carries about 22
+# significant bits: 1.1e-6 on its worst member, over the bar; it is reported
+# under other_precisions.
+DEFAULT_PREC = "bf16x6"
 
 
 def far_source_sha():
@@ -113,14 +116,21 @@ def serving(abm, torch, inputs, n_req, arena_bytes, prec):
     starts = np.array([done[j]["t_start"] for j in range(n_req)])
     ends = np.array([done[j]["t_done"] for j in range(n_req)])
     conc = [int(np.sum((starts <= t) & (ends > t))) for t in starts]
-    # final states against the stored oracle runs of a subset (the first 16
-    # Duffing requests of at most 8192 steps of the 2000-request stream)
-    errs = []
-    if n_req == 2000:
-        for key, g in load_golden().items():
-            if key.startswith("serving_") and g["index"] < n_req and done[g["index"]]["status"] == 0:
-                y = ys[g["index"]].cpu().numpy()
+    # final states of the first 64 requests of the 2000-request stream (half
+    # Lorenz, N up to 262144) against stored oracle runs: |y_N - oracle y_N|
+    # over the oracle's max |y_s|, beside each request's noise floor (the
+    # oracle's own change for x0 scaled by 1 + 1e-14)
+    errs, floors = [], []
+    path = os.path.join(ROOT, "tests", "golden", "serving_first64.json")
+    if n_req == 2000 and os.path.exists(path):
+        with open(path) as f:
+            gold = json.load(f)
+        for g in gold.values():
+            j = g["index"]
+            if done[j]["status"] == 0:
+                y = ys[j].cpu().numpy()[-1]
                 errs.append(float(np.max(np.abs(y - np.array(g["final"])))) / g["max_abs_y"])
+                floors.append(g["noise_floor"])
     ctx.close()
     return {"requests": n_req, "ok": ok, "rate_per_s": 200.0, "arena_bytes": arena_bytes,
             "far_prec": prec, "p50_s": float(np.percentile(lat, 50)),
@@ -129,7 +139,11 @@ def serving(abm, torch, inputs, n_req, arena_bytes, prec):
             "p99_queue_s": float(np.percentile(queue, 99)),
             "mean_concurrent": float(np.mean(conc)), "max_concurrent": int(max(conc)),
             "max_rel_err_vs_oracle_final_state": max(errs) if errs else None,
+            "median_rel_err_vs_oracle_final_state": float(np.median(errs)) if errs else None,
             "err_requests": len(errs),
+            "err_requests_note": "the first 64 requests of the stream (Duffing and Lorenz, "
+                                 "N up to 262144, fp32 far field); oracle noise floor of their "
+                                 "final states up to %.2g" % max(floors) if floors else None,
             "wall_s": wall,
             "throughput_req_per_s": n_req / wall, "history_macs_per_s": macs / wall,
             "workload": "Poisson 200/s, half Duffing (d=2) half Lorenz (d=3), alpha~U[0.90,0.99], "
@@ -147,6 +161,47 @@ def load_golden():
         return {}
     with open(path) as f:
         return json.load(f)
+
+
+def sweep_golden():
+    """Stored oracle runs of all 1024 sweep members (every 1024th state,
+    written by tests/golden/make_golden.py), or None."""
+    path = os.path.join(ROOT, "tests", "golden", "duffing_sweep_all.npy")
+    return np.load(path, allow_pickle=False) if os.path.exists(path) else None
+
+
+def sweep_error(ys, gold):
+    """Normwise error of every member against its stored oracle run: the max
+    over all members, the member it occurs at, and the median."""
+    if gold is None:
+        return None
+    e = np.array([normerr(y.cpu().numpy(), gold[i]) for i, y in enumerate(ys)])
+    return {"max": float(e.max()), "argmax": int(e.argmax()), "median": float(np.median(e)),
+            "members": int(e.size)}
+
+
+def exclusive_far_rate(abm, ctx, probs, stride, tuning, prec):
+    """The far-field kernel timed on its own: a plan whose far field and
+    chains share one stream (no overlap between launches), per-launch HIP
+    events on that stream."""
+    os.environ["ABM_OVERLAP"] = "0"
+    try:
+        plan = abm.Plan(ctx, probs, out_stride=stride, tuning=tuning)
+    finally:
+        del os.environ["ABM_OVERLAP"]
+    ys = [abm.alloc_out(p, stride) for p in probs]
+    abm.solve_batch(plan, probs, ys)            # warm-up
+    plan.timing(True)
+    st = abm.solve_batch(plan, probs, ys)
+    plan.timing(False)
+    plan.check()
+    plan.close()
+    far_flop = 4.0 * st["far_macs"]
+    achieved = far_flop / (st["far_ms"] / 1e3) / 1e12
+    return {"achieved": achieved, "frac": achieved / PEAK_TFLOPS[prec],
+            "executed_frac": achieved * EXEC_FACTOR[prec] / PEAK_TFLOPS[prec],
+            "far_ms_total": st["far_ms"], "avg_launch_ms": st["far_ms"] / st["far_launches"],
+            "chain_ms_total": st["chain_ms"], "launches": st["far_launches"]}
 
 
 def time_batch(abm, torch, plan, probs, ys, steps, warmup):
@@ -207,11 +262,14 @@ def plain_leg(abm, torch, inputs, ctx):
     y1 = abm.alloc_out(p1, 0)
     abm.solve(pp, p1, y1)
     pp.check()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    abm.solve(pp, p1, y1)
-    torch.cuda.synchronize()
-    dt1 = time.perf_counter() - t1
+    runs = []
+    for _ in range(5):                       # median of 5 after one warm-up
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        abm.solve(pp, p1, y1)
+        torch.cuda.synchronize()
+        runs.append(time.perf_counter() - t1)
+    dt1 = float(np.median(runs))
     pp.check()
     pp.close()
     # algorithmic bytes if every step streamed its history and weights: per
@@ -219,7 +277,7 @@ def plain_leg(abm, torch, inputs, ctx):
     n = p1.N
     algo_bytes = n * (n + 1) / 2 * 8 * (p1.d + 2)
     res = {"workload": "forced Duffing, alpha=0.9, h=1e-3, N=200000, d=2, one trajectory",
-           "seconds": dt1, "history_macs_per_s": p1.history_macs() / dt1,
+           "seconds": dt1, "seconds_runs": runs, "history_macs_per_s": p1.history_macs() / dt1,
            "us_per_step": dt1 / p1.N * 1e6,
            "streamed_bytes": algo_bytes, "effective_GBps": algo_bytes / dt1 / 1e9,
            "frac_of_hbm_peak": algo_bytes / dt1 / 8e12,
@@ -235,12 +293,14 @@ def plain_leg(abm, torch, inputs, ctx):
               (lambda: abm.solve_batch(pp, [p0], [y0]))
         run()
         pp.check()
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        for _ in range(5):
+        runs = []
+        for _ in range(5):                   # median of 5
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
             run()
-        torch.cuda.synchronize()
-        times[mode] = (time.perf_counter() - t1) / 5
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t1)
+        times[mode] = float(np.median(runs))
         pp.check()
     pp.close()
     res["linear_test"] = {"workload": "D^0.8 y = -y, y0 = 1, h = 2^-10, N = 8192, one trajectory",
@@ -252,7 +312,7 @@ def plain_leg(abm, torch, inputs, ctx):
 def long_leg(abm, torch, inputs, ctx):
     """The paper's step counts (Table 1: 1e6 and 3e6 steps of one trajectory):
     the forced fractional LCR circuit (alpha = 0.9, h = 0.01, f = 0.117) by the
-    blocked path, double far field."""
+    blocked path, double far field; median of three solves after a warm-up."""
     res = {"workload": "forced fractional LCR circuit, alpha=0.9, h=0.01, f=0.117, d=2, "
                        "one trajectory, far field fp64",
            "paper_bgp_seconds": {"1000000": 69.06, "3000000": 304.17}}
@@ -260,15 +320,22 @@ def long_leg(abm, torch, inputs, ctx):
         p = inputs.Problem("LCR", 0.9, 0.01, N, (0.1, 0.0), inputs.LCR_P + (0.117,))
         plan = abm.Plan(ctx, [p], out_stride=0)
         y = abm.alloc_out(p, 0)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        abm.solve_batch(plan, [p], [y])
-        torch.cuda.synchronize()
-        dt = time.perf_counter() - t0
+        abm.solve_batch(plan, [p], [y])      # warm-up
+        runs = []
+        for _ in range(3):                   # median of 3
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            abm.solve_batch(plan, [p], [y])
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t0)
+        dt = float(np.median(runs))
         plan.check()
         plan.close()
-        res[str(N)] = {"seconds": dt, "history_macs_per_s": p.history_macs() / dt,
-                       "us_per_step": dt / N * 1e6}
+        res[str(N)] = {"seconds": dt, "seconds_runs": runs,
+                       "history_macs_per_s": p.history_macs() / dt, "us_per_step": dt / N * 1e6,
+                       "parity": "tests/test_gpu_long.py: ~50 sampled steps of this launch "
+                                 "shape recomputed by the oracle from the GPU's own states, "
+                                 "each within its double-precision rounding bound"}
     return res
 
 
@@ -388,17 +455,10 @@ def main():
         eager_dt, _ = time_batch(abm, torch, plan, probs, ys, args.steps, 1)
         plan.graph(True)
 
-    # error against the stored double-precision oracle runs of four members
-    gold_path = os.path.join(ROOT, "tests", "golden", "oracle_fullsize.json")
-    errs = {}
-    if os.path.exists(gold_path):
-        with open(gold_path) as f:
-            g = json.load(f)
-        for i in (0, 1, 511, 1023):
-            key = "duffing_sweep_%d" % i
-            if key in g:
-                errs[i] = normerr(ys[i].cpu().numpy(), np.array(g[key]["y"]))
-    max_err = max(errs.values()) if errs else None
+    # error of every member against the stored double-precision oracle runs
+    gold = sweep_golden()
+    errs = sweep_error(ys, gold)
+    max_err = errs["max"] if errs else None
 
     # roofline of the far-field kernel: one more solve with per-launch events
     plan.timing(True)
@@ -419,6 +479,20 @@ def main():
             # launches of consecutive ticks overlap: the far field's rate over
             # the whole solve's wall time, for comparison
             "achieved_over_solve_wall": far_flop / dt / 1e12}
+    # the far-field kernel on its own (launches serialised on one stream):
+    # the kernel's own rate, reported as achieved/frac; the overlapped
+    # per-launch figure and the solve-wall bound are kept beside it
+    excl = exclusive_far_rate(abm, ctx, probs, stride, plan.config(), args.prec)
+    roof["overlapped"] = {"achieved": roof["achieved"], "frac": roof["frac"],
+                          "avg_launch_ms": roof["avg_launch_ms"]}
+    roof["achieved"] = excl["achieved"]
+    roof["frac"] = excl["frac"]
+    roof["executed_frac"] = excl["executed_frac"]
+    roof["avg_launch_ms"] = excl["avg_launch_ms"]
+    roof["exclusive"] = excl
+    roof["measure"] = ("achieved/frac: useful FLOP (4 per far-field history MAC) over the far "
+                       "kernel's own launch time, launches serialised on one stream; "
+                       "overlapped: the same launches timed inside the overlapped solve")
 
     plain = None if args.no_plain else plain_leg(abm, torch, inputs, ctx)
     longrun = None if args.no_long else long_leg(abm, torch, inputs, ctx)
@@ -443,15 +517,11 @@ def main():
             pl2 = abm.Plan(ctx, pp, out_stride=stride, tuning=None if pr == "fp64" else plan.config())
             pl2.graph(not args.eager)
             dt2, st2 = time_batch(abm, torch, pl2, pp, ys, 2, 1)
-            e2 = {}
-            if os.path.exists(gold_path):
-                for i in (0, 1, 511, 1023):
-                    key = "duffing_sweep_%d" % i
-                    if key in g:
-                        e2[i] = normerr(ys[i].cpu().numpy(), np.array(g[key]["y"]))
+            e2 = sweep_error(ys, gold)
             others[pr] = {"value": st2["history_macs"] / dt2, "ms_per_step": dt2 * 1e3,
                           "blocking": pl2.config(),
-                          "max_rel_err_vs_oracle": max(e2.values()) if e2 else None}
+                          "max_rel_err_vs_oracle": e2["max"] if e2 else None,
+                          "err_all_members": e2}
             pl2.close()
 
     cpu = None if args.no_cpu else cpu_baseline(inputs)
@@ -479,7 +549,7 @@ def main():
         "long_trajectory": longrun,
         "lcr_sweep": lcr,
         "max_rel_err_vs_oracle": max_err,
-        "err_members": errs,
+        "err_all_members": errs,
         "plan_seconds": plan_s,
         "autotune": tune_report,
         "roofline": roof,

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_1710_01133_amd import abm, inputs
-from gpu_common import TOL_FP64, golden, normerr, oracle_run, run_batch
+from gpu_common import sweep_errors, TOL_FP64, golden, normerr, oracle_run, run_batch
 
 pytestmark = pytest.mark.gpu
 
@@ -91,16 +91,13 @@ def test_batch_single_trajectory_long(ctx):
 
 def test_sweep_full_size_fp64(ctx, monkeypatch):
     """B = 1024, N = 65536 forcing sweep at the benchmark's launch shape:
-    sampled members against stored oracle runs, the rest finite and bounded,
-    and one member alone equal bit for bit to its column in the full batch."""
+    every member against its stored oracle run, and one member alone equal
+    bit for bit to its column in the full batch."""
     probs = inputs.duffing_sweep()
     outs, st = run_batch(ctx, probs, 1024)
-    g = golden()
-    for idx in (0, 1, 511, 1023):
-        ref = np.array(g["duffing_sweep_%d" % idx]["y"])
-        assert normerr(outs[idx], ref) <= TOL_FP64, idx
-    allv = np.stack(outs)
-    assert np.all(np.isfinite(allv)) and np.max(np.abs(allv)) < 10
+    errs = sweep_errors(outs)
+    print("fp64 sweep: max error %.3g (member %d)" % (errs.max(), errs.argmax()))
+    assert errs.max() <= TOL_FP64, int(errs.argmax())
     alone, _ = run_batch(ctx, [probs[511]], 1024)           # narrow group: other sum order
     assert normerr(alone[0], outs[511]) <= 1e-13
     monkeypatch.setenv("ABM_NARROW", "0")                    # same kernel: same bits

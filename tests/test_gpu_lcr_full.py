@@ -1,0 +1,72 @@
+"""The paper's own workload at full length: the forced fractional LCR circuit
+(eq. sys.LRC; sigma = 1.015, omega = 0.55, a = -1.02, b = -0.58) swept over
+its forcing F in [0, 0.2], B = 1024, N = 65536 (t = 653), with commensurate
+(0.9, 0.9) and incommensurate (0.9, 0.8) orders, in double and in the
+benchmark's fp16x3 far field, at the launch shapes the benchmark times.
+
+Chaos at some F makes a whole-trajectory comparison with the oracle
+ill-posed beyond t ~ 36, so sampled steps are recomputed by the oracle from
+the GPU's own states (gpu_common.recompute_errors): the double far field
+within its rounding bound, the fp16x3 far field within 1e-6 of the state's
+scale per step.  The Poincare-section output the benchmark writes (every
+1142nd state) is checked to be exactly those states of the full run."""
+import numpy as np
+import pytest
+
+from paper_1710_01133_amd import abm, inputs
+from gpu_common import check_steps_fp64, recompute_errors, sampled_steps
+
+pytestmark = pytest.mark.gpu
+
+MEMBERS = (0, 300, 585, 1023)          # F = 0, 0.059, 0.114 (near the chaotic band), 0.2
+SPLIT_BLOCKING = dict(block_L=256, kchunk=2048, max_split=2, column_tiles_only=0)
+TOL_STEP_LOWP = 1e-6
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    assert torch.cuda.is_available()
+    torch.cuda.init()
+    c = abm.Context(0)
+    yield c
+    c.close()
+
+
+def _solve(ctx, probs, stride, tuning):
+    plan = abm.Plan(ctx, probs, out_stride=stride, tuning=tuning)
+    ys = [abm.alloc_out(p, stride) for p in probs]
+    abm.solve_batch(plan, probs, ys)
+    plan.check()
+    plan.close()
+    return ys
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp16x3"])
+@pytest.mark.parametrize("alpha", [(0.9, 0.9), (0.9, 0.8)], ids=["0.9-0.9", "0.9-0.8"])
+def test_lcr_sweep_full_length(ctx, alpha, prec):
+    probs = inputs.lcr_sweep(alpha=alpha, far_prec=prec)
+    tuning = None if prec == "fp64" else SPLIT_BLOCKING
+    ys = _solve(ctx, probs, 1, tuning)
+    hist = {i: ys[i].cpu().numpy() for i in MEMBERS}
+    del ys
+    M = inputs.LCR_SECTION_STEPS
+    sec = _solve(ctx, probs, M, tuning)
+    for i in MEMBERS:
+        s = sec[i].cpu().numpy()
+        assert np.array_equal(s[:-1], hist[i][::M][: s.shape[0] - 1]), i
+        assert np.array_equal(s[-1], hist[i][-1]), i
+    del sec
+    N = probs[0].N
+    for i in MEMBERS:
+        y = hist[i]
+        assert np.all(np.isfinite(y))
+        s_list = sampled_steps(N, seed=i)
+        if prec == "fp64":
+            worst = check_steps_fp64(probs[i], y, s_list)
+            print(alpha, prec, i, "largest error / bound %.3g" % worst)
+        else:
+            err, _ = recompute_errors(probs[i], y, s_list)
+            rel = float(np.max(err) / np.max(np.abs(y)))
+            print(alpha, prec, i, "largest step error %.3g of max|y|" % rel)
+            assert rel <= TOL_STEP_LOWP, (i, rel)
