@@ -374,9 +374,15 @@ abm_status abm_solve(abm_plan_t* pl, const abm_problem* prob, double* y_out)
     A.out_stride = prob->out_stride;
     A.status = pl->status;
     A.spin_limit = kSpinLimit;
+    const int kind = chain_kind(prob->rhs, orders_differ(*prob));
+    if (pl->plain_single) {
+        e = launch_plain_single(A, kind, pl->ctx->stream);
+        if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
+        return ABM_OK;
+    }
     e = launch_fill_u32(pl->flags, 0, pl->plain_G, pl->ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "flag reset");
-    e = launch_plain(A, chain_kind(prob->rhs, orders_differ(*prob)), pl->ctx->stream);
+    e = launch_plain(A, kind, pl->ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
     return ABM_OK;
 }
@@ -397,10 +403,19 @@ abm_status plain_setup(abm_plan_s* pl)
     if (gmin > gcap)
         return fail(ABM_EINVAL, "N=%lld too long for the plain path (history does not fit the LDS of %d workgroups)",
                     (long long)p.N, gcap);
-    // default: the fewest workgroups whose local chunks all fit the
-    // kernel's register prefetch (no weight load on a step's dependent path)
-    const int pref = plain_prefetch_chunks(orders_differ(p) ? p.d : 1);
+    // a history that fits one CU runs in one workgroup with no grid
+    // synchronisation (unless a workgroup count is forced)
+    const int tables = orders_differ(p) ? p.d : 1;
     int G = env_int("ABM_PLAIN_G", 0);
+    if (G <= 0 && plain_single_fits(p.N, p.d, tables)) {
+        pl->plain_single = true;
+        pl->plain_G = 1;
+        pl->plain_nloc = 0;
+        return ABM_OK;
+    }
+    // otherwise the fewest workgroups whose local chunks all fit the
+    // kernel's register prefetch (no weight load on a step's dependent path)
+    const int pref = plain_prefetch_chunks(tables);
     if (G <= 0) G = (int)((nchunks + pref - 1) / pref);
     G = std::max(G, gmin);
     G = std::min(G, gcap);

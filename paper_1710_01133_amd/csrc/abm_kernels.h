@@ -52,6 +52,12 @@ int plain_prefetch_chunks(int tables);
 int plain_part_doubles(int G);
 // kind: chain_kind(rhs, components have their own orders)
 hipError_t launch_plain(const PlainArgs& A, int kind, hipStream_t st);
+// The one-workgroup form (no grid synchronisation, weights held in registers)
+// for histories that fit one CU's LDS: whether N steps of d components with
+// the given number of weight tables fit it, and its launch (G, nloc, part and
+// flags of A are not used).
+bool plain_single_fits(int64_t N, int d, int tables);
+hipError_t launch_plain_single(const PlainArgs& A, int kind, hipStream_t st);
 
 // ---- blocked method: groups and work items --------------------------------
 // A group is a set of trajectories sharing their orders (one weight table, or

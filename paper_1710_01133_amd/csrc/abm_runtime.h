@@ -99,6 +99,7 @@ struct abm_plan_s {
     // plain path (B == 1)
     int plain_G = 0;
     int plain_nloc = 0;
+    bool plain_single = false;    // the one-workgroup form (short histories)
     std::string plain_error;
     double* part = nullptr;
     uint32_t* flags = nullptr;

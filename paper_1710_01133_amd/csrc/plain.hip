@@ -306,6 +306,213 @@ hipError_t launch_plain_t(const PlainArgs& A, hipStream_t st)
     return launch_plain_nl<R, D, PC, 0>(A, st);
 }
 
+// ---------------------------------------------------------------------------
+// One workgroup, no grid synchronisation, for histories that fit one CU's LDS.
+// Weights stationary: work thread u of the NTH/64 - 1 work waves holds b_j,
+// a_j for j = u + (NTH - 64) q (q < NJ) in registers for the whole run and
+// reads f_{n-j} from the history in LDS (the same sums as Algorithm 1, split
+// over threads by weight index instead of history index).  Wave 0 only
+// updates: it adds the j = 0 terms, b_0 f_n and a_0 f_n, itself, with the f_n
+// it has just computed, so the work waves can sum step s+1's terms j >= 1
+// (f_{s-1} and older) while wave 0 updates step s; one barrier per step.
+// Scalar systems run 1024 threads (128 registers per lane); larger systems
+// 512, whose update needs more registers.
+constexpr size_t kSingleLds = 160 * 1024;
+constexpr int single_threads(int d, bool pc) { return (d == 1 && !pc) ? 1024 : 512; }
+// most weights per thread (over all tables) that stay in registers
+constexpr int single_max_nj(int d, bool pc) { return (d == 1 && !pc) ? 10 : 16; }
+
+template <int R, int D, bool PC, int NJ>
+__global__ __launch_bounds__(single_threads(D, PC)) void k_plain_single(PlainArgs A)
+{
+    constexpr int kSingleWork = single_threads(D, PC) - kWave;   // work threads
+    constexpr int kSingleWaves = kSingleWork / kWave;
+    extern __shared__ double sm[];
+    double* Fl = sm;                                   // [N][D] f_0 .. f_{N-1}
+    double* red = sm + (size_t)A.N * D;                // [2][work waves][2D] by step parity
+    constexpr int NW = PC ? D : 1;
+    const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
+    const int64_t N = A.N;
+
+    double wb[NJ][NW], wa[NJ][NW];                     // work waves: weights j = u + 960 q
+    double ha[D], g2[D], x0[D], x1[D], F0[D], Fn[D], cn[NW], b0[NW], a0[NW];
+    bool deriv[D];
+    if (wid == 0) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const int w = PC ? i : 0;
+            ha[i] = pow(A.h, A.alpha[w]);
+            g2[i] = A.gam[w][1];
+            deriv[i] = A.alpha[w] > 1.0;
+            x0[i] = A.x0[i];
+            x1[i] = A.x1[i];
+        }
+        rhs_eval<R, D>(A.p, 0.0, x0, F0);
+#pragma unroll
+        for (int i = 0; i < D; ++i) Fn[i] = F0[i];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            cn[w] = A.c[w][0];
+            b0[w] = A.b[w][0];
+            a0[w] = A.a[w][0];
+        }
+        if (lane == 0) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) Fl[i] = F0[i];
+            if (A.out_stride > 0) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) A.y_out[i] = x0[i];
+            }
+        }
+    } else {
+        const int u = t - kWave;
+#pragma unroll
+        for (int q = 0; q < NJ; ++q) {
+            const int j = u + kSingleWork * q;        // N <= 2^30: 32-bit indices
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                wb[q][w] = j < N ? A.b[w][j] : 0.0;
+                wa[q][w] = j < N ? A.a[w][j] : 0.0;
+            }
+        }
+    }
+    __syncthreads();
+
+    for (int64_t s = 1; s <= N; ++s) {
+        const int64_t n = s - 1;
+        double* rp = red + (size_t)(s & 1) * kSingleWaves * 2 * D;
+        if (wid != 0) {
+            const int u = t - kWave, nn = (int)n;
+            double P[D], C[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) P[i] = C[i] = 0.0;
+#pragma unroll
+            for (int q = 0; q < NJ; ++q) {
+                const int j = u + kSingleWork * q;
+                if (j >= 1 && j <= nn) {
+                    const double* f = Fl + (nn - j) * D;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        const double fc = j <= nn - 1 ? f[i] : 0.0;   // k = n - j >= 1
+                        P[i] = fma(wb[q][PC ? i : 0], f[i], P[i]);
+                        C[i] = fma(wa[q][PC ? i : 0], fc, C[i]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const double ps = wave_sum_dpp(P[i]);
+                const double cs = wave_sum_dpp(C[i]);
+                if (lane == 0) {
+                    rp[(wid - 1) * 2 * D + i] = ps;
+                    rp[(wid - 1) * 2 * D + D + i] = cs;
+                }
+            }
+        }
+        __syncthreads();                           // step s's partials are in LDS
+        if (wid == 0) {
+            double tot[2 * D];
+#pragma unroll
+            for (int j = 0; j < 2 * D; ++j) {
+                double acc = rp[j];
+#pragma unroll
+                for (int w = 1; w < kSingleWaves; ++w) acc += rp[w * 2 * D + j];
+                tot[j] = acc;
+            }
+            // the j = 0 terms: b_0 f_n, and a_0 f_n when k = n >= 1
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                tot[i] = fma(b0[PC ? i : 0], Fn[i], tot[i]);
+                if (n >= 1) tot[D + i] = fma(a0[PC ? i : 0], Fn[i], tot[D + i]);
+            }
+            const double td = (double)s * A.h;
+            double base[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) base[i] = deriv[i] ? x0[i] + td * x1[i] : x0[i];
+            double yP[D], fP[D], y[D], fs[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) yP[i] = base[i] + ha[i] * tot[i];
+            rhs_eval<R, D>(A.p, td, yP, fP);
+#pragma unroll
+            for (int i = 0; i < D; ++i)
+                y[i] = base[i] + ha[i] * ((tot[D + i] + cn[PC ? i : 0] * F0[i]) + fP[i] / g2[i]);
+            rhs_eval<R, D>(A.p, td, y, fs);
+            if (s < N) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) cn[w] = A.c[w][s];   // c_n of the next step
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i) Fn[i] = fs[i];
+            if (lane == 0) {
+                if (s < N) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i) Fl[(size_t)s * D + i] = fs[i];
+                }
+                bool bad = false;
+#pragma unroll
+                for (int i = 0; i < D; ++i) bad |= !isfinite(y[i]);
+                if (bad) raise_status(A.status, kStatusNonFinite);
+                int64_t w = -1;
+                if (A.out_stride == 0) {
+                    if (s == N) w = 0;
+                } else if (s % A.out_stride == 0) {
+                    w = s / A.out_stride;
+                } else if (s == N) {
+                    w = s / A.out_stride + 1;
+                }
+                if (w >= 0) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i) A.y_out[w * D + i] = y[i];
+                }
+            }
+        }
+        // no second barrier: the work waves' next partials read f_{s-1} and
+        // older (stored before this step's barrier) and the other half of red
+    }
+}
+
+size_t single_lds(int64_t N, int d, bool pc)
+{
+    return ((size_t)N * d + 2 * (single_threads(d, pc) / kWave - 1) * 2 * d) * sizeof(double);
+}
+
+template <int R, int D, bool PC, int NJ>
+hipError_t launch_single_nj(const PlainArgs& A, hipStream_t st)
+{
+    const size_t shmem = single_lds(A.N, D, PC);
+    const void* fn = reinterpret_cast<const void*>(&k_plain_single<R, D, PC, NJ>);
+    hipError_t e = allow_lds(fn, shmem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_plain_single<R, D, PC, NJ>), dim3(1), dim3(single_threads(D, PC)), shmem,
+                       st, A);
+    return hipGetLastError();
+}
+
+template <int R, int D, bool PC>
+hipError_t launch_single_t(const PlainArgs& A, hipStream_t st)
+{
+    constexpr int NW = PC ? D : 1;
+    constexpr int kSingleWork = single_threads(D, PC) - kWave;
+    const int64_t nj = (A.N + kSingleWork - 1) / kSingleWork;
+    if (nj <= 1) return launch_single_nj<R, D, PC, 1>(A, st);
+    if (nj <= 2) return launch_single_nj<R, D, PC, 2>(A, st);
+    if (nj <= 4) return launch_single_nj<R, D, PC, 4>(A, st);
+    constexpr int MAXNJ = single_max_nj(D, PC);
+    if constexpr (8 * NW <= MAXNJ) {
+        if (nj <= 8) return launch_single_nj<R, D, PC, 8>(A, st);
+    }
+    if constexpr (10 * NW <= MAXNJ && MAXNJ < 12) {
+        if (nj <= 10) return launch_single_nj<R, D, PC, 10>(A, st);
+    }
+    if constexpr (12 * NW <= MAXNJ) {
+        if (nj <= 12) return launch_single_nj<R, D, PC, 12>(A, st);
+    }
+    if constexpr (16 * NW <= MAXNJ) {
+        if (nj <= 16) return launch_single_nj<R, D, PC, 16>(A, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 }  // namespace
 
 int plain_max_local_chunks(int d)
@@ -319,6 +526,33 @@ int plain_chunk() { return kCh; }
 int plain_prefetch_chunks(int tables) { return kMaxPrefetch / tables; }
 
 int plain_part_doubles(int G) { return 2 * G * kPartStride; }
+
+bool plain_single_fits(int64_t N, int d, int tables)
+{
+    const bool pc = tables > 1;
+    const int64_t nj = (N + single_threads(d, pc) - kWave - 1) / (single_threads(d, pc) - kWave);
+    int njmax = 0;
+    for (int c : {1, 2, 4, 8, 10, 12, 16})
+        if (c * tables <= single_max_nj(d, pc) && (c != 10 || single_max_nj(d, pc) < 12)) njmax = c;
+    return nj <= njmax && single_lds(N, d, pc) <= kSingleLds;
+}
+
+hipError_t launch_plain_single(const PlainArgs& A, int kind, hipStream_t st)
+{
+    switch (kind) {
+    case ABM_RHS_LINEAR: return launch_single_t<ABM_RHS_LINEAR, 1, false>(A, st);
+    case ABM_RHS_DUFFING: return launch_single_t<ABM_RHS_DUFFING, 2, false>(A, st);
+    case ABM_RHS_LORENZ: return launch_single_t<ABM_RHS_LORENZ, 3, false>(A, st);
+    case ABM_RHS_POLY: return launch_single_t<ABM_RHS_POLY, 1, false>(A, st);
+    case ABM_RHS_LCR: return launch_single_t<ABM_RHS_LCR, 2, false>(A, st);
+    case ABM_RHS_DIAG: return launch_single_t<ABM_RHS_DIAG, 2, false>(A, st);
+    case kRhsCount + ABM_RHS_DUFFING: return launch_single_t<ABM_RHS_DUFFING, 2, true>(A, st);
+    case kRhsCount + ABM_RHS_LORENZ: return launch_single_t<ABM_RHS_LORENZ, 3, true>(A, st);
+    case kRhsCount + ABM_RHS_LCR: return launch_single_t<ABM_RHS_LCR, 2, true>(A, st);
+    case kRhsCount + ABM_RHS_DIAG: return launch_single_t<ABM_RHS_DIAG, 2, true>(A, st);
+    default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_plain(const PlainArgs& A, int kind, hipStream_t st)
 {
