@@ -263,6 +263,25 @@ abm_status abm_request_bytes(abm_ctx *ctx, const abm_problem *prob, size_t *byte
  * request that failed reports ABM_OK here with res->status set.  Thread-safe. */
 abm_status abm_poll(abm_ctx *ctx, uint64_t ticket, abm_result *res);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): abm_solve
+ * without a plan.  One trajectory by the plain per-step method, on the
+ * current HIP device, enqueued on hip_stream (a hipStream_t; NULL = the null
+ * stream), results bitwise those of abm_solve for the same problem.  prob and
+ * y_out as for abm_solve (y_out: device memory of n_out*d doubles, owned by
+ * the caller).  Allocates nothing: the weight tables, the status word and the
+ * cooperative form's step flags and partial sums live in a library-wide
+ * device array of 8 MiB that each GPU holds until the process ends.
+ * Limit: (distinct orders among the components) * 3 * (N + 2048) * 8 bytes
+ * plus 34 KiB must fit those 8 MiB (one order: N <= 346000), and the plain
+ * path's own limit applies; larger problems return ABM_EINVAL.  Calls on one
+ * GPU share the array and keep the last call's contents: calls that overlap
+ * on one GPU (different streams or host threads) race and must be serialised
+ * by the caller; one stream orders them.  No plan means no abm_plan_check: a
+ * run whose device-side wait gave up, or whose state became non-finite,
+ * leaves a non-finite final state in y_out.  Errors: ABM_EINVAL, ABM_EDEVICE. */
+abm_status abm_solve_noalloc(const abm_problem *prob, double *y_out, void *hip_stream);
+
 /* Cancel a queued or running request (its poll then reports ABM_ECANCELED). */
 abm_status abm_cancel(abm_ctx *ctx, uint64_t ticket);
 

@@ -26,7 +26,7 @@ PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 4}
 EXPORTED = ("abm_ctx_create", "abm_ctx_destroy", "abm_plan", "abm_plan_destroy", "abm_plan_check",
             "abm_plan_weights", "abm_plan_timing", "abm_plan_graph", "abm_solve", "abm_solve_batch", "abm_submit", "abm_poll", "abm_cancel",
             "abm_request_bytes", "abm_plan_tuned", "abm_plan_config", "abm_autotune",
-            "abm_strerror", "abm_last_error")
+            "abm_strerror", "abm_last_error", "abm_solve_noalloc")
 
 
 class AbmProblem(ctypes.Structure):
@@ -126,10 +126,11 @@ def load(path: str = LIB_PATH):
     lib.abm_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(AbmResult)]
     lib.abm_cancel.argtypes = [vp, ctypes.c_uint64]
     lib.abm_request_bytes.argtypes = [vp, ctypes.POINTER(AbmProblem), ctypes.POINTER(ctypes.c_size_t)]
+    lib.abm_solve_noalloc.argtypes = [ctypes.POINTER(AbmProblem), vp, vp]
     for name in ("abm_ctx_create", "abm_plan", "abm_plan_check", "abm_plan_weights",
                  "abm_plan_timing", "abm_plan_graph", "abm_solve", "abm_solve_batch", "abm_submit", "abm_poll",
                  "abm_cancel", "abm_request_bytes", "abm_plan_tuned", "abm_plan_config",
-                 "abm_autotune"):
+                 "abm_autotune", "abm_solve_noalloc"):
         getattr(lib, name).restype = ctypes.c_int32
     lib.abm_strerror.argtypes = [ctypes.c_int32]
     lib.abm_strerror.restype = ctypes.c_char_p
@@ -296,6 +297,17 @@ def solve(plan: Plan, problem: Problem, y_out) -> None:
     c = c_problem(problem, plan.out_stride)
     _check(load().abm_solve(plan.handle, ctypes.byref(c), ctypes.c_void_p(y_out.data_ptr())),
            "abm_solve")
+
+
+def solve_noalloc(problem: Problem, y_out, out_stride: int = 0, stream: Optional[int] = None) -> None:
+    """abm_solve_noalloc: the plain path without a plan or any device
+    allocation, on the current device and stream (torch's current one by
+    default).  y_out: float64 device tensor of n_out(N, out_stride) x d."""
+    c = c_problem(problem, out_stride)
+    if stream is None:
+        stream = _current_stream_handle()
+    _check(load().abm_solve_noalloc(ctypes.byref(c), ctypes.c_void_p(y_out.data_ptr()),
+                                    ctypes.c_void_p(stream)), "abm_solve_noalloc")
 
 
 def solve_batch(plan: Plan, problems: Sequence[Problem], y_outs: List) -> dict:

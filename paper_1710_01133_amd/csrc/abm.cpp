@@ -352,37 +352,18 @@ abm_status abm_solve(abm_plan_t* pl, const abm_problem* prob, double* y_out)
         return fail(ABM_EINVAL, "problem does not match the plan (rhs, d, orders, N, far_prec, out_stride)");
     hipError_t e = hipSetDevice(pl->ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    PlainArgs A{};
+    PlainTables T{};
     for (int i = 0; i < 4; ++i) {
         const WeightTable& t = pl->tables[pl->table_of[i]];
-        A.b[i] = t.b;
-        A.a[i] = t.a;
-        A.c[i] = t.c;
-        A.gam[i] = t.gam;
-        A.alpha[i] = t.alpha;
-        A.x0[i] = prob->x0[i];
-        A.x1[i] = prob->x1[i];
+        T.b[i] = t.b;
+        T.a[i] = t.a;
+        T.c[i] = t.c;
+        T.gam[i] = t.gam;
+        T.alpha[i] = t.alpha;
     }
-    A.h = prob->h;
-    for (int i = 0; i < 8; ++i) A.p[i] = prob->p[i];
-    A.N = prob->N;
-    A.G = pl->plain_G;
-    A.nloc = pl->plain_nloc;
-    A.part = pl->part;
-    A.flags = pl->flags;
-    A.y_out = y_out;
-    A.out_stride = prob->out_stride;
-    A.status = pl->status;
-    A.spin_limit = kSpinLimit;
-    const int kind = chain_kind(prob->rhs, orders_differ(*prob));
-    if (pl->plain_single) {
-        e = launch_plain_single(A, kind, pl->ctx->stream);
-        if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
-        return ABM_OK;
-    }
-    e = launch_fill_u32(pl->flags, 0, pl->plain_G, pl->ctx->stream);
-    if (e != hipSuccess) return hip_fail(e, "flag reset");
-    e = launch_plain(A, kind, pl->ctx->stream);
+    const PlainShape sh{pl->plain_single, pl->plain_G, pl->plain_nloc};
+    const PlainArgs A = plain_args(*prob, T, sh, pl->part, pl->flags, pl->status, y_out);
+    e = plain_enqueue(A, sh, chain_kind(prob->rhs, orders_differ(*prob)), pl->ctx->stream);
     if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
     return ABM_OK;
 }
@@ -391,14 +372,13 @@ abm_status abm_solve(abm_plan_t* pl, const abm_problem* prob, double* y_out)
 
 namespace abm {
 
-abm_status plain_setup(abm_plan_s* pl)
+abm_status plain_shape(const abm_problem& p, int n_cu, PlainShape* out)
 {
-    const abm_problem& p = pl->shape[0];
     const int ch = plain_chunk();
     const int64_t nchunks = std::max<int64_t>(1, (p.N + ch - 1) / ch);   // indices 0..N-1
     const int nloc_max = plain_max_local_chunks(p.d);
     // co-residency bound: one workgroup per CU is always possible for this kernel
-    const int gcap = std::min(pl->ctx->n_cu, 256);
+    const int gcap = std::min(n_cu, 256);
     const int gmin = (int)((nchunks + nloc_max - 1) / nloc_max);
     if (gmin > gcap)
         return fail(ABM_EINVAL, "N=%lld too long for the plain path (history does not fit the LDS of %d workgroups)",
@@ -408,9 +388,7 @@ abm_status plain_setup(abm_plan_s* pl)
     const int tables = orders_differ(p) ? p.d : 1;
     int G = env_int("ABM_PLAIN_G", 0);
     if (G <= 0 && plain_single_fits(p.N, p.d, tables)) {
-        pl->plain_single = true;
-        pl->plain_G = 1;
-        pl->plain_nloc = 0;
+        *out = PlainShape{true, 1, 0};
         return ABM_OK;
     }
     // otherwise the fewest workgroups whose local chunks all fit the
@@ -419,10 +397,56 @@ abm_status plain_setup(abm_plan_s* pl)
     if (G <= 0) G = (int)((nchunks + pref - 1) / pref);
     G = std::max(G, gmin);
     G = std::min(G, gcap);
-    pl->plain_G = G;
-    pl->plain_nloc = (int)((nchunks + G - 1) / G);
-    abm_status st = dev_alloc((void**)&pl->part, plain_part_doubles(G) * sizeof(double), "plain partials");
-    if (st == ABM_OK) st = dev_alloc((void**)&pl->flags, G * sizeof(uint32_t), "plain flags");
+    *out = PlainShape{false, G, (int)((nchunks + G - 1) / G)};
+    return ABM_OK;
+}
+
+PlainArgs plain_args(const abm_problem& prob, const PlainTables& T, const PlainShape& sh,
+                     double* part, uint32_t* flags, uint32_t* status, double* y_out)
+{
+    PlainArgs A{};
+    for (int i = 0; i < 4; ++i) {
+        A.b[i] = T.b[i];
+        A.a[i] = T.a[i];
+        A.c[i] = T.c[i];
+        A.gam[i] = T.gam[i];
+        A.alpha[i] = T.alpha[i];
+        A.x0[i] = prob.x0[i];
+        A.x1[i] = prob.x1[i];
+    }
+    A.h = prob.h;
+    for (int i = 0; i < 8; ++i) A.p[i] = prob.p[i];
+    A.N = prob.N;
+    A.G = sh.G;
+    A.nloc = sh.nloc;
+    A.part = part;
+    A.flags = flags;
+    A.y_out = y_out;
+    A.out_stride = prob.out_stride;
+    A.status = status;
+    A.spin_limit = kSpinLimit;
+    return A;
+}
+
+hipError_t plain_enqueue(const PlainArgs& A, const PlainShape& sh, int kind, hipStream_t st)
+{
+    if (sh.single) return launch_plain_single(A, kind, st);
+    hipError_t e = launch_fill_u32(A.flags, 0, sh.G, st);
+    if (e != hipSuccess) return e;
+    return launch_plain(A, kind, st);
+}
+
+abm_status plain_setup(abm_plan_s* pl)
+{
+    PlainShape sh{};
+    abm_status st = plain_shape(pl->shape[0], pl->ctx->n_cu, &sh);
+    if (st != ABM_OK) return st;
+    pl->plain_single = sh.single;
+    pl->plain_G = sh.G;
+    pl->plain_nloc = sh.nloc;
+    if (sh.single) return ABM_OK;
+    st = dev_alloc((void**)&pl->part, plain_part_doubles(sh.G) * sizeof(double), "plain partials");
+    if (st == ABM_OK) st = dev_alloc((void**)&pl->flags, sh.G * sizeof(uint32_t), "plain flags");
     return st;
 }
 

@@ -151,6 +151,26 @@ int env_int(const char* name, int dflt);
 abm_status dev_alloc(void** p, size_t bytes, const char* what);
 void dev_free(void* p);
 
+// Launch shape of the plain path for one problem: the one-workgroup form, or
+// G cooperative workgroups holding nloc history chunks each.
+struct PlainShape {
+    bool single;
+    int G;
+    int nloc;
+};
+// Weight tables of each component (all the same unless orders differ).
+struct PlainTables {
+    const double* b[4];
+    const double* a[4];
+    const double* c[4];
+    const double* gam[4];
+    double alpha[4];
+};
+abm_status plain_shape(const abm_problem& p, int n_cu, PlainShape* out);
+PlainArgs plain_args(const abm_problem& prob, const PlainTables& T, const PlainShape& sh,
+                     double* part, uint32_t* flags, uint32_t* status, double* y_out);
+// flags reset (cooperative form) and the kernel, on st
+hipError_t plain_enqueue(const PlainArgs& A, const PlainShape& sh, int kind, hipStream_t st);
 abm_status plain_setup(abm_plan_s* pl);
 abm_status batch_setup(abm_plan_s* pl);
 void batch_teardown(abm_plan_s* pl);

@@ -219,6 +219,14 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
             if (!ok) {
                 raise_status(A.status, kStatusTimeout);
                 s_abort = 1;
+                // the run is incomplete: its final state reads NaN
+                if (g == 0 && lane == 0) {
+                    const int64_t last = A.out_stride == 0
+                                             ? 0
+                                             : N / A.out_stride + (N % A.out_stride ? 1 : 0);
+#pragma unroll
+                    for (int i = 0; i < D; ++i) A.y_out[last * D + i] = __builtin_nan("");
+                }
             } else {
                 // predictor / corrector (eq. abm and the corrector after it),
                 // from the start term x0 (+ t x1 for orders above 1)
