@@ -306,6 +306,35 @@ def plain_leg(abm, torch, inputs, ctx):
     res["linear_test"] = {"workload": "D^0.8 y = -y, y0 = 1, h = 2^-10, N = 8192, one trajectory",
                           "plain_us_per_step": times["plain"] / p0.N * 1e6,
                           "blocked_us_per_step": times["blocked"] / p0.N * 1e6}
+    res["double_double"] = dd_leg(abm, torch, inputs, ctx,
+                                  {"linear_N8192": (p0, times["plain"]),
+                                   "oscillator_N200000": (p1, dt1)})
+    return res
+
+
+def dd_leg(abm, torch, inputs, ctx, cases):
+    """The double-double mode (the counterpart of the paper's long-double
+    runs) on the plain path's workloads: median of 3 after a warm-up, and its
+    cost over the double plain path on the same problem."""
+    res = {}
+    for name, (p, t_double) in cases.items():
+        q = inputs.Problem(p.rhs, p.alpha, p.h, p.N, p.x0, p.p, "dd", p.x1)
+        plan = abm.Plan(ctx, [q], out_stride=0)
+        y = abm.alloc_out(q, 0)
+        abm.solve(plan, q, y)
+        plan.check()
+        runs = []
+        for _ in range(3):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            abm.solve(plan, q, y)
+            torch.cuda.synchronize()
+            runs.append(time.perf_counter() - t0)
+        plan.check()
+        plan.close()
+        dt = float(np.median(runs))
+        res[name] = {"seconds": dt, "seconds_runs": runs, "us_per_step": dt / p.N * 1e6,
+                     "over_double_plain": dt / t_double}
     return res
 
 

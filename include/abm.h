@@ -71,8 +71,14 @@ enum abm_prec {
     ABM_FAR_FP32 = 1,   /* float products (MFMA f32), float accumulation per tile */
     ABM_FAR_BF16X3 = 2, /* two-term bf16 split (hi+lo) of both operands, 3 products */
     ABM_FAR_BF16X6 = 3, /* three-term bf16 split (hi+mid+lo), 6 products */
-    ABM_FAR_FP16X3 = 4  /* two-term fp16 split (hi+lo) of operands scaled by powers of two
+    ABM_FAR_FP16X3 = 4, /* two-term fp16 split (hi+lo) of operands scaled by powers of two
                            (history per 32 rows and column, weights per window), 3 products */
+    ABM_FAR_DD = 5      /* double-double (about 106 significant bits) for everything: weights,
+                           Gamma(alpha+1), Gamma(alpha+2), h^alpha, t_s, the right-hand side,
+                           history, sums and state -- the counterpart of the paper's
+                           long-double runs.  Plain path only (abm_plan with B = 1, abm_solve);
+                           y_out holds 2d doubles per state, the (hi, lo) pair of each
+                           component, value hi + lo */
 };
 
 typedef struct abm_problem {
@@ -235,7 +241,8 @@ abm_status abm_plan_graph(abm_plan_t *plan, int32_t enable);
 
 /* Copy the first n entries of the weight tables b_k, a_k, c_k (Section 2,
  * generated on the device by abm_plan) used by component 0 of problem idx of
- * the plan into host arrays of n doubles each (any of them may be NULL).
+ * the plan into host arrays of n doubles each (any of them may be NULL); a
+ * double-double plan (ABM_FAR_DD) copies n (hi, lo) pairs, 2n doubles each.
  * Synchronises the context's stream.  Errors: ABM_EINVAL (idx or n out of
  * range), ABM_EDEVICE. */
 abm_status abm_plan_weights(abm_plan_t *plan, int32_t idx, int64_t n, double *b, double *a,

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libabm.so")
 ABM_OK, ABM_EINVAL, ABM_ENOMEM, ABM_EDEVICE, ABM_EAGAIN, ABM_ENOENT, ABM_ECANCELED = \
     0, -1, -2, -3, -4, -5, -6
 RHS_ID = {"LINEAR": 0, "DUFFING": 1, "LORENZ": 2, "POLY": 3, "LCR": 4, "DIAG": 5}
-PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 4}
+PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 4, "dd": 5}
 
 EXPORTED = ("abm_ctx_create", "abm_ctx_destroy", "abm_plan", "abm_plan_destroy", "abm_plan_check",
             "abm_plan_weights", "abm_plan_timing", "abm_plan_graph", "abm_solve", "abm_solve_batch", "abm_submit", "abm_poll", "abm_cancel",
@@ -261,11 +261,13 @@ class Plan:
         _check(load().abm_plan_graph(self._h, 1 if enable else 0), "abm_plan_graph")
 
     def weights(self, idx: int, n: int):
-        """First n weights b, a, c of problem idx's table, as numpy arrays."""
+        """First n weights b, a, c of problem idx's table, as numpy arrays
+        ((n, 2) (hi, lo) pairs for a double-double plan)."""
         import numpy as np
-        b = np.zeros(n, np.float64)
-        a = np.zeros(n, np.float64)
-        c = np.zeros(n, np.float64)
+        shape = (n, 2) if self.problems[idx].far_prec == "dd" else (n,)
+        b = np.zeros(shape, np.float64)
+        a = np.zeros(shape, np.float64)
+        c = np.zeros(shape, np.float64)
         dp = ctypes.POINTER(ctypes.c_double)
         _check(load().abm_plan_weights(self._h, idx, n, b.ctypes.data_as(dp), a.ctypes.data_as(dp),
                                        c.ctypes.data_as(dp)), "abm_plan_weights")
@@ -287,9 +289,13 @@ class Plan:
 
 
 def alloc_out(problem: Problem, out_stride: int, device: str = "cuda"):
+    """Output buffer of a solve: (n_out, d) doubles, or (n_out, d, 2) (hi, lo)
+    pairs for a double-double problem."""
     import torch
-    return torch.zeros((n_out(problem.N, out_stride), problem.d), dtype=torch.float64,
-                       device=device)
+    shape = (n_out(problem.N, out_stride), problem.d)
+    if problem.far_prec == "dd":
+        shape = shape + (2,)
+    return torch.zeros(shape, dtype=torch.float64, device=device)
 
 
 def solve(plan: Plan, problem: Problem, y_out) -> None:

@@ -103,7 +103,7 @@ abm_status validate(const abm_problem& p, int idx)
         return fail(ABM_EINVAL, "problem %d: N=%lld outside [1, %lld]", idx, (long long)p.N,
                     (long long)kMaxSteps);
     if (p.out_stride < 0) return fail(ABM_EINVAL, "problem %d: out_stride < 0", idx);
-    if (p.far_prec < ABM_FAR_FP64 || p.far_prec > ABM_FAR_FP16X3)
+    if (p.far_prec < ABM_FAR_FP64 || p.far_prec > ABM_FAR_DD)
         return fail(ABM_EINVAL, "problem %d: unknown far_prec %d", idx, p.far_prec);
     for (int i = 0; i < d; ++i)
         if (!std::isfinite(p.x0[i])) return fail(ABM_EINVAL, "problem %d: x0 not finite", idx);
@@ -234,9 +234,14 @@ abm_status abm_plan_tuned(abm_ctx* ctx, const abm_problem* probs, int32_t B,
     }
     hipError_t e = hipSetDevice(ctx->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    bool dd = false;
+    for (int i = 0; i < B; ++i) dd |= probs[i].far_prec == ABM_FAR_DD;
+    if (dd && B != 1)
+        return fail(ABM_EINVAL, "double-double (ABM_FAR_DD) runs one trajectory per plan, on abm_solve");
     abm_plan_s* pl = new abm_plan_s();
     pl->ctx = ctx;
     pl->B = B;
+    pl->dd = dd;
     pl->shape.assign(probs, probs + B);
     if (tune) pl->tune = *tune;
     abm_status st = ABM_OK;
@@ -261,14 +266,17 @@ abm_status abm_plan_tuned(abm_ctx* ctx, const abm_problem* probs, int32_t B,
         for (int c = probs[i].d; c < 4; ++c) pl->table_of[(size_t)i * 4 + c] = pl->table_of[(size_t)i * 4];
     }
     for (auto& t : pl->tables) {
-        // padded so that block kernels may read a full tile past N
+        // padded so that block kernels may read a full tile past N; a
+        // double-double table holds (hi, lo) pairs
         const int64_t n = t.n + kWeightPad;
-        if ((st = dev_alloc((void**)&t.gam, 2 * sizeof(double), "weights")) ||
-            (st = dev_alloc((void**)&t.b, n * sizeof(double), "weights")) ||
-            (st = dev_alloc((void**)&t.a, n * sizeof(double), "weights")) ||
-            (st = dev_alloc((void**)&t.c, n * sizeof(double), "weights")))
+        const size_t w = dd ? 2 : 1;
+        if ((st = dev_alloc((void**)&t.gam, 2 * w * sizeof(double), "weights")) ||
+            (st = dev_alloc((void**)&t.b, w * n * sizeof(double), "weights")) ||
+            (st = dev_alloc((void**)&t.a, w * n * sizeof(double), "weights")) ||
+            (st = dev_alloc((void**)&t.c, w * n * sizeof(double), "weights")))
             break;
-        e = launch_weights(t.alpha, n, t.gam, t.b, t.a, t.c, ctx->stream);
+        e = dd ? launch_weights_dd(t.alpha, n, t.gam, t.b, t.a, t.c, ctx->stream)
+               : launch_weights(t.alpha, n, t.gam, t.b, t.a, t.c, ctx->stream);
         if (e != hipSuccess) {
             st = hip_fail(e, "weight kernel");
             break;
@@ -279,13 +287,16 @@ abm_status abm_plan_tuned(abm_ctx* ctx, const abm_problem* probs, int32_t B,
         e = launch_fill_u32(pl->status, 0, 1, ctx->stream);
         if (e != hipSuccess) st = hip_fail(e, "fill");
     }
-    if (st == ABM_OK && B == 1) {
+    if (st == ABM_OK && dd) {
+        // double-double: the plain path only, and it must fit
+        st = plain_setup_dd(pl);
+    } else if (st == ABM_OK && B == 1) {
         // the plain path is optional: a history too long for it leaves plain_G = 0
         const abm_status ps = plain_setup(pl);
         if (ps == ABM_ENOMEM || ps == ABM_EDEVICE) st = ps;
         if (ps != ABM_OK) pl->plain_error = abm_last_error();
     }
-    if (st == ABM_OK) st = batch_setup(pl);
+    if (st == ABM_OK && !dd) st = batch_setup(pl);
     if (st != ABM_OK) {
         abm_plan_destroy(pl);
         return st;
@@ -332,11 +343,12 @@ abm_status abm_plan_weights(abm_plan_t* pl, int32_t idx, int64_t n, double* b, d
     const WeightTable& t = pl->tables[pl->table_of[(size_t)idx * 4]];
     if (n < 0 || n > t.n + kWeightPad)
         return fail(ABM_EINVAL, "n=%lld outside [0, %lld]", (long long)n, (long long)(t.n + kWeightPad));
+    const size_t bytes = (pl->dd ? 2 : 1) * n * sizeof(double);
     hipError_t e = hipSetDevice(pl->ctx->device);
     if (e == hipSuccess) e = hipStreamSynchronize(pl->ctx->stream);
-    if (e == hipSuccess && b) e = hipMemcpy(b, t.b, n * sizeof(double), hipMemcpyDeviceToHost);
-    if (e == hipSuccess && a) e = hipMemcpy(a, t.a, n * sizeof(double), hipMemcpyDeviceToHost);
-    if (e == hipSuccess && c) e = hipMemcpy(c, t.c, n * sizeof(double), hipMemcpyDeviceToHost);
+    if (e == hipSuccess && b) e = hipMemcpy(b, t.b, bytes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && a) e = hipMemcpy(a, t.a, bytes, hipMemcpyDeviceToHost);
+    if (e == hipSuccess && c) e = hipMemcpy(c, t.c, bytes, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(e, "weight copy");
     return ABM_OK;
 }
@@ -363,7 +375,14 @@ abm_status abm_solve(abm_plan_t* pl, const abm_problem* prob, double* y_out)
     }
     const PlainShape sh{pl->plain_single, pl->plain_G, pl->plain_nloc};
     const PlainArgs A = plain_args(*prob, T, sh, pl->part, pl->flags, pl->status, y_out);
-    e = plain_enqueue(A, sh, chain_kind(prob->rhs, orders_differ(*prob)), pl->ctx->stream);
+    const int kind = chain_kind(prob->rhs, orders_differ(*prob));
+    if (pl->dd) {
+        if (!sh.single && (e = launch_fill_u32(A.flags, 0, sh.G, pl->ctx->stream)) != hipSuccess)
+            return hip_fail(e, "flag reset");
+        e = launch_plain_dd(A, sh.single, kind, pl->ctx->stream);
+    } else {
+        e = plain_enqueue(A, sh, kind, pl->ctx->stream);
+    }
     if (e != hipSuccess) return hip_fail(e, "plain kernel launch");
     return ABM_OK;
 }
@@ -434,6 +453,37 @@ hipError_t plain_enqueue(const PlainArgs& A, const PlainShape& sh, int kind, hip
     hipError_t e = launch_fill_u32(A.flags, 0, sh.G, st);
     if (e != hipSuccess) return e;
     return launch_plain(A, kind, st);
+}
+
+abm_status plain_setup_dd(abm_plan_s* pl)
+{
+    const abm_problem& p = pl->shape[0];
+    const int tables = orders_differ(p) ? p.d : 1;
+    int G = env_int("ABM_PLAIN_G", 0);
+    if (G <= 0 && plain_dd_single_fits(p.N, p.d, tables)) {
+        pl->plain_single = true;
+        pl->plain_G = 1;
+        pl->plain_nloc = 0;
+        return ABM_OK;
+    }
+    const int ch = plain_chunk();
+    const int64_t nchunks = std::max<int64_t>(1, (p.N + ch - 1) / ch);
+    const int nloc_max = plain_dd_max_local_chunks(p.d);
+    const int gcap = std::min(pl->ctx->n_cu, 256);
+    const int gmin = (int)((nchunks + nloc_max - 1) / nloc_max);
+    if (gmin > gcap)
+        return fail(ABM_EINVAL, "N=%lld too long for the double-double plain path (history does not "
+                    "fit the LDS of %d workgroups)", (long long)p.N, gcap);
+    // four local chunks per workgroup: the double-double sums are costly
+    if (G <= 0) G = (int)((nchunks + 3) / 4);
+    G = std::min(std::max(G, gmin), gcap);
+    pl->plain_single = false;
+    pl->plain_G = G;
+    pl->plain_nloc = (int)((nchunks + G - 1) / G);
+    abm_status st = dev_alloc((void**)&pl->part, plain_dd_part_doubles(G) * sizeof(double),
+                              "plain partials");
+    if (st == ABM_OK) st = dev_alloc((void**)&pl->flags, G * sizeof(uint32_t), "plain flags");
+    return st;
 }
 
 abm_status plain_setup(abm_plan_s* pl)

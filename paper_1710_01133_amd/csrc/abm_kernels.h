@@ -59,6 +59,18 @@ hipError_t launch_plain(const PlainArgs& A, int kind, hipStream_t st);
 bool plain_single_fits(int64_t N, int d, int tables);
 hipError_t launch_plain_single(const PlainArgs& A, int kind, hipStream_t st);
 
+// ---- K0 / K1 in double-double (ABM_FAR_DD) -----------------------------------
+// Tables of (hi, lo) pairs: gam holds Gamma(alpha+1), Gamma(alpha+2) (4 doubles),
+// b, a, c 2n doubles each; PlainArgs pointers refer to such pairs and y_out
+// receives 2d doubles per state.
+hipError_t launch_weights_dd(double alpha, int64_t n, double* gam, double* b, double* a, double* c,
+                             hipStream_t st);
+bool plain_dd_single_fits(int64_t N, int d, int tables);
+int plain_dd_max_local_chunks(int d);
+int plain_dd_part_doubles(int G);
+// single: the one-workgroup form; otherwise A.G cooperative workgroups (flags zero)
+hipError_t launch_plain_dd(const PlainArgs& A, bool single, int kind, hipStream_t st);
+
 // ---- blocked method: groups and work items --------------------------------
 // A group is a set of trajectories sharing their orders (one weight table, or
 // one per component), one right-hand side and one far-field precision; their

@@ -100,6 +100,8 @@ struct abm_plan_s {
     int plain_G = 0;
     int plain_nloc = 0;
     bool plain_single = false;    // the one-workgroup form (short histories)
+    bool dd = false;              // double-double plan (ABM_FAR_DD): plain path only, tables
+                                  // of (hi, lo) pairs
     std::string plain_error;
     double* part = nullptr;
     uint32_t* flags = nullptr;
@@ -172,6 +174,7 @@ PlainArgs plain_args(const abm_problem& prob, const PlainTables& T, const PlainS
 // flags reset (cooperative form) and the kernel, on st
 hipError_t plain_enqueue(const PlainArgs& A, const PlainShape& sh, int kind, hipStream_t st);
 abm_status plain_setup(abm_plan_s* pl);
+abm_status plain_setup_dd(abm_plan_s* pl);
 abm_status batch_setup(abm_plan_s* pl);
 void batch_teardown(abm_plan_s* pl);
 void free_reduced(WeightTable& t);

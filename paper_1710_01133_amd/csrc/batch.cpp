@@ -688,6 +688,7 @@ extern "C" abm_status abm_solve_batch(abm_plan_t* pl, const abm_problem* probs, 
                                       double* const* y_out, abm_stats* stats)
 {
     if (!pl || !probs || !y_out) return fail(ABM_EINVAL, "NULL argument");
+    if (pl->dd) return fail(ABM_EINVAL, "a double-double plan runs on abm_solve only");
     if (B != pl->B) return fail(ABM_EINVAL, "B=%d but the plan was made for %d problems", B, pl->B);
     for (int i = 0; i < B; ++i) {
         abm_status s = validate(probs[i], i);

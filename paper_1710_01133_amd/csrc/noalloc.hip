@@ -82,6 +82,8 @@ extern "C" abm_status abm_solve_noalloc(const abm_problem* prob, double* y_out, 
     if (!prob || !y_out) return fail(ABM_EINVAL, "NULL argument");
     abm_status s = validate(*prob, 0);
     if (s != ABM_OK) return s;
+    if (prob->far_prec == ABM_FAR_DD)
+        return fail(ABM_EINVAL, "double-double (ABM_FAR_DD) runs on abm_solve only");
     const size_t need = noalloc_bytes_needed(*prob);
     if (need > kScratchBytes)
         return fail(ABM_EINVAL,

@@ -731,6 +731,8 @@ abm_status abm_submit(abm_ctx* ctx, const abm_problem* prob, double* y_out, uint
     if (!ctx || !prob || !y_out || !ticket) return fail(ABM_EINVAL, "NULL argument");
     abm_status s = validate(*prob, 0);
     if (s) return s;
+    if (prob->far_prec == ABM_FAR_DD)
+        return fail(ABM_EINVAL, "double-double (ABM_FAR_DD) runs on abm_solve only");
     ServeState* S = ctx->serve;   // made with the context, fixed until it is destroyed
     int L = 0, kchunk = 0;
     if ((s = serve_params(&L, &kchunk))) return s;
@@ -766,6 +768,8 @@ abm_status abm_request_bytes(abm_ctx* ctx, const abm_problem* prob, size_t* byte
     if (!ctx || !prob || !bytes) return fail(ABM_EINVAL, "NULL argument");
     abm_status s = validate(*prob, 0);
     if (s) return s;
+    if (prob->far_prec == ABM_FAR_DD)
+        return fail(ABM_EINVAL, "double-double (ABM_FAR_DD) is not served");
     int L = 0, kchunk = 0;
     if ((s = serve_params(&L, &kchunk))) return s;
     *bytes = layout_of(*prob, L, kchunk, ctx->serve->max_split).total;

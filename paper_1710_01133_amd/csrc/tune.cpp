@@ -96,6 +96,8 @@ extern "C" abm_status abm_autotune(abm_ctx* ctx, const abm_problem* probs, int32
     for (int i = 0; i < B; ++i) {
         abm_status s = validate(probs[i], i);
         if (s) return s;
+        if (probs[i].far_prec == ABM_FAR_DD)
+            return fail(ABM_EINVAL, "problem %d: double-double runs on abm_solve, nothing to tune", i);
         all_fp64 &= probs[i].far_prec == ABM_FAR_FP64;
     }
     hipError_t e = hipSetDevice(ctx->device);
