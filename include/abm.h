@@ -64,8 +64,10 @@ enum abm_rhs {
 
 /* Precision of the far-field history products of abm_solve_batch.  The near
  * band, the weight generation and the predictor/corrector state are always
- * double.  Reduced modes round F and the weights once to the stated type,
- * accumulate in float inside one K-tile and add tile partials in double. */
+ * double.  Reduced floating-point modes round F and the weights once to the
+ * stated type, accumulate in float inside one K-tile and add tile partials in
+ * double; the integer mode accumulates exactly and adds per-block partials in
+ * double. */
 enum abm_prec {
     ABM_FAR_FP64 = 0,   /* double products, double accumulation */
     ABM_FAR_FP32 = 1,   /* float products (MFMA f32), float accumulation per tile */
@@ -73,12 +75,19 @@ enum abm_prec {
     ABM_FAR_BF16X6 = 3, /* three-term bf16 split (hi+mid+lo), 6 products */
     ABM_FAR_FP16X3 = 4, /* two-term fp16 split (hi+lo) of operands scaled by powers of two
                            (history per 32 rows and column, weights per window), 3 products */
-    ABM_FAR_DD = 5      /* double-double (about 106 significant bits) for everything: weights,
+    ABM_FAR_DD = 5,     /* double-double (about 106 significant bits) for everything: weights,
                            Gamma(alpha+1), Gamma(alpha+2), h^alpha, t_s, the right-hand side,
                            history, sums and state -- the counterpart of the paper's
                            long-double runs.  Plain path only (abm_plan with B = 1, abm_solve);
                            y_out holds 2d doubles per state, the (hi, lo) pair of each
                            component, value hi + lo */
+    ABM_FAR_I8 = 6      /* integer limbs on the int8 matrix cores: each weight window scaled by
+                           a power of two and cut into four balanced base-256 int8 digits (30
+                           bits), the history per block of L rows and column into three (22
+                           bits); the nine digit products whose weight is at least 2^-24 of
+                           the leading one, summed exactly in int32 over each block of history
+                           rows and converted to double once per block.  Block lengths 128 and
+                           256 only */
 };
 
 typedef struct abm_problem {

@@ -21,7 +21,7 @@ LIB_PATH = os.path.join(_HERE, "libabm.so")
 ABM_OK, ABM_EINVAL, ABM_ENOMEM, ABM_EDEVICE, ABM_EAGAIN, ABM_ENOENT, ABM_ECANCELED = \
     0, -1, -2, -3, -4, -5, -6
 RHS_ID = {"LINEAR": 0, "DUFFING": 1, "LORENZ": 2, "POLY": 3, "LCR": 4, "DIAG": 5}
-PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 4, "dd": 5}
+PREC_ID = {"fp64": 0, "fp32": 1, "bf16x3": 2, "bf16x6": 3, "fp16x3": 4, "dd": 5, "i8x9": 6}
 
 EXPORTED = ("abm_ctx_create", "abm_ctx_destroy", "abm_plan", "abm_plan_destroy", "abm_plan_check",
             "abm_plan_weights", "abm_plan_timing", "abm_plan_graph", "abm_solve", "abm_solve_batch", "abm_submit", "abm_poll", "abm_cancel",

@@ -103,7 +103,7 @@ abm_status validate(const abm_problem& p, int idx)
         return fail(ABM_EINVAL, "problem %d: N=%lld outside [1, %lld]", idx, (long long)p.N,
                     (long long)kMaxSteps);
     if (p.out_stride < 0) return fail(ABM_EINVAL, "problem %d: out_stride < 0", idx);
-    if (p.far_prec < ABM_FAR_FP64 || p.far_prec > ABM_FAR_DD)
+    if (p.far_prec < ABM_FAR_FP64 || p.far_prec > ABM_FAR_I8)
         return fail(ABM_EINVAL, "problem %d: unknown far_prec %d", idx, p.far_prec);
     for (int i = 0; i < d; ++i)
         if (!std::isfinite(p.x0[i])) return fail(ABM_EINVAL, "problem %d: x0 not finite", idx);

@@ -159,6 +159,14 @@ __device__ __forceinline__ int64_t kblocked_index(int64_t k, int64_t col, int64_
     return (((k - 1) >> 3) * ld + col) * 8 + ((k - 1) & 7);
 }
 
+// Index of history row k >= 1, column col, in the layout of the int8 history
+// limbs: 16 consecutive rows of one column are contiguous (one 16-byte operand
+// of the int8 matrix product).
+__device__ __forceinline__ int64_t q16_index(int64_t k, int64_t col, int64_t ld)
+{
+    return (((k - 1) >> 4) * ld + col) * 16 + ((k - 1) & 15);
+}
+
 // Index of history row k, column col, in the column-blocked layout of the
 // float history copy: 16 columns form a block and each block stores its rows
 // contiguously (rows * 16 floats), so a far-field workgroup reading one block

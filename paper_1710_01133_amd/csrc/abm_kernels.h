@@ -3,6 +3,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "abm.h"
+
 namespace abm {
 
 // ---- K0: weight tables ---------------------------------------------------
@@ -113,6 +115,10 @@ struct GroupDev {
     uint16_t* Fh[3];       // bf16 (or fp16) split terms of the history, k-blocked (kblocked_index)
     float* Fsc;            // fp16 split: 2^-e of the scaling of rows 32g+1 .. 32g+32 of
                            // column c at [g * ldF + c] (null otherwise)
+    int8_t* Fq[3];         // int8 limbs of the history (far_prec i8): digit i of row k,
+                           // column c at q16_index(k, c, ldF)
+    double* Fqs;           // int8 limbs: 2^-e of the scaling of block g (rows gL+1 ..
+                           // gL+L) of column c at [g * ldF + c]
     int64_t ldF;           // padded columns
     int64_t rows;          // history rows allocated
     double* accn;          // [member][2][d][L] sums carried into the next block
@@ -172,18 +178,27 @@ int far_split_bound(int64_t kfar_max, int kchunk, int max_split);
 hipError_t launch_far(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
                       int max_nsplit, int kchunk, int L, int cls, hipStream_t st);
 size_t far_lp_lds_bytes(int L, int kchunk, int prec);
+// Integer-limb far field (far_prec i8): LDS bytes, launch (L = 128 or 256).
+size_t far_i8_lds_bytes(int L, int kchunk);
+int far_i8_tile_cols();
+hipError_t launch_far_i8(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
+                         int max_nsplit, int kchunk, int L, hipStream_t st);
 hipError_t launch_far_lp(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
                          int max_nsplit, int kchunk, int L, int prec, hipStream_t st);
 hipError_t allow_lds(const void* fn, size_t bytes);   // dynamic LDS above 64 KiB
 
-// Far-field launch classes: 0..4 the Toeplitz kernels by precision (abm_prec),
-// 5 and 6 the blocked convolution of narrow groups in double and float.
-constexpr int kFarClasses = 7;
+// Far-field launch classes: 0..6 the Toeplitz kernels by precision (abm_prec;
+// 5, double-double, never reaches the blocked path), 7 and 8 the blocked
+// convolution of narrow groups in double and float.
+constexpr int kFarClasses = 9;
 inline int far_class(int prec, bool narrow)
 {
-    return narrow ? (prec == 0 ? 5 : 6) : prec;
+    return narrow ? (prec == 0 ? 7 : 8) : prec;
 }
-inline bool is_narrow_class(int cls) { return cls >= 5; }
+inline bool is_narrow_class(int cls) { return cls >= 7; }
+// Precisions of the blocked path (abm_prec values a batch may use).
+constexpr int kBlockedPrecs[6] = {ABM_FAR_FP64, ABM_FAR_FP32, ABM_FAR_BF16X3, ABM_FAR_BF16X6,
+                                  ABM_FAR_FP16X3, ABM_FAR_I8};
 // Blocked convolution (narrow groups, fp64 / fp32 far field): product tiles
 // of a block for cols columns, whether a group qualifies, its split plan over
 // the K + L - 16 rows of shifts and the bound of that plan's slice count.

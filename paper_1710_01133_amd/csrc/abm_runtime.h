@@ -58,6 +58,8 @@ struct Group {
     float* F32 = nullptr;
     uint16_t* Fh[3] = {nullptr, nullptr, nullptr};
     float* Fsc = nullptr;
+    int8_t* Fq[3] = {nullptr, nullptr, nullptr};
+    double* Fqs = nullptr;
     TrajDesc* traj_dev = nullptr;   // members' descriptors (device)
     double* accn = nullptr;         // sums carried into the next block [member][2][d][L]
     double* part[2] = {nullptr, nullptr};   // far partials by block parity

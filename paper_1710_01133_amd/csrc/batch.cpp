@@ -50,6 +50,8 @@ void free_group(Group& g)
     dev_free(g.F32);
     for (int i = 0; i < 3; ++i) dev_free(g.Fh[i]);
     dev_free(g.Fsc);
+    for (int i = 0; i < 3; ++i) dev_free(g.Fq[i]);
+    dev_free(g.Fqs);
     dev_free(g.traj_dev);
     dev_free(g.accn);
     dev_free(g.part[0]);
@@ -137,6 +139,15 @@ abm_status alloc_group(Group& g, int L, int nsplit_max, hipStream_t st)
             if ((s = dev_alloc((void**)&g.Fsc, sb, "history scales"))) return s;
             if ((e = hipMemsetAsync(g.Fsc, 0, sb, st)) != hipSuccess) return hip_fail(e, "clear");
         }
+    } else if (g.prec == ABM_FAR_I8) {
+        const size_t bytes = (size_t)((g.rows + 15) / 16) * g.ldF * 16;
+        for (int i = 0; i < 3; ++i) {
+            if ((s = dev_alloc((void**)&g.Fq[i], bytes, "int8 history"))) return s;
+            if ((e = hipMemsetAsync(g.Fq[i], 0, bytes, st)) != hipSuccess) return hip_fail(e, "clear");
+        }
+        const size_t sb = (size_t)(g.rows / L + 1) * g.ldF * sizeof(double);
+        if ((s = dev_alloc((void**)&g.Fqs, sb, "history scales"))) return s;
+        if ((e = hipMemsetAsync(g.Fqs, 0, sb, st)) != hipSuccess) return hip_fail(e, "clear");
     }
     if ((s = dev_alloc((void**)&g.traj_dev, nm * sizeof(TrajDesc), "descriptors"))) return s;
     if ((s = dev_alloc((void**)&g.accn, nm * 2 * g.d * L * sizeof(double), "carried sums"))) return s;
@@ -170,6 +181,8 @@ GroupDev group_dev(const Group& g, const WeightTable* const W[4])
     }
     for (int i = 0; i < 3; ++i) d.Fh[i] = g.Fh[i];
     d.Fsc = g.Fsc;
+    for (int i = 0; i < 3; ++i) d.Fq[i] = g.Fq[i];
+    d.Fqs = g.Fqs;
     d.F = g.F;
     d.F32 = g.F32;
     d.ldF = g.ldF;
@@ -294,14 +307,17 @@ abm_status choose_blocking(abm_plan_s* pl, const abm_problem* probs, int B)
     const abm_tuning& T = pl->tune;
     int L = T.block_L ? T.block_L : env_int("ABM_BLOCK_L", 256);
     if (!valid_L(L)) return fail(ABM_EINVAL, "block length %d not in {64,128,256,512}", L);
-    for (int i = 0; i < B; ++i)
+    for (int i = 0; i < B; ++i) {
         if (probs[i].far_prec != ABM_FAR_FP64 && L < 128)
             return fail(ABM_EINVAL, "problem %d: reduced-precision far field needs block length >= 128", i);
+        if (probs[i].far_prec == ABM_FAR_I8 && L > 256)
+            return fail(ABM_EINVAL, "problem %d: the int8 far field needs block length 128 or 256", i);
+    }
     int kchunk = T.kchunk ? T.kchunk : env_int("ABM_KCHUNK", 2048);
     if (kchunk < 512 || kchunk % 512 || kchunk > (1 << 20))
         return fail(ABM_EINVAL, "history chunk %d must be a multiple of 512 (at most 2^20)", kchunk);
     // largest chunk whose LDS footprint fits every precision used
-    for (int prec = 0; prec <= ABM_FAR_FP16X3; ++prec)
+    for (int prec : kBlockedPrecs)
         while (kchunk > 512 && far_lds_bytes(L, kchunk, prec) > kMaxLds) kchunk -= 512;
     pl->L = L;
     pl->kchunk = kchunk;

@@ -39,6 +39,8 @@ struct ChainArgs {
     gptr<uint16_t> Fmid;
     gptr<uint16_t> Flo;
     gptr<float> Fsc;       // non-null: fp16 split (Fhi, Fmid) with per-32-row scales
+    gptr<int8_t> Fq[3];    // non-null: int8 limbs of the history, one scale per block
+    gptr<double> Fqs;
     int64_t ldF;
     int64_t rows;
     bool narrow;           // F32 time-major [k][ldF] instead of column-blocked
@@ -67,6 +69,9 @@ __device__ __forceinline__ void chain_view(const GroupDev& G, const ChainItem& i
     A.Fmid = as_global(G.Fh[1]);
     A.Flo = as_global(G.Fh[2]);
     A.Fsc = as_global(G.Fsc);
+#pragma unroll
+    for (int i = 0; i < 3; ++i) A.Fq[i] = as_global(G.Fq[i]);
+    A.Fqs = as_global(G.Fqs);
     A.ldF = G.ldF;
     A.rows = G.rows;
     A.narrow = G.narrow != 0;
@@ -102,6 +107,51 @@ __device__ __forceinline__ int f16_exponent(double m)
     (void)frexp(m, &ex);                       // m = f 2^ex, 0.5 <= f < 1
     int e = 14 - ex;
     return e < -100 ? -100 : (e > 100 ? 100 : e);
+}
+
+// Exponent of the int8 limbs of the history: the rows of block m of a column
+// are stored as f 2^e.  The previous block's exponent (prev, from its
+// recorded scale) is kept while the block's largest |f| times 2^prev lies in
+// [32, 127) -- as many digits as a fresh scale gives, which puts that largest
+// |f| in [32, 64) -- so that the far field can sum consecutive blocks exactly
+// without converting in between (e = 0 for an all-zero or non-finite block).
+__device__ __forceinline__ int q8_exponent(double m, double prev_scale)
+{
+    if (!(m > 0.0) || !isfinite(m)) return 0;
+    if (prev_scale > 0.0) {
+        int pe;
+        (void)frexp(prev_scale, &pe);          // prev_scale = 2^-prev = 0.5 * 2^pe
+        const double x = ldexp(m, 1 - pe);
+        if (x >= 32.0 && x < 127.0) return 1 - pe;
+    }
+    int ex;
+    (void)frexp(m, &ex);
+    return 6 - ex;
+}
+
+// Row s of component i as three balanced base-256 digits of f 2^e at
+// resolution 2^-16 (|f 2^e| < 127: |d0| <= 127, d1, d2 in [-128, 127]); the
+// block's first row records the scale 2^-e.
+template <int D>
+__device__ __forceinline__ void store_history_q8(const ChainArgs& A, const TrajDesc& T, int64_t s,
+                                                 int64_t block, bool first, const double* fs,
+                                                 const int* q8e)
+{
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        const int64_t col = comp_col(T, i);
+        const double x = ldexp(fs[i], q8e[i] + 16);
+        int64_t I = isfinite(x) ? (int64_t)rint(x) : 0;
+        const int64_t d2 = ((I + 128) & 255) - 128;
+        I = (I - d2) >> 8;
+        const int64_t d1 = ((I + 128) & 255) - 128;
+        const int64_t d0 = (I - d1) >> 8;
+        const int64_t at = q16_index(s, col, A.ldF);
+        A.Fq[0][at] = (int8_t)d0;
+        A.Fq[1][at] = (int8_t)d1;
+        A.Fq[2][at] = (int8_t)d2;
+        if (first) A.Fqs[block * A.ldF + col] = ldexp(1.0, -q8e[i]);
+    }
 }
 
 template <int D>
@@ -190,6 +240,11 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
     const int64_t mL = A.mL;
     if (mL >= T.N) return;
     const int rows = (int)((T.N - mL) < L ? (T.N - mL) : L);
+    // int8 limbs: the previous block's history scales (read now, used at the end)
+    double q8prev[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i)
+        q8prev[i] = (A.Fq[0] && mL >= L) ? A.Fqs[(mL / L - 1) * A.ldF + comp_col(T, i)] : 0.0;
     const bool more = T.N > mL + L;           // a next block follows
 
     double x0[D], x1[D], F0[D], p[8];
@@ -406,6 +461,22 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
             f16e[i] = f16_exponent(m);
         }
     }
+    // int8 limbs: one scale per block and column (the whole wave's rows)
+    int q8e[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) q8e[i] = 0;
+    if (A.Fq[0]) {
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            double m = 0.0;
+#pragma unroll
+            for (int q = 0; q < Q; ++q)
+                if (r0 + q < rows) m = fmax(m, fabs(myF[q][i]));
+#pragma unroll
+            for (int x = 1; x < kWave; x <<= 1) m = fmax(m, __shfl_xor(m, x, kWave));
+            q8e[i] = q8_exponent(m, q8prev[i]);
+        }
+    }
     // history rows, reduced copies and output states of this lane's rows
     bool bad = false;
 #pragma unroll
@@ -414,6 +485,7 @@ __device__ __forceinline__ void chain_block(const GroupDev& G, const ChainItem& 
         if (r < rows) {
             const int64_t s = mL + r + 1;
             store_history<D>(A, T, s, myF[q], f16e);
+            if (A.Fq[0]) store_history_q8<D>(A, T, s, mL / L, r == 0, myF[q], q8e);
             store_output<D>(T, s, myY[q]);
 #pragma unroll
             for (int i = 0; i < D; ++i) bad |= !isfinite(myY[q][i]);

@@ -174,6 +174,7 @@ hipError_t launch_t(const GroupDev* groups, const FarItem* items, int n, int max
 
 int far_tile_cols(int L, int prec)
 {
+    if (prec == ABM_FAR_I8) return far_i8_tile_cols();
     if (prec != ABM_FAR_FP64) return 16;
     switch (L) {
     case 64: return 128;
@@ -188,6 +189,7 @@ int far_stage_rows() { return kKS; }
 
 size_t far_lds_bytes(int L, int kchunk, int prec)
 {
+    if (prec == ABM_FAR_I8) return far_i8_lds_bytes(L, kchunk);
     if (prec != ABM_FAR_FP64) return far_lp_lds_bytes(L, kchunk, prec);
     return (2 * (size_t)(L + kchunk) + 2 * kKS * far_tile_cols(L, prec)) * sizeof(double);
 }
@@ -229,6 +231,7 @@ hipError_t launch_far(const GroupDev* groups, const FarItem* items, int n, int m
     if (cls == far_class(ABM_FAR_FP64, true) || cls == far_class(ABM_FAR_FP32, true))
         return launch_far_hankel(groups, items, n, max_coltiles, max_nsplit, L,
                                  cls == far_class(ABM_FAR_FP64, true) ? ABM_FAR_FP64 : ABM_FAR_FP32, st);
+    if (cls == ABM_FAR_I8) return launch_far_i8(groups, items, n, max_coltiles, max_nsplit, kchunk, L, st);
     if (cls != ABM_FAR_FP64)
         return launch_far_lp(groups, items, n, max_coltiles, max_nsplit, kchunk, L, cls, st);
     switch (L) {

@@ -23,19 +23,39 @@ struct FarArgs {
     int32_t kchunk;
     int32_t nchunks;
     int32_t chunks_per_split;
+    gptr<const int8_t> Fq[3];  // int8 limbs of the history (q16_index layout)
+    gptr<const double> Fqs;    // int8 limbs: per-block scales of the history
     gptr<double> part;
     int64_t ldP;
 };
 
-// Fills A for work item blockIdx.z; false when this workgroup lies beyond the
-// item's column tiles or history splits (the launch grid covers the largest
-// item).
-__device__ __forceinline__ bool far_view(const GroupDev* __restrict__ groups,
-                                         const FarItem* __restrict__ items, int kchunk, int L,
-                                         FarArgs& A)
+// History rows k_lo .. k_hi-1 of one chunk of a far item and the window of
+// weight indices jb .. jb+wlen-1 its products read (block rows r = 0..L-1).
+struct ChunkBounds {
+    int64_t k_lo, k_hi, jb;
+    int nk, wlen;
+};
+
+__device__ __forceinline__ ChunkBounds chunk_bounds(const FarArgs& A, int L, int chunk)
 {
-    const FarItem it = items[blockIdx.z];
-    if ((int)blockIdx.x >= it.ncoltiles || (int)blockIdx.y >= it.nsplit) return false;
+    ChunkBounds c;
+    c.k_lo = 1 + (int64_t)chunk * A.kchunk;
+    c.k_hi = c.k_lo + A.kchunk;
+    if (c.k_hi > A.kfar + 1) c.k_hi = A.kfar + 1;
+    c.nk = (int)(c.k_hi - c.k_lo);
+    c.jb = A.mL - c.k_hi + 1;
+    c.wlen = L + c.nk - 1;
+    return c;
+}
+
+// Fills A for work item `item`; false when column tile `tile` or history split
+// `split` lies beyond the item's (the launch grid covers the largest item).
+__device__ __forceinline__ bool far_view_at(const GroupDev* __restrict__ groups,
+                                            const FarItem* __restrict__ items, int item, int tile,
+                                            int split, int kchunk, int L, FarArgs& A)
+{
+    const FarItem it = items[item];
+    if (tile >= it.ncoltiles || split >= it.nsplit) return false;
     const GroupDev& G = groups[it.group];
     const CompWeights& W = G.w[it.comp];
     A.b = as_global(W.b);
@@ -53,6 +73,10 @@ __device__ __forceinline__ bool far_view(const GroupDev* __restrict__ groups,
         A.Fh[i] = G.Fh[i] ? as_global((const uint16_t*)G.Fh[i]) + coff * 8 : nullptr;
     }
     A.Fsc = G.Fsc ? as_global((const float*)G.Fsc) + coff : nullptr;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+        A.Fq[i] = G.Fq[i] ? as_global((const int8_t*)G.Fq[i]) + coff * 16 : nullptr;
+    A.Fqs = G.Fqs ? as_global((const double*)G.Fqs) + coff : nullptr;
     A.F = as_global((const double*)G.F) + coff;
     A.F32 = G.F32 ? as_global((const float*)G.F32) + (coff >> 4) * G.rows * 16 : nullptr;
     A.ldF = G.ldF;
@@ -65,6 +89,15 @@ __device__ __forceinline__ bool far_view(const GroupDev* __restrict__ groups,
     A.part = as_global(G.part[(it.mL / L) & 1]) + coff * (2 * L);
     A.ldP = it.ldP;
     return true;
+}
+
+// The view of workgroup (blockIdx.x = column tile, blockIdx.y = split,
+// blockIdx.z = item).
+__device__ __forceinline__ bool far_view(const GroupDev* __restrict__ groups,
+                                         const FarItem* __restrict__ items, int kchunk, int L,
+                                         FarArgs& A)
+{
+    return far_view_at(groups, items, blockIdx.z, blockIdx.x, blockIdx.y, kchunk, L, A);
 }
 
 }  // namespace abm

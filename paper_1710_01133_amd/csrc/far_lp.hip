@@ -44,23 +44,6 @@ typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef unsigned u4 __attribute__((ext_vector_type(4)));
 
-struct ChunkBounds {
-    int64_t k_lo, k_hi, jb;
-    int nk, wlen;
-};
-
-__device__ __forceinline__ ChunkBounds chunk_bounds(const FarArgs& A, int L, int chunk)
-{
-    ChunkBounds c;
-    c.k_lo = 1 + (int64_t)chunk * A.kchunk;
-    c.k_hi = c.k_lo + A.kchunk;
-    if (c.k_hi > A.kfar + 1) c.k_hi = A.kfar + 1;
-    c.nk = (int)(c.k_hi - c.k_lo);
-    c.jb = A.mL - c.k_hi + 1;
-    c.wlen = L + c.nk - 1;
-    return c;
-}
-
 template <int MT, int NT>
 __device__ __forceinline__ void flush_acc(f4 (&acc)[MT][NT], d4 (&acc64)[MT][NT])
 {

@@ -166,7 +166,7 @@ struct ReqLayout {
     TableLayout tab[4];
     int ntab;
     int tab_of[4];                    // table of each component
-    size_t F, F32, Fh[3], Fsc, traj, accn, part, status, total;
+    size_t F, F32, Fh[3], Fsc, Fq[3], Fqs, traj, accn, part, status, total;
     int64_t wn, rows, ldF, ldC;
     size_t part_half;
     bool narrow, per_comp;
@@ -210,7 +210,7 @@ ReqLayout layout_of(const abm_problem& p, int L, int kchunk, int max_split)
         if (p.far_prec == ABM_FAR_FP32 || p.far_prec == ABM_FAR_FP16X3) {
             T.b32 = take(r.wn * sizeof(float));
             T.a32 = take(r.wn * sizeof(float));
-        } else if (p.far_prec != ABM_FAR_FP64) {
+        } else if (p.far_prec == ABM_FAR_BF16X3 || p.far_prec == ABM_FAR_BF16X6) {
             for (int i = 0; i < 3; ++i) {
                 T.bh[i] = take(r.wn * sizeof(uint16_t));
                 T.ah[i] = take(r.wn * sizeof(uint16_t));
@@ -228,6 +228,12 @@ ReqLayout layout_of(const abm_problem& p, int L, int kchunk, int max_split)
         for (int i = 0; i < terms; ++i)
             r.Fh[i] = take((size_t)((r.rows + 7) / 8) * r.ldF * 8 * sizeof(uint16_t));
         if (p.far_prec == ABM_FAR_FP16X3) r.Fsc = take((size_t)(r.rows / 32 + 1) * r.ldF * sizeof(float));
+    }
+    for (int i = 0; i < 3; ++i) r.Fq[i] = 0;
+    r.Fqs = 0;
+    if (p.far_prec == ABM_FAR_I8) {
+        for (int i = 0; i < 3; ++i) r.Fq[i] = take((size_t)((r.rows + 15) / 16) * r.ldF * 16);
+        r.Fqs = take((size_t)(r.rows / L + 1) * r.ldF * sizeof(double));
     }
     r.traj = take(sizeof(TrajDesc));
     r.accn = take((size_t)2 * p.d * L * sizeof(double));
@@ -260,7 +266,7 @@ abm_status serve_params(int* L, int* kchunk)
     if (*L != 128 && *L != 256 && *L != 512)
         return fail(ABM_EINVAL, "ABM_SERVE_BLOCK_L must be 128, 256 or 512");
     *kchunk = 2048;
-    for (int prec = 0; prec <= ABM_FAR_FP16X3; ++prec)
+    for (int prec : kBlockedPrecs)
         while (*kchunk > 512 && far_lds_bytes(*L, *kchunk, prec) > kMaxLds) *kchunk -= 512;
     return ABM_OK;
 }
@@ -342,6 +348,8 @@ abm_status admit(ServeState* S, Request* r, size_t off, const ReqLayout& lay)
     g.F32 = lay.F32 ? (float*)(base + lay.F32) : nullptr;
     for (int i = 0; i < 3; ++i) g.Fh[i] = lay.Fh[i] ? (uint16_t*)(base + lay.Fh[i]) : nullptr;
     g.Fsc = lay.Fsc ? (float*)(base + lay.Fsc) : nullptr;
+    for (int i = 0; i < 3; ++i) g.Fq[i] = lay.Fq[i] ? (int8_t*)(base + lay.Fq[i]) : nullptr;
+    g.Fqs = lay.Fqs ? (double*)(base + lay.Fqs) : nullptr;
     g.traj_dev = (TrajDesc*)(base + lay.traj);
     g.accn = (double*)(base + lay.accn);
     g.part_half = lay.part_half;
@@ -736,6 +744,8 @@ abm_status abm_submit(abm_ctx* ctx, const abm_problem* prob, double* y_out, uint
     ServeState* S = ctx->serve;   // made with the context, fixed until it is destroyed
     int L = 0, kchunk = 0;
     if ((s = serve_params(&L, &kchunk))) return s;
+    if (prob->far_prec == ABM_FAR_I8 && L > 256)
+        return fail(ABM_EINVAL, "the int8 far field needs block length 128 or 256 (ABM_SERVE_BLOCK_L=%d)", L);
     const ReqLayout lay = layout_of(*prob, L, kchunk, S->max_split);
     if (lay.total > ctx->arena_bytes)
         return fail(ABM_ENOMEM, "request needs %zu bytes, the arena has %zu", lay.total,
@@ -772,6 +782,8 @@ abm_status abm_request_bytes(abm_ctx* ctx, const abm_problem* prob, size_t* byte
         return fail(ABM_EINVAL, "double-double (ABM_FAR_DD) is not served");
     int L = 0, kchunk = 0;
     if ((s = serve_params(&L, &kchunk))) return s;
+    if (prob->far_prec == ABM_FAR_I8 && L > 256)
+        return fail(ABM_EINVAL, "the int8 far field needs block length 128 or 256 (ABM_SERVE_BLOCK_L=%d)", L);
     *bytes = layout_of(*prob, L, kchunk, ctx->serve->max_split).total;
     return ABM_OK;
 }

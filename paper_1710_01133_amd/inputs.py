@@ -48,7 +48,7 @@ class Problem:
     N: int                        # number of steps
     x0: Tuple[float, ...]         # initial state, length d
     p: Tuple[float, ...] = field(default_factory=tuple)   # rhs parameters
-    far_prec: str = "fp64"        # far-field precision: fp64 | fp32 | bf16x3 | bf16x6 | fp16x3 | dd
+    far_prec: str = "fp64"        # far-field precision: fp64 | fp32 | bf16x3 | bf16x6 | fp16x3 | i8x9 | dd
     x1: Optional[Tuple[float, ...]] = None   # y'(0), for components of order above 1
 
     @property

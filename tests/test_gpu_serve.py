@@ -50,7 +50,8 @@ def _mix(prec="fp64", n=8, seed=3):
     return probs
 
 
-@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("fp32", 1e-6), ("fp16x3", 1e-6)])
+@pytest.mark.parametrize("prec,tol", [("fp64", TOL_FP64), ("fp32", 1e-6), ("fp16x3", 1e-6),
+                                      ("i8x9", 2e-7)])
 def test_served_results_match_oracle(torch_ready, prec, tol):
     ctx = abm.Context(0, arena_bytes=256 << 20)
     probs = _mix(prec)
