@@ -49,7 +49,7 @@ DEFAULT_PREC = "i8x9"
 
 def far_source_sha():
     h = hashlib.sha256()
-    for f in ("far.hip", "far_lp.hip", "far_common.h"):
+    for f in ("far.hip", "far_lp.hip", "far_i8.hip", "far_common.h"):
         with open(os.path.join(ROOT, "paper_1710_01133_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
