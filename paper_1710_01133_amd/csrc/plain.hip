@@ -9,22 +9,28 @@
 //     LDS, so every workgroup holds an equal share of the history at every
 //     step (the paper's static contiguous slices would leave most of them
 //     idle early in the run);
-//   * per step every work thread sums b_{n-k} f_k and a_{n-k} f_k over its
-//     indices; the weights were loaded into registers during the previous
-//     step's synchronisation (they depend only on n - k), so no global load
-//     waits on the step's dependent path;
-//   * a fifth wave reduces the work waves' partials (DPP row operations, then
-//     LDS), publishes the workgroup's 2d sums and raises its step flag (the
-//     all-reduce of Algorithm 1), waits for all G flags, adds the G partials
-//     in a fixed order and takes the predictor/corrector update itself,
-//     bit-identically in every workgroup (every process computes the update,
-//     as in Algorithm 1); the owner of index s keeps f_s in its LDS slice.
-//     The work waves never wait on that wave's flag traffic, and it issues no
-//     weight loads, so its memory fences never wait on theirs;
-//   * with G = 1 there is nothing to publish: the step is two barriers.
-// Partial slots are double-buffered by step parity: a workgroup can only
-// overwrite slot s+2 after every workgroup has published s+1, which each does
-// after reading slot s.
+//   * the all-reduce of Algorithm 1 is pipelined by two steps: during step s
+//     every work thread sums b_{s+1-k} f_k and a_{s+1-k} f_k over its indices
+//     k <= s-1 -- step s+2's sums without their two newest terms, which need
+//     nothing that steps s and s+1 compute; the weights were loaded into
+//     registers during the previous step (they depend only on s - k), so no
+//     global load waits on a step's dependent path;
+//   * meanwhile a fifth wave waits for all G flags of step s (raised right
+//     after step s-2, so they have had a whole step to arrive), adds the G
+//     partials in a fixed order and the two newest terms b_1 f_{s-2} +
+//     b_0 f_{s-1} (a_1 f_{s-2} + a_0 f_{s-1}) from the rows it keeps, and
+//     takes the predictor/corrector update itself, bit-identically in every
+//     workgroup (every process computes the update, as in Algorithm 1); the
+//     owner of index s keeps f_s in its LDS slice;
+//   * one barrier per step; after it work wave 0 reduces the work waves'
+//     partials (DPP row operations, then LDS), publishes the workgroup's 2d
+//     sums of step s+2 and raises its flag to s+2;
+//   * with G = 1 there is nothing to publish: the fifth wave reads the work
+//     waves' partials of step s from LDS, written during step s-2.
+// Partial slots (in LDS and in global memory) are kept by step mod 4: a
+// workgroup writes step m's slot after step m-2, when its fifth wave has seen
+// every flag reach m-2; a workgroup raises its flag to m-2 after step m-4,
+// whose reads of the slot that m now reuses came before that.
 #include "abm_dev.h"
 #include "abm_kernels.h"
 
@@ -75,7 +81,7 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
 {
     extern __shared__ double sm[];
     double* Fl = sm;                                   // [nloc][256][D] history slice
-    double* red = sm + (size_t)A.nloc * kCh * D;       // [4][2D] work-wave partials
+    double* red = sm + (size_t)A.nloc * kCh * D;       // [4][4][2D] work-wave partials by step mod 4
     __shared__ int s_abort;
     constexpr int NW = PC ? D : 1;                     // weight tables in use
     constexpr int NLR = NL > 0 ? NL : 1;
@@ -114,14 +120,21 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
         }
     }
 
-    // weights b_{n-k}, a_{n-k} of this thread's indices k for step n + 1
-    // (index clamped at 0 where k > n: those are not used)
+    // Step s's history sums in two parts (Algorithm 1's all-reduce pipelined
+    // by two steps): the slice sums over every index but the two newest
+    // (k <= s-3) are computed during step s-2 and published right after it,
+    // so they have a whole step to reach the other workgroups; the two newest
+    // terms, b_1 f_{s-2} + b_0 f_{s-1} (and a_1 f_{s-2} + a_0 f_{s-1}), are
+    // added by the synchronising wave, which holds f_{s-2} and f_{s-1} from its
+    // own (redundant) updates.
+    // Weights b_{m-k}, a_{m-k} of this thread's indices k for the slice sums
+    // of step m+1 (index clamped at 0 where k > m: those are not used).
     double wb[NLR][NW], wa[NLR][NW];
-    auto fetch = [&](int64_t n) {
+    auto fetch = [&](int64_t m) {
 #pragma unroll
         for (int l = 0; l < NL; ++l) {
             const int64_t k = (int64_t)(g + l * G) * kCh + t;
-            const int64_t idx = n - k < 0 ? 0 : n - k;
+            const int64_t idx = m - k < 0 ? 0 : m - k;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
                 wb[l][w] = bw[w][idx];
@@ -129,75 +142,48 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
             }
         }
     };
-    double cn[NW];                                     // c_n of the coming step (sync wave)
+    // synchronising wave: c_n of the coming step, b_0, b_1, a_0, a_1, and the
+    // two newest history rows f_{s-1}, f_{s-2}
+    double cn[NW], b01[2][NW], a01[2][NW];
+    double Fm1[D], Fm2[D];
     if (!sync_wave) {
-        if constexpr (NL > 0) fetch(0);
+        if constexpr (NL > 0) fetch(2);
     } else {
 #pragma unroll
-        for (int w = 0; w < NW; ++w) cn[w] = cw[w][0];
+        for (int w = 0; w < NW; ++w) {
+            cn[w] = cw[w][0];
+#pragma unroll
+            for (int j = 0; j < 2; ++j) {
+                b01[j][w] = bw[w][j];
+                a01[j][w] = aw[w][j];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            Fm1[i] = F0[i];
+            Fm2[i] = 0.0;
+        }
     }
     __syncthreads();
 
     for (int64_t s = 1; s <= N; ++s) {
         const int64_t n = s - 1;
-        if (!sync_wave) {
-            double P[D], C[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) P[i] = C[i] = 0.0;
-            if constexpr (NL > 0) {
-#pragma unroll
-                for (int l = 0; l < NL; ++l) {
-                    const int64_t k = (int64_t)(g + l * G) * kCh + t;
-                    if (l < nloc && k <= n) {
-                        const double* f = Fl + ((size_t)l * kCh + t) * D;
-#pragma unroll
-                        for (int i = 0; i < D; ++i) {
-                            const double fa = k >= 1 ? f[i] : 0.0;   // k = 0 enters through c_n
-                            P[i] = fma(wb[l][PC ? i : 0], f[i], P[i]);
-                            C[i] = fma(wa[l][PC ? i : 0], fa, C[i]);
-                        }
-                    }
-                }
-                fetch(n + 1);      // in flight while the step is reduced and synchronised
-            } else {
-                for (int l = 0; l < nloc; ++l) {
-                    const int64_t k = (int64_t)(g + l * G) * kCh + t;
-                    if (k > n) break;               // later local chunks lie further out
-                    const double* f = Fl + ((size_t)l * kCh + t) * D;
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        const int w = PC ? i : 0;
-                        P[i] = fma(bw[w][n - k], f[i], P[i]);
-                        C[i] = fma((k >= 1) ? aw[w][n - k] : 0.0, f[i], C[i]);
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                const double ps = wave_sum_dpp(P[i]);
-                const double cs = wave_sum_dpp(C[i]);
-                if (lane == 0) {
-                    red[wid * 2 * D + i] = ps;
-                    red[wid * 2 * D + D + i] = cs;
-                }
-            }
-        }
-        __syncthreads();                           // work-wave partials are in LDS
+        // work-wave partials of step m in LDS slot m mod 4: written during
+        // step m-2, read during step m (a single workgroup) or published
+        // right after step m-2 (several)
         if (sync_wave) {
             double tot[2 * D];
-#pragma unroll
-            for (int j = 0; j < 2 * D; ++j)
-                tot[j] = ((red[j] + red[2 * D + j]) + red[4 * D + j]) + red[6 * D + j];
             bool ok = true;
-            if (G > 1) {
-                double* slot_base = A.part + (size_t)(s & 1) * G * kPartStride;
-                if (lane == 0) {
-                    double* slot = slot_base + (size_t)g * kPartStride;
+            if (s <= 2) {
 #pragma unroll
-                    for (int j = 0; j < 2 * D; ++j) slot[j] = tot[j];
-                    st_release(&A.flags[g], (uint32_t)s);
-                }
-                // wait until every workgroup has published step s
+                for (int j = 0; j < 2 * D; ++j) tot[j] = 0.0;   // no history before f_{s-2}
+            } else if (G == 1) {
+                const double* rr = red + (size_t)(s & 3) * kWorkWaves * 2 * D;
+#pragma unroll
+                for (int j = 0; j < 2 * D; ++j)
+                    tot[j] = ((rr[j] + rr[2 * D + j]) + rr[4 * D + j]) + rr[6 * D + j];
+            } else {
+                // wait until every workgroup has published step s (after step s-2)
                 for (int q = lane; q < G; q += kWave) {
                     uint32_t spins = 0;
                     while (ld_relaxed(&A.flags[q]) < (uint32_t)s) {
@@ -208,11 +194,16 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
                         spin_pause();
                     }
                 }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                // the partials are read with device-coherent loads issued after
+                // every flag load has returned s: each writer's release made its
+                // partials visible before its flag, so no acquire fence (which
+                // would invalidate this XCD's L2 every step) is needed
+                const double* slot_base = A.part + (size_t)(s & 3) * G * kPartStride;
 #pragma unroll
                 for (int j = 0; j < 2 * D; ++j) {
                     double acc = 0.0;
-                    for (int q = lane; q < G; q += kWave) acc += slot_base[(size_t)q * kPartStride + j];
+                    for (int q = lane; q < G; q += kWave)
+                        acc += ld_relaxed(&slot_base[(size_t)q * kPartStride + j]);
                     tot[j] = wave_sum_dpp(acc);
                 }
             }
@@ -228,6 +219,16 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
                     for (int i = 0; i < D; ++i) A.y_out[last * D + i] = __builtin_nan("");
                 }
             } else {
+                // the two newest terms: k = n-1 (b_1, a_1 for k >= 1) and
+                // k = n (b_0, a_0 for k >= 1); the k = 0 corrector term is c_n f_0
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const int w = PC ? i : 0;
+                    if (n >= 1) tot[i] = fma(b01[1][w], Fm2[i], tot[i]);
+                    tot[i] = fma(b01[0][w], Fm1[i], tot[i]);
+                    if (n >= 2) tot[D + i] = fma(a01[1][w], Fm2[i], tot[D + i]);
+                    if (n >= 1) tot[D + i] = fma(a01[0][w], Fm1[i], tot[D + i]);
+                }
                 // predictor / corrector (eq. abm and the corrector after it),
                 // from the start term x0 (+ t x1 for orders above 1)
                 const double td = (double)s * A.h;
@@ -242,6 +243,11 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
                 for (int i = 0; i < D; ++i)
                     y[i] = base[i] + ha[i] * ((tot[D + i] + cn[PC ? i : 0] * F0[i]) + fP[i] / g2[i]);
                 rhs_eval<R, D>(A.p, td, y, fs);
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    Fm2[i] = Fm1[i];
+                    Fm1[i] = fs[i];
+                }
                 if (s < N) {
 #pragma unroll
                     for (int w = 0; w < NW; ++w) cn[w] = cw[w][s];   // c_n of the next step
@@ -275,16 +281,71 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
                     }
                 }
             }
+        } else if (s + 2 <= N) {
+            // slice sums of step s+2 over this thread's indices k <= s-1:
+            // b_{s+1-k} f_k and, for k >= 1, a_{s+1-k} f_k
+            double* rw = red + (size_t)((s + 2) & 3) * kWorkWaves * 2 * D;
+            double P[D], C[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) P[i] = C[i] = 0.0;
+            if constexpr (NL > 0) {
+#pragma unroll
+                for (int l = 0; l < NL; ++l) {
+                    const int64_t k = (int64_t)(g + l * G) * kCh + t;
+                    if (l < nloc && k <= n) {
+                        const double* f = Fl + ((size_t)l * kCh + t) * D;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            const double fa = k >= 1 ? f[i] : 0.0;   // k = 0 enters through c_n
+                            P[i] = fma(wb[l][PC ? i : 0], f[i], P[i]);
+                            C[i] = fma(wa[l][PC ? i : 0], fa, C[i]);
+                        }
+                    }
+                }
+                fetch(s + 2);      // in flight while the step is synchronised
+            } else {
+                for (int l = 0; l < nloc; ++l) {
+                    const int64_t k = (int64_t)(g + l * G) * kCh + t;
+                    if (k > n) break;               // later local chunks lie further out
+                    const double* f = Fl + ((size_t)l * kCh + t) * D;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        const int w = PC ? i : 0;
+                        P[i] = fma(bw[w][s + 1 - k], f[i], P[i]);
+                        C[i] = fma((k >= 1) ? aw[w][s + 1 - k] : 0.0, f[i], C[i]);
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const double ps = wave_sum_dpp(P[i]);
+                const double cs = wave_sum_dpp(C[i]);
+                if (lane == 0) {
+                    rw[wid * 2 * D + i] = ps;
+                    rw[wid * 2 * D + D + i] = cs;
+                }
+            }
         }
-        __syncthreads();                           // f_s stored, partials consumed
+        // f_s is stored and step s+2's work-wave partials are in LDS
+        __syncthreads();
         if (s_abort) return;
+        // work wave 0 publishes the workgroup's slice sums of step s+2 and
+        // raises its flag to s+2 (slots by step mod 4)
+        if (G > 1 && t == 0 && s + 2 <= N) {
+            const double* rw = red + (size_t)((s + 2) & 3) * kWorkWaves * 2 * D;
+            double* slot = A.part + ((size_t)((s + 2) & 3) * G + g) * kPartStride;
+#pragma unroll
+            for (int j = 0; j < 2 * D; ++j)
+                slot[j] = ((rw[j] + rw[2 * D + j]) + rw[4 * D + j]) + rw[6 * D + j];
+            st_release(&A.flags[g], (uint32_t)(s + 2));
+        }
     }
 }
 
 template <int R, int D, bool PC, int NL>
 hipError_t launch_plain_nl(const PlainArgs& A, hipStream_t st)
 {
-    const size_t shmem = ((size_t)A.nloc * kCh * D + kWorkWaves * 2 * D) * sizeof(double);
+    const size_t shmem = ((size_t)A.nloc * kCh * D + 4 * kWorkWaves * 2 * D) * sizeof(double);
     const void* fn = reinterpret_cast<const void*>(&k_plain<R, D, PC, NL>);
     hipError_t e = allow_lds(fn, shmem);
     if (e != hipSuccess) return e;
@@ -526,14 +587,14 @@ hipError_t launch_single_t(const PlainArgs& A, hipStream_t st)
 int plain_max_local_chunks(int d)
 {
     // the CU's whole LDS (one workgroup per CU): history slice + wave partials
-    return (int)((kPlainLds - 4 * 2 * d * sizeof(double)) / ((size_t)kCh * d * sizeof(double)));
+    return (int)((kPlainLds - 4 * kWorkWaves * 2 * d * sizeof(double)) / ((size_t)kCh * d * sizeof(double)));
 }
 
 int plain_chunk() { return kCh; }
 
 int plain_prefetch_chunks(int tables) { return kMaxPrefetch / tables; }
 
-int plain_part_doubles(int G) { return 2 * G * kPartStride; }
+int plain_part_doubles(int G) { return 4 * G * kPartStride; }
 
 bool plain_single_fits(int64_t N, int d, int tables)
 {
