@@ -120,16 +120,22 @@ __global__ __launch_bounds__(256, 2) void k_far_i8_32(const GroupDev* groups, co
     constexpr int NK = ROWS / L > 1 ? ROWS / L : 1;          // row kinds per workgroup
     constexpr int QS = kQ32Stage / 32;          // K-steps per stage
     constexpr int GSTEPS = L / 32;              // K-steps per history block
-    const int sub = KW > 1 ? (int)blockIdx.x % KW : 0;
+    // blockIdx.x = sub * (column tiles of the grid) + tile: the predictor and
+    // corrector workgroups of one column tile are a multiple of 8 apart in
+    // dispatch order (the grid's tile count is a multiple of 8), so they land
+    // on the same XCD and the second reads the tile's history from that L2
+    const int ntg = (int)gridDim.x / KW;
+    const int sub = KW > 1 ? (int)blockIdx.x / ntg : 0;
+    const int tile = KW > 1 ? (int)blockIdx.x % ntg : (int)blockIdx.x;
     FarArgs A;
-    if (!far_view_at(groups, items, blockIdx.z, blockIdx.x / KW, blockIdx.y, kchunk, L, A)) return;
+    if (!far_view_at(groups, items, blockIdx.z, tile, blockIdx.y, kchunk, L, A)) return;
     extern __shared__ __attribute__((aligned(16))) int8_t smq[];
     const int win = L + A.kchunk + cpad;
     int8_t* wq = smq;                           // [kind of the workgroup][limb][copy][win]
     u4* Bst = reinterpret_cast<u4*>(smq + NK * kWLimbs * kCopies * win);   // [2][kQ32StageU4]
 
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    const int col0 = (blockIdx.x / KW) * TN;
+    const int col0 = tile * TN;
     const int rowbase = sub * ROWS + wid * 64;  // first of this wave's 64 rows in 0..2L
     const int kind = rowbase / L;               // 0: predictor (b), 1: corrector (a)
     const int wk = NK > 1 ? kind : 0;           // the kind's window in this workgroup
@@ -297,7 +303,8 @@ hipError_t launch_i8_32_t(const GroupDev* groups, const FarItem* items, int n, i
     hipError_t e = allow_lds(reinterpret_cast<const void*>(&k_far_i8_32<L>), shmem);
     if (e != hipSuccess) return e;
     constexpr int KW = 2 * L / 256;
-    hipLaunchKernelGGL((k_far_i8_32<L>), dim3((unsigned)(max_coltiles * KW), (unsigned)max_nsplit, (unsigned)n),
+    const int ntg = (max_coltiles + 7) / 8 * 8;     // tile count of the grid: a multiple of 8
+    hipLaunchKernelGGL((k_far_i8_32<L>), dim3((unsigned)(ntg * KW), (unsigned)max_nsplit, (unsigned)n),
                        dim3(256), shmem, st, groups, items, kchunk, kCopyPad);
     return hipGetLastError();
 }
