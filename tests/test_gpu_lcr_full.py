@@ -1,13 +1,14 @@
 """The paper's own workload at full length: the forced fractional LCR circuit
 (eq. sys.LRC; sigma = 1.015, omega = 0.55, a = -1.02, b = -0.58) swept over
 its forcing F in [0, 0.2], B = 1024, N = 65536 (t = 653), with commensurate
-(0.9, 0.9) and incommensurate (0.9, 0.8) orders, in double and in the
-benchmark's fp16x3 far field, at the launch shapes the benchmark times.
+(0.9, 0.9) and incommensurate (0.9, 0.8) orders, in double, in the
+benchmark's int8-limb far field (i8x9) and in the fp16x3 far field, at the
+launch shapes the benchmark times.
 
 Chaos at some F makes a whole-trajectory comparison with the oracle
 ill-posed beyond t ~ 36, so sampled steps are recomputed by the oracle from
 the GPU's own states (gpu_common.recompute_errors): the double far field
-within its rounding bound, the fp16x3 far field within 1e-6 of the state's
+within its rounding bound, the reduced far fields within 1e-6 of the state's
 scale per step.  The Poincare-section output the benchmark writes (every
 1142nd state) is checked to be exactly those states of the full run."""
 import numpy as np
@@ -42,7 +43,7 @@ def _solve(ctx, probs, stride, tuning):
     return ys
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp16x3"])
+@pytest.mark.parametrize("prec", ["fp64", "i8x9", "fp16x3"])
 @pytest.mark.parametrize("alpha", [(0.9, 0.9), (0.9, 0.8)], ids=["0.9-0.9", "0.9-0.8"])
 def test_lcr_sweep_full_length(ctx, alpha, prec):
     probs = inputs.lcr_sweep(alpha=alpha, far_prec=prec)
