@@ -112,9 +112,11 @@ __device__ __forceinline__ int f16_exponent(double m)
 // Exponent of the int8 limbs of the history: the rows of block m of a column
 // are stored as f 2^e.  The previous block's exponent (prev, from its
 // recorded scale) is kept while the block's largest |f| times 2^prev lies in
-// [32, 127) -- as many digits as a fresh scale gives, which puts that largest
-// |f| in [32, 64) -- so that the far field can sum consecutive blocks exactly
-// without converting in between (e = 0 for an all-zero or non-finite block).
+// [16, 127) -- at most one bit below what a fresh scale gives, which puts that
+// largest |f| in [32, 64) -- so that the far field can sum consecutive blocks
+// exactly without converting in between (e = 0 for an all-zero or non-finite
+// block).  A column tile's scales then change at a few percent of the block
+// boundaries instead of about one in six with the band [32, 127).
 __device__ __forceinline__ int q8_exponent(double m, double prev_scale)
 {
     if (!(m > 0.0) || !isfinite(m)) return 0;
@@ -122,7 +124,7 @@ __device__ __forceinline__ int q8_exponent(double m, double prev_scale)
         int pe;
         (void)frexp(prev_scale, &pe);          // prev_scale = 2^-prev = 0.5 * 2^pe
         const double x = ldexp(m, 1 - pe);
-        if (x >= 32.0 && x < 127.0) return 1 - pe;
+        if (x >= 16.0 && x < 127.0) return 1 - pe;
     }
     int ex;
     (void)frexp(m, &ex);

@@ -9,7 +9,8 @@
 // [-128, 127] (30 bits).  The history is scaled per block of L rows and
 // column and cut into three digits e0 + e1 2^-8 + e2 2^-16 at resolution
 // 2^-16 with |e0| <= 127 (written by the chain, chain.hip, which keeps a
-// column's scale from one block to the next while its values fit).  A
+// column's scale from one block to the next while the block's largest |f|
+// stays within [16, 127) of it).  A
 // product w F is then
 //   2^-(ew+ef) sum_{i,j} d_i e_j 2^-8(i+j),
 // and the nine digit products with i + j <= 3 are kept (the dropped ones
@@ -20,11 +21,11 @@
 // 3 * 2^14 per row, and a chunk is at most 4608 rows, far below 2^31).  When
 // a column's history scale changes, and at the end of each chunk, the four
 // levels are combined in double (exactly: every partial is a multiple of
-// 2^-24 below 2^27) and added, scaled, into the double accumulator.  Weights need more
-// digits than the history: a rounding error of a weight repeats in every
-// step that uses it, while the history's errors do not line up, so 30 bits of
-// weights and 22 of history keep the whole sweep near 5e-8 where 22 bits of
-// weights alone give about 1e-6.
+// 2^-24 below 2^27) and added, scaled, into the double accumulator.  Weights
+// need more digits than the history: a rounding error of a weight repeats in
+// every step that uses it, while the history's errors do not line up, so 30
+// bits of weights and 21-22 of history keep the whole sweep near 8e-8 where
+// 22 bits of weights alone give about 1e-6.
 //
 // Tiling: v_mfma_i32_32x32x32_i8, row tiles of 32 rows and 32 columns,
 // K-steps of 32 history rows.  Lane (li = lane%32, g = lane/32) supplies row
@@ -32,16 +33,19 @@
 // same rows of the B fragment; result row 8(v/4) + 4g + v%4, column li sits in
 // register v.  The Toeplitz A fragment of row tile t at K-step q starts at
 // byte L-1-rbase-li+16g + 32(q - t) of the reversed weight window, so
-// fragment(t, q) = fragment(t+1, q+1): one new fragment per limb and step
-// (kept in a two-slot ring for limbs 0 and 1; limbs 2 and 3, in three of the
-// nine products, are read where they are used).  The window is held in four
-// copies shifted by 0..3 bytes; each lane reads the copy that makes its
-// fragments dword-aligned, and the copies lie 8 dwords apart modulo the 32
-// LDS banks so that the lanes reading one dword offset in the four copies hit
-// different banks.  Each wave holds 2 row tiles (64 rows x 32 columns), a
-// workgroup 4 waves (256 rows: the predictor or the corrector rows of a
-// block at L = 256, both at L = 128) within 256 registers per lane, so two
-// workgroups -- or one beside a chain workgroup -- share a CU.
+// fragment(t, q) = fragment(t+1, q+1): one new fragment per limb and step.
+// The fragments of step q + 1 (four weight limbs, three history limbs) are
+// read from the LDS while step q's 18 products run, one read issued after
+// each of the first eleven products.  The window is held in four copies
+// shifted by 0..3 bytes; each lane reads the copy that makes its fragments
+// dword-aligned, and the copies lie 8 dwords apart modulo the 32 LDS banks so
+// that the lanes reading one dword offset in the four copies hit different
+// banks.  Each wave holds 2 row tiles (64 rows x 32 columns), a workgroup 4
+// waves (256 rows: the predictor or the corrector rows of a block at L = 256,
+// both at L = 128).  Registers hold the exact level sums and two steps of
+// fragments (256 per lane); the double sums between flushes live in a
+// per-wave LDS region.  A workgroup's ~125 KB of LDS leaves room for one
+// chain workgroup (32 KB) beside it on a CU.
 #include "far_common.h"
 
 namespace abm {
@@ -76,10 +80,15 @@ __device__ __forceinline__ void weight_digits(double w, int e, int (&d)[kWLimbs]
     d[0] = (int)I;
 }
 
-// History stages: two buffers of 128 rows x 32 columns x 3 limbs, copied
-// global -> LDS by DMA (q32_dma_stage).
+// History stages: kStageBufs buffers of 128 rows x 32 columns x 3 limbs,
+// copied global -> LDS by DMA (q32_dma_stage) kStageBufs - 1 stages ahead.
+#ifndef I8_NBUF
+#define I8_NBUF 2
+#endif
+constexpr int kStageBufs = I8_NBUF;
 constexpr int kQ32Stage = 128;                               // history rows per LDS stage
 constexpr int kQ32StageU4 = 3 * (kQ32Stage / 16) * 32;       // 16-byte units per stage
+constexpr int kDmaPerStage = kQ32StageU4 / 256;              // copies per thread and stage (256 threads)
 
 template <int NTH>
 __device__ __forceinline__ void q32_dma_stage(gptr<const int8_t> q0, gptr<const int8_t> q1,
@@ -120,6 +129,7 @@ __global__ __launch_bounds__(256, 2) void k_far_i8_32(const GroupDev* groups, co
     constexpr int NK = ROWS / L > 1 ? ROWS / L : 1;          // row kinds per workgroup
     constexpr int QS = kQ32Stage / 32;          // K-steps per stage
     constexpr int GSTEPS = L / 32;              // K-steps per history block
+    static_assert(kQ32StageU4 == kDmaPerStage * NTH, "each thread issues kDmaPerStage copies per stage");
     // blockIdx.x = sub * (column tiles of the grid) + tile: the predictor and
     // corrector workgroups of one column tile are a multiple of 8 apart in
     // dispatch order (the grid's tile count is a multiple of 8), so they land
@@ -132,7 +142,7 @@ __global__ __launch_bounds__(256, 2) void k_far_i8_32(const GroupDev* groups, co
     extern __shared__ __attribute__((aligned(16))) int8_t smq[];
     const int win = L + A.kchunk + cpad;
     int8_t* wq = smq;                           // [kind of the workgroup][limb][copy][win]
-    u4* Bst = reinterpret_cast<u4*>(smq + NK * kWLimbs * kCopies * win);   // [2][kQ32StageU4]
+    u4* Bst = reinterpret_cast<u4*>(smq + NK * kWLimbs * kCopies * win);   // [kStageBufs][kQ32StageU4]
 
     const int t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const int col0 = tile * TN;
@@ -152,14 +162,24 @@ __global__ __launch_bounds__(256, 2) void k_far_i8_32(const GroupDev* groups, co
         return __builtin_bit_cast(i4, x);
     };
 
-    double acc64[MT][16];
-#pragma unroll
-    for (int i = 0; i < MT; ++i)
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc64[i][v] = 0.0;
     const gptr<const int8_t> q0 = A.Fq[0], q1 = A.Fq[1], q2 = A.Fq[2];
     // the workgroup's kinds: kind0 .. kind0 + NK - 1
     const int kind0 = (sub * ROWS) / L;
+    // FFpart[split][col][2L]: row 8(v/4) + 4g + v%4 of column li of tile i in
+    // register v.
+    const gptr<double> out = A.part + (size_t)blockIdx.y * A.ldP * (2 * L) + (size_t)(col0 + li) * (2 * L) +
+                             rowbase + 4 * g;
+    // The double sums of this wave's 64 x 32 outputs between flushes (a
+    // history scale change or a chunk's end): values v, v + 1 of tile i of
+    // lane `lane` at accs[(8 i + v/2) * 64 + lane], one LDS region per wave
+    // (registers hold the exact level sums and the fragments of two K-steps).
+    // The split's last flush writes FFpart instead.
+    double2* accs = reinterpret_cast<double2*>(smq + NK * kWLimbs * kCopies * win + kStageBufs * kQ32StageU4 * 16) +
+                    wid * (MT * 8 * 64);
+    bool first = true;
+    auto bfrag = [&](const u4* Bs, int qq, int j) -> i4 {
+        return __builtin_bit_cast(i4, Bs[(j * (kQ32Stage / 16) + 2 * qq + g) * TN + li]);
+    };
 
     const int c_begin = blockIdx.y * A.chunks_per_split;
     int c_end = c_begin + A.chunks_per_split;
@@ -167,6 +187,7 @@ __global__ __launch_bounds__(256, 2) void k_far_i8_32(const GroupDev* groups, co
     for (int chunk = c_begin; chunk < c_end; ++chunk) {
         const ChunkBounds cb = chunk_bounds(A, L, chunk);
         const int64_t kb16 = (cb.k_lo - 1) >> 4;
+        const int nstages = cb.nk / kQ32Stage;
         __syncthreads();   // previous chunk's readers are done with the LDS
         int ew[2];
         ew[0] = i8_exponent(fmax(fabs(A.b[cb.jb]), fabs(A.b[cb.jb + cb.wlen - 1])));
@@ -200,48 +221,53 @@ __global__ __launch_bounds__(256, 2) void k_far_i8_32(const GroupDev* groups, co
                 }
             }
         }
-        q32_dma_stage<NTH>(q0, q1, q2, A.ldF, col0, kb16, t, Bst);
+        for (int s0 = 0; s0 < kStageBufs - 1 && s0 < nstages; ++s0)
+            q32_dma_stage<NTH>(q0, q1, q2, A.ldF, col0, kb16 + (int64_t)s0 * (kQ32Stage / 16), t,
+                               Bst + s0 * kQ32StageU4);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
-        // ring[l][slot] (limbs 0, 1): fragment v in slot v mod 2; start with
-        // v = -1, 0.  Limbs 2 and 3 (in three of the nine products) are read
-        // where they are used, which keeps the wave within 256 registers.
-        constexpr int RL = 2;
-        i4 ring[RL][MT];
+        // Fragments of K-step q: aC[l] = window fragment v = q (row tile 0),
+        // aP[l] = v = q - 1 (row tile 1), bC[j] the history's; those of step
+        // q + 1 are read from the LDS while step q's products run.
+        i4 aP[kWLimbs], aC[kWLimbs], bC[kFLimbs];
 #pragma unroll
-        for (int l = 0; l < RL; ++l) {
-            ring[l][0] = afrag(l, 0);
-            ring[l][1] = afrag(l, -1);
+        for (int l = 0; l < kWLimbs; ++l) {
+            aC[l] = afrag(l, 0);
+            aP[l] = afrag(l, -1);
         }
+#pragma unroll
+        for (int j = 0; j < kFLimbs; ++j) bC[j] = bfrag(Bst, 0, j);
         const int64_t b0 = (cb.k_lo - 1) / L;
         double fsc = A.Fqs[b0 * A.ldF + col0 + li];
         double fsc_nx = cb.nk > L ? A.Fqs[(b0 + 1) * A.ldF + col0 + li] : 0.0;
-        // [level][tile]: exact sums, flushed into acc64 by the chunk's end
+        // [level][tile]: exact sums, flushed by the chunk's end
         i16v acc[4][MT];
 #pragma unroll
         for (int i = 0; i < MT; ++i)
 #pragma unroll
             for (int l = 0; l < 4; ++l) acc[l][i] = i16v{};
-        const int nstages = cb.nk / kQ32Stage;
         const int nsteps = cb.nk / 32;
         for (int st = 0; st < nstages; ++st) {
-            const int buf = st & 1;
-            const u4* Bs = Bst + buf * kQ32StageU4;
+            const u4* Bs = Bst + (st % kStageBufs) * kQ32StageU4;
+            const u4* Bnext = Bst + ((st + 1) % kStageBufs) * kQ32StageU4;
+            // the copy of stage st + kStageBufs - 1 runs under the K-steps of
+            // the stages before it (its buffer was last read before the
+            // previous stage's closing barrier)
+            const int sa = st + kStageBufs - 1;
+            if (sa < nstages)
+                q32_dma_stage<NTH>(q0, q1, q2, A.ldF, col0, kb16 + (int64_t)sa * (kQ32Stage / 16), t,
+                                   Bst + (sa % kStageBufs) * kQ32StageU4);
 #pragma unroll
             for (int qq = 0; qq < QS; ++qq) {
                 const int q = st * QS + qq;
-                if (q > 0) {
-                    // v = q replaces v = q - 2 (slot q mod 2)
+                const bool more = qq + 1 < QS || st + 1 < nstages;   // step q + 1 exists
+                i4 aN[kWLimbs], bN[kFLimbs];
 #pragma unroll
-                    for (int l = 0; l < RL; ++l) ring[l][qq & 1] = afrag(l, q);
+                for (int l = 0; l < kWLimbs; ++l) aN[l] = more ? afrag(l, q + 1) : aC[l];
+                if (qq + 1 < QS) {
+#pragma unroll
+                    for (int j = 0; j < kFLimbs; ++j) bN[j] = bfrag(Bs, qq + 1, j);
                 }
-                i4 bfr[kFLimbs];
-#pragma unroll
-                for (int j = 0; j < kFLimbs; ++j)
-                    bfr[j] = __builtin_bit_cast(i4, Bs[(j * (kQ32Stage / 16) + 2 * qq + g) * TN + li]);
-                if (qq == QS - 1 && st + 1 < nstages)
-                    q32_dma_stage<NTH>(q0, q1, q2, A.ldF, col0, kb16 + (int64_t)(st + 1) * (kQ32Stage / 16),
-                                       t, Bst + (buf ^ 1) * kQ32StageU4);
                 // digit products (i, j), i + j <= 3, into level i + j, ordered so
                 // that products of one level are at least two apart:
                 // (0,0) (0,1) (0,2) (1,2) (1,0) (1,1) (2,1) (2,0) (3,0)
@@ -252,27 +278,60 @@ __global__ __launch_bounds__(256, 2) void k_far_i8_32(const GroupDev* groups, co
 #pragma unroll
                     for (int tm = 0; tm < MT; ++tm) {
                         const int lv = pw[pp] + ph[pp];
-                        const i4 a = pw[pp] < RL ? ring[pw[pp] < RL ? pw[pp] : 0][(qq - tm + 2) & 1]
-                                                 : afrag(pw[pp], q - tm);
-                        acc[lv][tm] = mfma_i8_32(a, bfr[ph[pp]], acc[lv][tm]);
+                        const i4 a = tm == 0 ? aC[pw[pp]] : aP[pw[pp]];
+                        acc[lv][tm] = mfma_i8_32(a, bC[ph[pp]], acc[lv][tm]);
                     }
+                if (qq + 1 == QS) {
+                    if (more) {
+                        // the next stage's copy is in (later stages' copies,
+                        // issued after it, may still run): its first fragments
+                        if (kStageBufs > 2 && st + kStageBufs - 1 < nstages)
+                            asm volatile("s_waitcnt vmcnt(%0)" ::"n"((kStageBufs - 2) * kDmaPerStage) : "memory");
+                        else
+                            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                        __syncthreads();
+#pragma unroll
+                        for (int j = 0; j < kFLimbs; ++j) bN[j] = bfrag(Bnext, 0, j);
+                    } else {
+#pragma unroll
+                        for (int j = 0; j < kFLimbs; ++j) bN[j] = bC[j];
+                    }
+                }
                 if ((q + 1) % GSTEPS == 0) {
-                    const bool last = q + 1 == nsteps;
+                    const bool last = !more;
                     const double fnx = last ? 0.0 : fsc_nx;
                     if (last || __any(fnx != fsc)) {
                         const double sc = wscale * fsc;
+                        const bool to_out = last && chunk + 1 == c_end;
 #pragma unroll
                         for (int tm = 0; tm < MT; ++tm) {
+                            double2 prev[8];
 #pragma unroll
-                            for (int v = 0; v < 16; ++v) {
-                                double T = fma((double)acc[1][tm][v], 0x1p-8, (double)acc[0][tm][v]);
-                                T = fma((double)acc[2][tm][v], 0x1p-16, T);
-                                T = fma((double)acc[3][tm][v], 0x1p-24, T);
-                                acc64[tm][v] = fma(T, sc, acc64[tm][v]);
+                            for (int vp = 0; vp < 8; ++vp)
+                                prev[vp] = first ? double2{0.0, 0.0} : accs[(tm * 8 + vp) * 64 + lane];
+#pragma unroll
+                            for (int vp = 0; vp < 8; ++vp) {
+                                double r[2];
+#pragma unroll
+                                for (int h = 0; h < 2; ++h) {
+                                    const int v = 2 * vp + h;
+                                    double T = fma((double)acc[1][tm][v], 0x1p-8, (double)acc[0][tm][v]);
+                                    T = fma((double)acc[2][tm][v], 0x1p-16, T);
+                                    T = fma((double)acc[3][tm][v], 0x1p-24, T);
+                                    r[h] = fma(T, sc, h ? prev[vp].y : prev[vp].x);
+                                }
+                                if (to_out) {
+                                    const gptr<double> o = out + tm * 32 + 8 * (vp / 2) + 2 * (vp % 2);
+                                    o[0] = r[0];
+                                    o[1] = r[1];
+                                } else {
+                                    accs[(tm * 8 + vp) * 64 + lane] = double2{r[0], r[1]};
+                                }
                             }
 #pragma unroll
                             for (int l = 0; l < 4; ++l) acc[l][tm] = i16v{};
                         }
+                        first = false;
                     }
                     if (!last) {
                         fsc = fnx;
@@ -280,18 +339,31 @@ __global__ __launch_bounds__(256, 2) void k_far_i8_32(const GroupDev* groups, co
                         if ((q + 1) / GSTEPS + 1 < nsteps / GSTEPS) fsc_nx = A.Fqs[nb * A.ldF + col0 + li];
                     }
                 }
+#pragma unroll
+                for (int l = 0; l < kWLimbs; ++l) {
+                    aP[l] = aC[l];
+                    aC[l] = aN[l];
+                }
+#pragma unroll
+                for (int j = 0; j < kFLimbs; ++j) bC[j] = bN[j];
+                // step q + 1's reads spread over the first products of step q
+#pragma unroll
+                for (int k = 0; k < 11; ++k) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);   // one product
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);   // one LDS read
+                }
+                __builtin_amdgcn_sched_group_barrier(0x008, 7, 0);
+                // keep the scheduler from pulling step q + 1's products up to
+                // the reads that feed them
+                __builtin_amdgcn_sched_barrier(0);
             }
-            asm volatile("s_waitcnt vmcnt(0)" ::"v"(acc[0][0][0]), "v"(acc[0][1][0]) : "memory");
-            __syncthreads();
         }
     }
-    // FFpart[split][col][2L]: row 8(v/4) + 4g + v%4 of column li of tile i in register v
-    const gptr<double> out = A.part + (size_t)blockIdx.y * A.ldP * (2 * L);
+    if (first) {   // no history rows in this split
 #pragma unroll
-    for (int i = 0; i < MT; ++i) {
-        const gptr<double> o = out + (size_t)(col0 + li) * (2 * L) + rowbase + i * 32 + 4 * g;
+        for (int i = 0; i < MT; ++i)
 #pragma unroll
-        for (int v = 0; v < 16; ++v) o[8 * (v / 4) + (v % 4)] = acc64[i][v];
+            for (int v = 0; v < 16; ++v) out[i * 32 + 8 * (v / 4) + (v % 4)] = 0.0;
     }
 }
 
@@ -316,7 +388,9 @@ int far_i8_tile_cols() { return 32; }
 size_t far_i8_lds_bytes(int L, int kchunk)
 {
     const int nk = L >= 256 ? 1 : 2;           // weight windows per workgroup
-    return (size_t)nk * kWLimbs * kCopies * (L + kchunk + kCopyPad) + 2 * (size_t)kQ32StageU4 * 16;
+    constexpr size_t kAccBytes = 4 * 64 * 2 * 16 * sizeof(double);   // 4 waves x 64 lanes x 2 tiles x 16
+    return (size_t)nk * kWLimbs * kCopies * (L + kchunk + kCopyPad) + (size_t)kStageBufs * kQ32StageU4 * 16 +
+           kAccBytes;
 }
 
 hipError_t launch_far_i8(const GroupDev* groups, const FarItem* items, int n, int max_coltiles,
