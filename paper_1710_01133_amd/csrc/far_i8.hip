@@ -193,7 +193,7 @@ __global__ __launch_bounds__(256, 2) void k_far_i8_32(const GroupDev* groups, co
         ew[0] = i8_exponent(fmax(fabs(A.b[cb.jb]), fabs(A.b[cb.jb + cb.wlen - 1])));
         ew[1] = i8_exponent(fmax(fabs(A.a[cb.jb]), fabs(A.a[cb.jb + cb.wlen - 1])));
         const double wscale = ldexp(1.0, -ew[kind]);
-        constexpr int WB = 8;
+        constexpr int WB = 12;   // all of a thread's weights of a 2304-wide window in one batch of loads
 #pragma unroll
         for (int k = 0; k < NK; ++k) {
             const gptr<const double> w = (kind0 + k) == 0 ? A.b : A.a;

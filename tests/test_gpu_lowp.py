@@ -17,10 +17,11 @@ pytestmark = pytest.mark.gpu
 # bits of every operand and meet 1e-6 (measured 6.7e-7, 4.9e-7); fp16x3 keeps
 # about 22 (11 + 11 bits per operand, the lo*lo product dropped): measured
 # 1.1e-6 on its worst member, so its bound is 2e-6; bf16x3 keeps 16 (1.0e-4).
-# i8x9 carries 30 bits of every weight and 22 of the history (relative to
+# i8x9 carries 30 bits of every weight and 21-22 of the history (relative to
 # their window's and block's largest value) and sums its products exactly: a
 # CPU model of its arithmetic put the sweep's worst member near 5e-8, against
-# 3e-7 for the same model of bf16x6, so its bound is 2e-7.
+# 3e-7 for the same model of bf16x6; measured 7.9e-8 over the sweep and 2.25e-7
+# on the LCR case of the mixed test, so its bound is 3e-7.
 BOUND = {"fp32": 1e-6, "bf16x3": 2e-4, "bf16x6": 1e-6, "fp16x3": 2e-6, "i8x9": 3e-7}
 LOWP = ["fp32", "bf16x3", "bf16x6", "fp16x3", "i8x9"]
 
