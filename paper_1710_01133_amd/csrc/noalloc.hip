@@ -31,7 +31,7 @@ constexpr size_t kScratchBytes = (size_t)8 << 20;
 constexpr size_t kStatusOff = 0;
 constexpr size_t kFlagsOff = 256;
 constexpr size_t kPartOff = 1280;
-constexpr size_t kTablesOff = kPartOff + 4 * 256 * 8 * sizeof(double);   // plain_part_doubles(256)
+constexpr size_t kTablesOff = kPartOff + 8 * 256 * 8 * sizeof(double);   // plain_part_doubles(256)
 constexpr int kMaxDevices = 64;
 
 static __device__ __align__(256) unsigned char scratch[kScratchBytes];

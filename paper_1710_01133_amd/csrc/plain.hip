@@ -9,28 +9,31 @@
 //     LDS, so every workgroup holds an equal share of the history at every
 //     step (the paper's static contiguous slices would leave most of them
 //     idle early in the run);
-//   * the all-reduce of Algorithm 1 is pipelined by two steps: during step s
-//     every work thread sums b_{s+1-k} f_k and a_{s+1-k} f_k over its indices
-//     k <= s-1 -- step s+2's sums without their two newest terms, which need
-//     nothing that steps s and s+1 compute; the weights were loaded into
-//     registers during the previous step (they depend only on s - k), so no
-//     global load waits on a step's dependent path;
-//   * meanwhile a fifth wave waits for all G flags of step s (raised right
-//     after step s-2, so they have had a whole step to arrive), adds the G
-//     partials in a fixed order and the two newest terms b_1 f_{s-2} +
-//     b_0 f_{s-1} (a_1 f_{s-2} + a_0 f_{s-1}) from the rows it keeps, and
-//     takes the predictor/corrector update itself, bit-identically in every
-//     workgroup (every process computes the update, as in Algorithm 1); the
-//     owner of index s keeps f_s in its LDS slice;
+//   * the all-reduce of Algorithm 1 is pipelined by kLook = 4 steps: during
+//     step s every work thread sums b_{s+3-k} f_k and a_{s+3-k} f_k over its
+//     indices k <= s-1 -- step s+4's sums without their four newest terms,
+//     which need nothing that steps s .. s+3 compute; the weights were loaded
+//     into registers during the previous step (they depend only on s - k), so
+//     no global load waits on a step's dependent path;
+//   * a fifth wave takes the predictor/corrector update itself,
+//     bit-identically in every workgroup (every process computes the update,
+//     as in Algorithm 1): at step s it adds the G partials of step s in a
+//     fixed order, and the four newest terms b_3 f_{s-4} + .. + b_0 f_{s-1}
+//     (a_j likewise) from the rows it keeps; the owner of index s keeps f_s
+//     in its LDS slice;
+//   * no global round trip sits on a step's path: during step s that wave
+//     checks the G flags of step s+1 (loaded during step s-1; a flag reaches
+//     m after its workgroup's step m-4), then issues the loads of step s+1's
+//     partials, summed at step s+1, and the loads of step s+2's flags;
 //   * one barrier per step; after it work wave 0 reduces the work waves'
 //     partials (DPP row operations, then LDS), publishes the workgroup's 2d
-//     sums of step s+2 and raises its flag to s+2;
+//     sums of step s+4 and raises its flag to s+4;
 //   * with G = 1 there is nothing to publish: the fifth wave reads the work
-//     waves' partials of step s from LDS, written during step s-2.
-// Partial slots (in LDS and in global memory) are kept by step mod 4: a
-// workgroup writes step m's slot after step m-2, when its fifth wave has seen
-// every flag reach m-2; a workgroup raises its flag to m-2 after step m-4,
-// whose reads of the slot that m now reuses came before that.
+//     waves' partials of step s from LDS, written during step s-4.
+// Partial slots (in LDS and in global memory) are kept by step mod kSlots = 8:
+// a workgroup writes step m's slot after its step m-4, having seen at that
+// step every flag reach m-3, i.e. every workgroup past step m-7; the readers
+// of the slot's previous step, m-8, loaded it during their step m-9.
 #include "abm_dev.h"
 #include "abm_kernels.h"
 
@@ -42,6 +45,9 @@ constexpr int kCh = 256;                  // history indices per chunk (= work t
 constexpr int kWorkWaves = kCh / kWave;
 constexpr int kThreads = kCh + kWave;     // + the wave that synchronises and updates
 constexpr int kPartStride = 8;            // doubles per partial slot (2d <= 6 used)
+constexpr int kLook = 4;                  // steps between a slice sum and its use
+constexpr int kSlots = 8;                 // partial slots, by step mod kSlots
+constexpr int kMaxGLanes = 4;             // workgroups per lane of the fifth wave (G <= 256)
 constexpr size_t kPlainLds = 160 * 1024 - 256;   // LDS of one gfx950 CU, less the static flag
 constexpr int kMaxPrefetch = 16;          // register-prefetched (local chunk, weight table) pairs
 
@@ -81,7 +87,7 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
 {
     extern __shared__ double sm[];
     double* Fl = sm;                                   // [nloc][256][D] history slice
-    double* red = sm + (size_t)A.nloc * kCh * D;       // [4][4][2D] work-wave partials by step mod 4
+    double* red = sm + (size_t)A.nloc * kCh * D;       // [kSlots][4][2D] work-wave partials by step mod kSlots
     __shared__ int s_abort;
     constexpr int NW = PC ? D : 1;                     // weight tables in use
     constexpr int NLR = NL > 0 ? NL : 1;
@@ -121,12 +127,11 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
     }
 
     // Step s's history sums in two parts (Algorithm 1's all-reduce pipelined
-    // by two steps): the slice sums over every index but the two newest
-    // (k <= s-3) are computed during step s-2 and published right after it,
-    // so they have a whole step to reach the other workgroups; the two newest
-    // terms, b_1 f_{s-2} + b_0 f_{s-1} (and a_1 f_{s-2} + a_0 f_{s-1}), are
-    // added by the synchronising wave, which holds f_{s-2} and f_{s-1} from its
-    // own (redundant) updates.
+    // by kLook steps): the slice sums over every index but the kLook newest
+    // (k <= s-5) are computed during step s-4 and published right after it;
+    // the kLook newest terms, b_3 f_{s-4} + .. + b_0 f_{s-1} (a_j likewise),
+    // are added by the synchronising wave, which holds f_{s-4} .. f_{s-1} from
+    // its own (redundant) updates.
     // Weights b_{m-k}, a_{m-k} of this thread's indices k for the slice sums
     // of step m+1 (index clamped at 0 where k > m: those are not used).
     double wb[NLR][NW], wa[NLR][NW];
@@ -142,69 +147,114 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
             }
         }
     };
-    // synchronising wave: c_n of the coming step, b_0, b_1, a_0, a_1, and the
-    // two newest history rows f_{s-1}, f_{s-2}
-    double cn[NW], b01[2][NW], a01[2][NW];
-    double Fm1[D], Fm2[D];
+    // synchronising wave: c_n of the coming step, b_0 .. b_3, a_0 .. a_3, the
+    // kLook newest history rows (Fm[j] = f_{s-1-j}), and per lane the loaded
+    // partials (pl, of step s+1) and flags (fl, of step s+2) of workgroups
+    // lane, lane + 64, ..
+    double cn[NW], bn[kLook][NW], an[kLook][NW];
+    double Fm[kLook][D];
+    double pl[kMaxGLanes][2 * D];
+    uint32_t fl[kMaxGLanes];
     if (!sync_wave) {
-        if constexpr (NL > 0) fetch(2);
+        if constexpr (NL > 0) fetch(kLook);
     } else {
 #pragma unroll
         for (int w = 0; w < NW; ++w) {
             cn[w] = cw[w][0];
 #pragma unroll
-            for (int j = 0; j < 2; ++j) {
-                b01[j][w] = bw[w][j];
-                a01[j][w] = aw[w][j];
+            for (int j = 0; j < kLook; ++j) {
+                bn[j][w] = bw[w][j];
+                an[j][w] = aw[w][j];
             }
         }
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            Fm1[i] = F0[i];
-            Fm2[i] = 0.0;
+            Fm[0][i] = F0[i];
+#pragma unroll
+            for (int j = 1; j < kLook; ++j) Fm[j][i] = 0.0;
+        }
+#pragma unroll
+        for (int r = 0; r < kMaxGLanes; ++r) {
+            fl[r] = 0u;
+#pragma unroll
+            for (int j = 0; j < 2 * D; ++j) pl[r][j] = 0.0;
+        }
+        // flags of step kLook + 1, checked at step kLook
+        if (G > 1 && kLook + 1 <= N) {
+#pragma unroll
+            for (int r = 0; r < kMaxGLanes; ++r)
+                if (lane + kWave * r < G) fl[r] = ld_relaxed(&A.flags[lane + kWave * r]);
         }
     }
     __syncthreads();
 
     for (int64_t s = 1; s <= N; ++s) {
         const int64_t n = s - 1;
-        // work-wave partials of step m in LDS slot m mod 4: written during
-        // step m-2, read during step m (a single workgroup) or published
-        // right after step m-2 (several)
+        // work-wave partials of step m in LDS slot m mod kSlots: written
+        // during step m-kLook, read during step m (a single workgroup) or
+        // published right after step m-kLook (several)
         if (sync_wave) {
             double tot[2 * D];
             bool ok = true;
-            if (s <= 2) {
+            if (s <= kLook) {
 #pragma unroll
-                for (int j = 0; j < 2 * D; ++j) tot[j] = 0.0;   // no history before f_{s-2}
+                for (int j = 0; j < 2 * D; ++j) tot[j] = 0.0;   // no history before f_{s-kLook}
             } else if (G == 1) {
-                const double* rr = red + (size_t)(s & 3) * kWorkWaves * 2 * D;
+                const double* rr = red + (size_t)(s % kSlots) * kWorkWaves * 2 * D;
 #pragma unroll
                 for (int j = 0; j < 2 * D; ++j)
                     tot[j] = ((rr[j] + rr[2 * D + j]) + rr[4 * D + j]) + rr[6 * D + j];
             } else {
-                // wait until every workgroup has published step s (after step s-2)
-                for (int q = lane; q < G; q += kWave) {
-                    uint32_t spins = 0;
-                    while (ld_relaxed(&A.flags[q]) < (uint32_t)s) {
-                        if (++spins > A.spin_limit) {
-                            ok = false;
-                            break;
-                        }
-                        spin_pause();
-                    }
-                }
-                // the partials are read with device-coherent loads issued after
-                // every flag load has returned s: each writer's release made its
-                // partials visible before its flag, so no acquire fence (which
-                // would invalidate this XCD's L2 every step) is needed
-                const double* slot_base = A.part + (size_t)(s & 3) * G * kPartStride;
+                // step s's partials, loaded during step s-1, in a fixed order
 #pragma unroll
                 for (int j = 0; j < 2 * D; ++j) {
                     double acc = 0.0;
-                    for (int q = lane; q < G; q += kWave)
-                        acc += ld_relaxed(&slot_base[(size_t)q * kPartStride + j]);
+#pragma unroll
+                    for (int r = 0; r < kMaxGLanes; ++r)
+                        if (lane + kWave * r < G) acc += pl[r][j];
                     tot[j] = wave_sum_dpp(acc);
+                }
+            }
+            if (G > 1 && s + 1 > kLook && s + 1 <= N) {
+                // every workgroup has published step s+1 (after its step
+                // s+1-kLook): checked on the flags loaded during step s-1
+                const uint32_t m1 = (uint32_t)(s + 1);
+#pragma unroll
+                for (int r = 0; r < kMaxGLanes; ++r) {
+                    const int q = lane + kWave * r;
+                    if (q < G) {
+                        uint32_t spins = 0;
+                        while (fl[r] < m1) {
+                            if (++spins > A.spin_limit) {
+                                ok = false;
+                                break;
+                            }
+                            spin_pause();
+                            fl[r] = ld_relaxed(&A.flags[q]);
+                        }
+                    }
+                }
+                // the partials of step s+1 (summed at step s+1), loaded with
+                // device-coherent loads issued after every flag load has
+                // returned s+1: each writer's release made its partials
+                // visible before its flag, so no acquire fence (which would
+                // invalidate this XCD's L2 every step) is needed
+                if (ok) {
+                    const double* slot_base = A.part + (size_t)((s + 1) % kSlots) * G * kPartStride;
+#pragma unroll
+                    for (int r = 0; r < kMaxGLanes; ++r) {
+                        const int q = lane + kWave * r;
+                        if (q < G) {
+#pragma unroll
+                            for (int j = 0; j < 2 * D; ++j) pl[r][j] = ld_relaxed(&slot_base[(size_t)q * kPartStride + j]);
+                        }
+                    }
+                }
+                // the flags of step s+2, checked at step s+1
+                if (s + 2 <= N) {
+#pragma unroll
+                    for (int r = 0; r < kMaxGLanes; ++r)
+                        if (lane + kWave * r < G) fl[r] = ld_relaxed(&A.flags[lane + kWave * r]);
                 }
             }
             if (!ok) {
@@ -219,15 +269,17 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
                     for (int i = 0; i < D; ++i) A.y_out[last * D + i] = __builtin_nan("");
                 }
             } else {
-                // the two newest terms: k = n-1 (b_1, a_1 for k >= 1) and
-                // k = n (b_0, a_0 for k >= 1); the k = 0 corrector term is c_n f_0
+                // the kLook newest terms, oldest first: k = n-j with weights
+                // b_j (k >= 0) and a_j (k >= 1); the k = 0 corrector term is
+                // c_n f_0
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    const int w = PC ? i : 0;
-                    if (n >= 1) tot[i] = fma(b01[1][w], Fm2[i], tot[i]);
-                    tot[i] = fma(b01[0][w], Fm1[i], tot[i]);
-                    if (n >= 2) tot[D + i] = fma(a01[1][w], Fm2[i], tot[D + i]);
-                    if (n >= 1) tot[D + i] = fma(a01[0][w], Fm1[i], tot[D + i]);
+                for (int j = kLook - 1; j >= 0; --j) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        const int w = PC ? i : 0;
+                        if (n >= j) tot[i] = fma(bn[j][w], Fm[j][i], tot[i]);
+                        if (n >= j + 1) tot[D + i] = fma(an[j][w], Fm[j][i], tot[D + i]);
+                    }
                 }
                 // predictor / corrector (eq. abm and the corrector after it),
                 // from the start term x0 (+ t x1 for orders above 1)
@@ -245,8 +297,9 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
                 rhs_eval<R, D>(A.p, td, y, fs);
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
-                    Fm2[i] = Fm1[i];
-                    Fm1[i] = fs[i];
+#pragma unroll
+                    for (int j = kLook - 1; j >= 1; --j) Fm[j][i] = Fm[j - 1][i];
+                    Fm[0][i] = fs[i];
                 }
                 if (s < N) {
 #pragma unroll
@@ -281,10 +334,10 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
                     }
                 }
             }
-        } else if (s + 2 <= N) {
-            // slice sums of step s+2 over this thread's indices k <= s-1:
-            // b_{s+1-k} f_k and, for k >= 1, a_{s+1-k} f_k
-            double* rw = red + (size_t)((s + 2) & 3) * kWorkWaves * 2 * D;
+        } else if (s + kLook <= N) {
+            // slice sums of step s+4 over this thread's indices k <= s-1:
+            // b_{s+3-k} f_k and, for k >= 1, a_{s+3-k} f_k
+            double* rw = red + (size_t)((s + kLook) % kSlots) * kWorkWaves * 2 * D;
             double P[D], C[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) P[i] = C[i] = 0.0;
@@ -302,7 +355,7 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
                         }
                     }
                 }
-                fetch(s + 2);      // in flight while the step is synchronised
+                fetch(s + kLook);      // in flight while the step is synchronised
             } else {
                 for (int l = 0; l < nloc; ++l) {
                     const int64_t k = (int64_t)(g + l * G) * kCh + t;
@@ -311,8 +364,8 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
 #pragma unroll
                     for (int i = 0; i < D; ++i) {
                         const int w = PC ? i : 0;
-                        P[i] = fma(bw[w][s + 1 - k], f[i], P[i]);
-                        C[i] = fma((k >= 1) ? aw[w][s + 1 - k] : 0.0, f[i], C[i]);
+                        P[i] = fma(bw[w][s + kLook - 1 - k], f[i], P[i]);
+                        C[i] = fma((k >= 1) ? aw[w][s + kLook - 1 - k] : 0.0, f[i], C[i]);
                     }
                 }
             }
@@ -326,18 +379,18 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
                 }
             }
         }
-        // f_s is stored and step s+2's work-wave partials are in LDS
+        // f_s is stored and step s+4's work-wave partials are in LDS
         __syncthreads();
         if (s_abort) return;
-        // work wave 0 publishes the workgroup's slice sums of step s+2 and
-        // raises its flag to s+2 (slots by step mod 4)
-        if (G > 1 && t == 0 && s + 2 <= N) {
-            const double* rw = red + (size_t)((s + 2) & 3) * kWorkWaves * 2 * D;
-            double* slot = A.part + ((size_t)((s + 2) & 3) * G + g) * kPartStride;
+        // work wave 0 publishes the workgroup's slice sums of step s+4 and
+        // raises its flag to s+4 (slots by step mod kSlots)
+        if (G > 1 && t == 0 && s + kLook <= N) {
+            const double* rw = red + (size_t)((s + kLook) % kSlots) * kWorkWaves * 2 * D;
+            double* slot = A.part + ((size_t)((s + kLook) % kSlots) * G + g) * kPartStride;
 #pragma unroll
             for (int j = 0; j < 2 * D; ++j)
                 slot[j] = ((rw[j] + rw[2 * D + j]) + rw[4 * D + j]) + rw[6 * D + j];
-            st_release(&A.flags[g], (uint32_t)(s + 2));
+            st_release(&A.flags[g], (uint32_t)(s + kLook));
         }
     }
 }
@@ -345,7 +398,7 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
 template <int R, int D, bool PC, int NL>
 hipError_t launch_plain_nl(const PlainArgs& A, hipStream_t st)
 {
-    const size_t shmem = ((size_t)A.nloc * kCh * D + 4 * kWorkWaves * 2 * D) * sizeof(double);
+    const size_t shmem = ((size_t)A.nloc * kCh * D + kSlots * kWorkWaves * 2 * D) * sizeof(double);
     const void* fn = reinterpret_cast<const void*>(&k_plain<R, D, PC, NL>);
     hipError_t e = allow_lds(fn, shmem);
     if (e != hipSuccess) return e;
@@ -587,14 +640,14 @@ hipError_t launch_single_t(const PlainArgs& A, hipStream_t st)
 int plain_max_local_chunks(int d)
 {
     // the CU's whole LDS (one workgroup per CU): history slice + wave partials
-    return (int)((kPlainLds - 4 * kWorkWaves * 2 * d * sizeof(double)) / ((size_t)kCh * d * sizeof(double)));
+    return (int)((kPlainLds - kSlots * kWorkWaves * 2 * d * sizeof(double)) / ((size_t)kCh * d * sizeof(double)));
 }
 
 int plain_chunk() { return kCh; }
 
 int plain_prefetch_chunks(int tables) { return kMaxPrefetch / tables; }
 
-int plain_part_doubles(int G) { return 4 * G * kPartStride; }
+int plain_part_doubles(int G) { return kSlots * G * kPartStride; }
 
 bool plain_single_fits(int64_t N, int d, int tables)
 {
