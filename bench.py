@@ -65,12 +65,12 @@ def measured_traffic(prec, blocking):
         return None
     with open(path) as f:
         t = json.load(f)
-    e = t.get(prec)
-    if not e or e.get("source_sha") != far_source_sha():
-        return None
-    if e.get("blocking") != [blocking["block_L"], blocking["kchunk"], blocking["max_split"]]:
-        return None
-    return e["bytes_per_launch"]
+    want = [blocking["block_L"], blocking["kchunk"], blocking["max_split"]]
+    entries = t.get(prec) or []
+    for e in entries if isinstance(entries, list) else [entries]:
+        if e.get("source_sha") == far_source_sha() and e.get("blocking") == want:
+            return e["bytes_per_launch"]
+    return None
 
 
 def copy_calibration(torch):

@@ -135,8 +135,9 @@ extern "C" abm_status abm_autotune(abm_ctx* ctx, const abm_problem* probs, int32
         c.block_L = Ls[i];
         (void)T.run(c);
     }
-    // stage 2: split count, stage 3: chunk, at the best so far
-    const int splits[] = {4, 16, 2};
+    // stage 2: split count (fewest partial slices first: a larger count has to
+    // win by the margin), stage 3: chunk, at the best so far
+    const int splits[] = {2, 4, 16};
     for (int sp : splits) {
         const abm_tune_trial* b = T.best();
         if (!b || !in_budget()) break;
