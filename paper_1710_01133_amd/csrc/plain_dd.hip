@@ -144,14 +144,28 @@ __global__ __launch_bounds__(256) void k_weights_dd(double alpha, int64_t n, con
 }
 
 // ------------------------------------------------------------------ f(t, y)
+// sin and cos of the forcing's phase at t (Duffing: omega t, LCR: omega t);
+// zero for the unforced systems
+template <int R>
+__device__ __forceinline__ void forcing_dd(const double* __restrict__ p, dd t, dd* sn, dd* cs)
+{
+    if constexpr (R == ABM_RHS_DUFFING) {
+        dd_sincos(dd_mul_d(t, p[2]), sn, cs);
+    } else if constexpr (R == ABM_RHS_LCR) {
+        dd_sincos(dd_mul_d(t, p[1]), sn, cs);
+    } else {
+        *sn = *cs = dd_make(0.0);
+    }
+}
+
+// f(t, y) with the forcing's sin and cos at t given (one evaluation serves
+// the predictor's and the corrector's right-hand side of a step)
 template <int R, int D>
-__device__ __forceinline__ void rhs_dd(const double* __restrict__ p, dd t, const dd* y, dd* f)
+__device__ __forceinline__ void rhs_dd_sc(const double* __restrict__ p, dd t, dd sn, dd cs, const dd* y, dd* f)
 {
     if constexpr (R == ABM_RHS_LINEAR) {
         f[0] = dd_mul_d(y[0], -p[0]);
     } else if constexpr (R == ABM_RHS_DUFFING) {
-        dd sn, cs;
-        dd_sincos(dd_mul_d(t, p[2]), &sn, &cs);
         f[0] = y[1];
         const dd cube = dd_mul(dd_mul(y[0], y[0]), y[0]);
         f[1] = dd_add(dd_sub(dd_sub(dd_mul_d(y[1], -p[0]), y[0]), cube), dd_mul_d(cs, p[1]));
@@ -170,14 +184,23 @@ __device__ __forceinline__ void rhs_dd(const double* __restrict__ p, dd t, const
             g = dd_add_d(dd_add_d(dd_mul_d(x, p[3]), p[2]), -p[3]);
         else
             g = dd_mul_d(x, p[2]);
-        dd sn, cs;
-        dd_sincos(dd_mul_d(t, p[1]), &sn, &cs);
         f[0] = dd_sub(y[1], g);
         f[1] = dd_add(dd_sub(dd_mul_d(y[1], -p[0]), y[0]), dd_mul_d(sn, p[4]));
     } else if constexpr (R == ABM_RHS_DIAG) {
         f[0] = dd_add_d(dd_mul_d(y[0], -p[0]), p[2]);
         f[1] = dd_add_d(dd_mul_d(y[1], -p[1]), p[3]);
     }
+    (void)t;
+    (void)sn;
+    (void)cs;
+}
+
+template <int R, int D>
+__device__ __forceinline__ void rhs_dd(const double* __restrict__ p, dd t, const dd* y, dd* f)
+{
+    dd sn, cs;
+    forcing_dd<R>(p, t, &sn, &cs);
+    rhs_dd_sc<R, D>(p, t, sn, cs, y, f);
 }
 
 // ------------------------------------------------------------------ reductions
@@ -242,13 +265,15 @@ __device__ __forceinline__ void update_dd(const PlainArgs& A, int64_t s, const d
     dd yP[D], fP[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) yP[i] = dd_add(base[i], dd_mul(ha[i], tot[i]));
-    rhs_dd<R, D>(A.p, td, yP, fP);
+    dd sn, cs;
+    forcing_dd<R>(A.p, td, &sn, &cs);
+    rhs_dd_sc<R, D>(A.p, td, sn, cs, yP, fP);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
         const dd corr = dd_add(dd_add(tot[D + i], dd_mul(cn[PC ? i : 0], F0[i])), dd_div(fP[i], g2[i]));
         y[i] = dd_add(base[i], dd_mul(ha[i], corr));
     }
-    rhs_dd<R, D>(A.p, td, y, fs);
+    rhs_dd_sc<R, D>(A.p, td, sn, cs, y, fs);
 }
 
 // Scalar factors of each component: h^alpha, Gamma(alpha+2), start-term flag.
@@ -412,9 +437,13 @@ constexpr int kCdThreads = kCdCh + kWave;  // + the synchronising wave
 constexpr int kCdPartStride = 16;          // doubles per partial slot (2D pairs, D <= 3)
 constexpr size_t kCdLds = 160 * 1024 - 256;
 
-template <int R, int D, bool PC>
+// NLP > 0 (one weight table, at most NLP local chunks): the weights of the
+// coming step are loaded into registers during the current one, so no global
+// load waits on a step's path; NLP = 0: loaded in the step.
+template <int R, int D, bool PC, int NLP>
 __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
 {
+    static_assert(NLP == 0 || !PC, "prefetched weights: one weight table");
     extern __shared__ double sm[];
     dd* Fl = reinterpret_cast<dd*>(sm);                        // [nloc][256][D] history slice
     dd* red = Fl + (size_t)A.nloc * kCdCh * D;                 // [4][2D] work-wave partials
@@ -442,6 +471,19 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
     }
 #pragma unroll
     for (int w = 0; w < NW; ++w) cn[w] = ld(A.c[w], 0);
+    // prefetched weights b_{nn-k}, a_{nn-k} of this thread's indices k
+    constexpr int NLPR = NLP > 0 ? NLP : 1;
+    dd wbp[NLPR], wap[NLPR];
+    auto fetch = [&](int64_t nn) {
+#pragma unroll
+        for (int l = 0; l < NLP; ++l) {
+            const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
+            const int64_t idx = nn - k < 0 ? 0 : nn - k;
+            wbp[l] = ld(A.b[0], idx);
+            wap[l] = ld(A.a[0], idx);
+        }
+    };
+    if (!sync_wave) fetch(0);
     __syncthreads();
 
     for (int64_t s = 1; s <= N; ++s) {
@@ -450,15 +492,31 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
             dd P[D], C[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) P[i] = C[i] = dd_make(0.0);
-            for (int l = 0; l < nloc; ++l) {
-                const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
-                if (k > n) break;
-                const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
+            if constexpr (NLP > 0) {
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    const int w = PC ? i : 0;
-                    P[i] = dd_fma(ld(A.b[w], n - k), f[i], P[i]);
-                    if (k >= 1) C[i] = dd_fma(ld(A.a[w], n - k), f[i], C[i]);   // k = 0: c_n
+                for (int l = 0; l < NLP; ++l) {
+                    const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
+                    if (l < nloc && k <= n) {
+                        const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            P[i] = dd_fma(wbp[l], f[i], P[i]);
+                            if (k >= 1) C[i] = dd_fma(wap[l], f[i], C[i]);   // k = 0: c_n
+                        }
+                    }
+                }
+                fetch(n + 1);      // in flight while the step is synchronised
+            } else {
+                for (int l = 0; l < nloc; ++l) {
+                    const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
+                    if (k > n) break;
+                    const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        const int w = PC ? i : 0;
+                        P[i] = dd_fma(ld(A.b[w], n - k), f[i], P[i]);
+                        if (k >= 1) C[i] = dd_fma(ld(A.a[w], n - k), f[i], C[i]);   // k = 0: c_n
+                    }
                 }
             }
 #pragma unroll
@@ -499,12 +557,17 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
                         spin_pause();
                     }
                 }
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                // the partials are read with device-coherent loads issued after
+                // every flag load has returned s: each writer's release made its
+                // partials visible before its flag, so no acquire fence (which
+                // would invalidate this XCD's L2 every step) is needed
 #pragma unroll
                 for (int j = 0; j < 2 * D; ++j) {
                     dd acc = dd_make(0.0);
-                    for (int q = lane; q < G; q += kWave)
-                        acc = dd_add(acc, ld(slot_base + (size_t)q * kCdPartStride, j));
+                    for (int q = lane; q < G; q += kWave) {
+                        const double* sl = slot_base + (size_t)q * kCdPartStride;
+                        acc = dd_add(acc, dd{ld_relaxed(&sl[2 * j]), ld_relaxed(&sl[2 * j + 1])});
+                    }
                     tot[j] = wave_sum_dd(acc);
                 }
             }
@@ -579,7 +642,8 @@ hipError_t launch_dd_t(const PlainArgs& A, bool single, hipStream_t st)
         return hipErrorInvalidValue;
     }
     const size_t shmem = ((size_t)A.nloc * kCdCh * D + 4 * 2 * D) * 2 * sizeof(double);
-    const void* fn = reinterpret_cast<const void*>(&k_plain_dd<R, D, PC>);
+    const void* fn = !PC && A.nloc <= 4 ? reinterpret_cast<const void*>(&k_plain_dd<R, D, false, 4>)
+                                        : reinterpret_cast<const void*>(&k_plain_dd<R, D, PC, 0>);
     hipError_t e = allow_lds(fn, shmem);
     if (e != hipSuccess) return e;
     PlainArgs a = A;
