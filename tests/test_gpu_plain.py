@@ -79,6 +79,20 @@ def test_plain_workgroup_counts(ctx, G, N, monkeypatch):
     assert normerr(y, oracle_run(p, 1)) <= TOL_FP64
 
 
+@pytest.mark.parametrize("G", [2, 65])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 9, 12])
+def test_plain_pipeline_start_and_end(ctx, G, N, monkeypatch):
+    """The cooperative kernel's all-reduce runs four steps ahead of the
+    update: runs shorter than twice that cover steps with no published
+    partials, the first published ones and the last; 65 workgroups put two
+    of them on some lanes of the synchronising wave."""
+    monkeypatch.setenv("ABM_PLAIN_G", str(G))
+    p = inputs.duffing_single(N=N)
+    for stride in (1, 0):
+        y = run_plain(ctx, p, stride)
+        assert normerr(y, oracle_run(p, stride)) <= TOL_FP64, (G, N, stride)
+
+
 @pytest.mark.parametrize("G", [1, 2, 7])
 def test_plain_workgroup_counts_per_component_orders(ctx, G, monkeypatch):
     """Two weight tables (incommensurate orders) halve the register prefetch:
