@@ -103,6 +103,19 @@ __host__ __device__ __forceinline__ dd dd_div(dd x, dd y)
     return dd_add_d(fast_two_sum(q1, q2), q3);
 }
 
+// x / y for a double y: q1 = x.hi / y, the remainder x - q1 y exactly
+// (two_prod), q2 = remainder / y (two divisions against dd_div's three; about
+// the same accuracy, a few units of 2^-104)
+__host__ __device__ __forceinline__ dd dd_div_d(dd x, double y)
+{
+    const double q1 = x.hi / y;
+    const dd p = two_prod(q1, y);
+    const dd s = two_sum(x.hi, -p.hi);
+    const double t = (s.lo - p.lo) + x.lo;
+    const double q2 = (s.hi + t) / y;
+    return fast_two_sum(q1, q2);
+}
+
 // acc + w * f
 __host__ __device__ __forceinline__ dd dd_fma(dd w, dd f, dd acc) { return dd_add(acc, dd_mul(w, f)); }
 
@@ -188,8 +201,8 @@ __host__ __device__ inline void dd_sincos(dd x, dd* sn, dd* cs)
     // sin r = r - r^3/3! + ..., cos r = 1 - r^2/2! + ...
     dd ts = r, s = r, tc = dd_make(1.0), c = dd_make(1.0);
     for (int n = 1; n < 30; ++n) {
-        ts = dd_neg(dd_div(dd_mul(ts, r2), dd_make((2.0 * n) * (2.0 * n + 1.0))));
-        tc = dd_neg(dd_div(dd_mul(tc, r2), dd_make((2.0 * n - 1.0) * (2.0 * n))));
+        ts = dd_neg(dd_div_d(dd_mul(ts, r2), (2.0 * n) * (2.0 * n + 1.0)));
+        tc = dd_neg(dd_div_d(dd_mul(tc, r2), (2.0 * n - 1.0) * (2.0 * n)));
         s = dd_add(s, ts);
         c = dd_add(c, tc);
         if (fabs(ts.hi) <= 1e-34 * fabs(s.hi) + 1e-300 && fabs(tc.hi) <= 1e-34) break;
