@@ -12,8 +12,9 @@
 //   * k_plain_single_dd: one workgroup, weights stationary in registers, the
 //     history in LDS (short histories);
 //   * k_plain_dd: G cooperative workgroups, block-cyclic history slices in LDS,
-//     the weights read in the step, one published partial per workgroup and
-//     step, and the update taken redundantly by every workgroup.
+//     one published partial per workgroup and step, the all-reduce pipelined
+//     four steps ahead as in k_plain, and the update taken redundantly by
+//     every workgroup.
 // Tables and outputs are (hi, lo) pairs of doubles.
 #include "abm_dev.h"
 #include "abm_kernels.h"
@@ -434,27 +435,43 @@ __global__ __launch_bounds__(kSdThreads) void k_plain_single_dd(PlainArgs A)
 // ------------------------------------------------------------------ cooperative
 constexpr int kCdCh = 256;                 // history indices per chunk (= work threads)
 constexpr int kCdThreads = kCdCh + kWave;  // + the synchronising wave
+constexpr int kCdWorkWaves = kCdCh / kWave;
 constexpr int kCdPartStride = 16;          // doubles per partial slot (2D pairs, D <= 3)
+constexpr int kCdLook = 4;                 // steps between a slice sum and its use
+constexpr int kCdSlots = 8;                // partial slots, by step mod kCdSlots
+constexpr int kCdGLanes = 4;               // workgroups per lane of the synchronising wave (G <= 256)
 constexpr size_t kCdLds = 160 * 1024 - 256;
 
+// pairs of LDS beside the history slice: the work-wave partials of kCdSlots
+// steps and b_0 .. b_3, a_0 .. a_3 of each weight table
+constexpr size_t cd_extra_pairs(int d, int tables) { return (size_t)kCdSlots * kCdWorkWaves * 2 * d + 2 * kCdLook * tables; }
+
+// As k_plain (plain.hip) with pairs, and the same pipelining of the
+// all-reduce: the slice sums of step s+4 over the indices k <= s-1 are taken
+// during step s and published right after it; the synchronising wave adds
+// the kCdLook newest terms, b_3 f_{s-4} + .. + b_0 f_{s-1} (a_j likewise),
+// from its own updates.  It checks the flags of step s+1 (loaded during step
+// s-1) and loads step s+1's partials during step s, so no global round trip
+// lies on a step's path while every workgroup keeps up.
 // NLP > 0 (one weight table, at most NLP local chunks): the weights of the
-// coming step are loaded into registers during the current one, so no global
-// load waits on a step's path; NLP = 0: loaded in the step.
+// coming step are loaded into registers during the current one; NLP = 0:
+// loaded in the step.
 template <int R, int D, bool PC, int NLP>
 __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
 {
     static_assert(NLP == 0 || !PC, "prefetched weights: one weight table");
+    constexpr int NW = PC ? D : 1;
     extern __shared__ double sm[];
     dd* Fl = reinterpret_cast<dd*>(sm);                        // [nloc][256][D] history slice
-    dd* red = Fl + (size_t)A.nloc * kCdCh * D;                 // [4][2D] work-wave partials
+    dd* red = Fl + (size_t)A.nloc * kCdCh * D;                 // [kCdSlots][4][2D] work-wave partials by step mod kCdSlots
+    dd* wn = red + (size_t)kCdSlots * kCdWorkWaves * 2 * D;    // [kCdLook][NW] b_j, then [kCdLook][NW] a_j
     __shared__ int s_abort;
-    constexpr int NW = PC ? D : 1;
     const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wid = t >> 6;
-    const bool sync_wave = wid == kCdCh / kWave;
+    const bool sync_wave = wid == kCdWorkWaves;
     const int G = A.G, nloc = A.nloc;
     const int64_t N = A.N;
 
-    dd ha[D], g2[D], F0[D], cn[NW];
+    dd ha[D], g2[D], F0[D];
     bool deriv[D];
     factors_dd<D, PC>(A, ha, g2, deriv);
     {
@@ -465,110 +482,129 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
         if (t == 0) s_abort = 0;
         if (sync_wave && lane == 0 && g == 0) {
 #pragma unroll
-            for (int i = 0; i < D; ++i) Fl[i] = F0[i];
+            for (int i = 0; i < D; ++i) Fl[i] = F0[i];       // f_0: chunk 0, local chunk 0, thread 0
             if (A.out_stride > 0) write_out_dd<D>(A, 0, x0);
         }
     }
-#pragma unroll
-    for (int w = 0; w < NW; ++w) cn[w] = ld(A.c[w], 0);
-    // prefetched weights b_{nn-k}, a_{nn-k} of this thread's indices k
+    // weights b_{m-k}, a_{m-k} of this thread's indices k for the slice sums
+    // of step m+1 (index clamped at 0 where k > m: those are not used)
     constexpr int NLPR = NLP > 0 ? NLP : 1;
     dd wbp[NLPR], wap[NLPR];
-    auto fetch = [&](int64_t nn) {
+    auto fetch = [&](int64_t m) {
 #pragma unroll
         for (int l = 0; l < NLP; ++l) {
             const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
-            const int64_t idx = nn - k < 0 ? 0 : nn - k;
+            const int64_t idx = m - k < 0 ? 0 : m - k;
             wbp[l] = ld(A.b[0], idx);
             wap[l] = ld(A.a[0], idx);
         }
     };
-    if (!sync_wave) fetch(0);
+    // synchronising wave: c_n of the coming step, the kCdLook newest history
+    // rows (Fm[j] = f_{s-1-j}), and per lane the loaded partials (pl, of step
+    // s+1) and flags (fl, of step s+2) of workgroups lane, lane + 64, ..
+    dd cn[NW], Fm[kCdLook][D];
+    dd pl[kCdGLanes][2 * D];
+    uint32_t fl[kCdGLanes];
+    if (!sync_wave) {
+        if constexpr (NLP > 0) fetch(kCdLook);
+    } else {
+#pragma unroll
+        for (int w = 0; w < NW; ++w) cn[w] = ld(A.c[w], 0);
+        if (lane < kCdLook * NW) {
+            const int j = lane / NW, w = lane % NW;
+            wn[lane] = ld(A.b[w], j);
+            wn[kCdLook * NW + lane] = ld(A.a[w], j);
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            Fm[0][i] = F0[i];
+#pragma unroll
+            for (int j = 1; j < kCdLook; ++j) Fm[j][i] = dd_make(0.0);
+        }
+#pragma unroll
+        for (int r = 0; r < kCdGLanes; ++r) {
+            fl[r] = 0u;
+#pragma unroll
+            for (int j = 0; j < 2 * D; ++j) pl[r][j] = dd_make(0.0);
+        }
+        // flags of step kCdLook + 1, checked at step kCdLook
+        if (G > 1 && kCdLook + 1 <= N) {
+#pragma unroll
+            for (int r = 0; r < kCdGLanes; ++r)
+                if (lane + kWave * r < G) fl[r] = ld_relaxed(&A.flags[lane + kWave * r]);
+        }
+    }
     __syncthreads();
 
     for (int64_t s = 1; s <= N; ++s) {
         const int64_t n = s - 1;
-        if (!sync_wave) {
-            dd P[D], C[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) P[i] = C[i] = dd_make(0.0);
-            if constexpr (NLP > 0) {
-#pragma unroll
-                for (int l = 0; l < NLP; ++l) {
-                    const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
-                    if (l < nloc && k <= n) {
-                        const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
-#pragma unroll
-                        for (int i = 0; i < D; ++i) {
-                            P[i] = dd_fma(wbp[l], f[i], P[i]);
-                            if (k >= 1) C[i] = dd_fma(wap[l], f[i], C[i]);   // k = 0: c_n
-                        }
-                    }
-                }
-                fetch(n + 1);      // in flight while the step is synchronised
-            } else {
-                for (int l = 0; l < nloc; ++l) {
-                    const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
-                    if (k > n) break;
-                    const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        const int w = PC ? i : 0;
-                        P[i] = dd_fma(ld(A.b[w], n - k), f[i], P[i]);
-                        if (k >= 1) C[i] = dd_fma(ld(A.a[w], n - k), f[i], C[i]);   // k = 0: c_n
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                const dd ps = wave_sum_dd(P[i]);
-                const dd cs = wave_sum_dd(C[i]);
-                if (lane == 0) {
-                    red[wid * 2 * D + i] = ps;
-                    red[wid * 2 * D + D + i] = cs;
-                }
-            }
-        }
-        __syncthreads();
+        // work-wave partials of step m in LDS slot m mod kCdSlots: written
+        // during step m-kCdLook, read during step m (a single workgroup) or
+        // published right after step m-kCdLook (several)
         if (sync_wave) {
             dd tot[2 * D];
-#pragma unroll
-            for (int j = 0; j < 2 * D; ++j)
-                tot[j] = dd_add(dd_add(dd_add(red[j], red[2 * D + j]), red[4 * D + j]), red[6 * D + j]);
             bool ok = true;
-            if (G > 1) {
-                double* slot_base = A.part + (size_t)(s & 1) * G * kCdPartStride;
-                if (lane == 0) {
-                    double* slot = slot_base + (size_t)g * kCdPartStride;
+            if (s <= kCdLook) {
 #pragma unroll
-                    for (int j = 0; j < 2 * D; ++j) {
-                        slot[2 * j] = tot[j].hi;
-                        slot[2 * j + 1] = tot[j].lo;
-                    }
-                    st_release(&A.flags[g], (uint32_t)s);
-                }
-                for (int q = lane; q < G; q += kWave) {
-                    uint32_t spins = 0;
-                    while (ld_relaxed(&A.flags[q]) < (uint32_t)s) {
-                        if (++spins > A.spin_limit) {
-                            ok = false;
-                            break;
-                        }
-                        spin_pause();
-                    }
-                }
-                // the partials are read with device-coherent loads issued after
-                // every flag load has returned s: each writer's release made its
-                // partials visible before its flag, so no acquire fence (which
-                // would invalidate this XCD's L2 every step) is needed
+                for (int j = 0; j < 2 * D; ++j) tot[j] = dd_make(0.0);   // no history before f_{s-kCdLook}
+            } else if (G == 1) {
+                const dd* rr = red + (size_t)(s % kCdSlots) * kCdWorkWaves * 2 * D;
+#pragma unroll
+                for (int j = 0; j < 2 * D; ++j)
+                    tot[j] = dd_add(dd_add(dd_add(rr[j], rr[2 * D + j]), rr[4 * D + j]), rr[6 * D + j]);
+            } else {
+                // step s's partials, loaded during step s-1, in a fixed order
 #pragma unroll
                 for (int j = 0; j < 2 * D; ++j) {
                     dd acc = dd_make(0.0);
-                    for (int q = lane; q < G; q += kWave) {
-                        const double* sl = slot_base + (size_t)q * kCdPartStride;
-                        acc = dd_add(acc, dd{ld_relaxed(&sl[2 * j]), ld_relaxed(&sl[2 * j + 1])});
-                    }
+#pragma unroll
+                    for (int r = 0; r < kCdGLanes; ++r)
+                        if (lane + kWave * r < G) acc = dd_add(acc, pl[r][j]);
                     tot[j] = wave_sum_dd(acc);
+                }
+            }
+            if (G > 1 && s + 1 > kCdLook && s + 1 <= N) {
+                // every workgroup has published step s+1 (after its step
+                // s+1-kCdLook): checked on the flags loaded during step s-1
+                const uint32_t m1 = (uint32_t)(s + 1);
+#pragma unroll
+                for (int r = 0; r < kCdGLanes; ++r) {
+                    const int q = lane + kWave * r;
+                    if (q < G) {
+                        uint32_t spins = 0;
+                        while (fl[r] < m1) {
+                            if (++spins > A.spin_limit) {
+                                ok = false;
+                                break;
+                            }
+                            spin_pause();
+                            fl[r] = ld_relaxed(&A.flags[q]);
+                        }
+                    }
+                }
+                // the partials of step s+1 (summed at step s+1), loaded with
+                // device-coherent loads issued after every flag load has
+                // returned s+1: each writer's release made its partials
+                // visible before its flag, so no acquire fence (which would
+                // invalidate this XCD's L2 every step) is needed
+                if (ok) {
+                    const double* slot_base = A.part + (size_t)((s + 1) % kCdSlots) * G * kCdPartStride;
+#pragma unroll
+                    for (int r = 0; r < kCdGLanes; ++r) {
+                        const int q = lane + kWave * r;
+                        if (q < G) {
+                            const double* sl = slot_base + (size_t)q * kCdPartStride;
+#pragma unroll
+                            for (int j = 0; j < 2 * D; ++j)
+                                pl[r][j] = dd{ld_relaxed(&sl[2 * j]), ld_relaxed(&sl[2 * j + 1])};
+                        }
+                    }
+                }
+                // the flags of step s+2, checked at step s+1
+                if (s + 2 <= N) {
+#pragma unroll
+                    for (int r = 0; r < kCdGLanes; ++r)
+                        if (lane + kWave * r < G) fl[r] = ld_relaxed(&A.flags[lane + kWave * r]);
                 }
             }
             if (!ok) {
@@ -583,8 +619,26 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
                     }
                 }
             } else {
+                // the kCdLook newest terms, oldest first: k = n-j with weights
+                // b_j (k >= 0) and a_j (k >= 1); the k = 0 corrector term is
+                // c_n f_0
+#pragma unroll
+                for (int j = kCdLook - 1; j >= 0; --j) {
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        const int w = PC ? i : 0;
+                        if (n >= j) tot[i] = dd_fma(wn[j * NW + w], Fm[j][i], tot[i]);
+                        if (n >= j + 1) tot[D + i] = dd_fma(wn[(kCdLook + j) * NW + w], Fm[j][i], tot[D + i]);
+                    }
+                }
                 dd y[D], fs[D];
                 update_dd<R, D, PC>(A, s, tot, ha, g2, deriv, cn, F0, y, fs);
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+#pragma unroll
+                    for (int j = kCdLook - 1; j >= 1; --j) Fm[j][i] = Fm[j - 1][i];
+                    Fm[0][i] = fs[i];
+                }
                 if (s < N) {
 #pragma unroll
                     for (int w = 0; w < NW; ++w) cn[w] = ld(A.c[w], s);
@@ -607,9 +661,66 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
                     }
                 }
             }
+        } else if (s + kCdLook <= N) {
+            // slice sums of step s+4 over this thread's indices k <= s-1:
+            // b_{s+3-k} f_k and, for k >= 1, a_{s+3-k} f_k
+            dd* rw = red + (size_t)((s + kCdLook) % kCdSlots) * kCdWorkWaves * 2 * D;
+            dd P[D], C[D];
+#pragma unroll
+            for (int i = 0; i < D; ++i) P[i] = C[i] = dd_make(0.0);
+            if constexpr (NLP > 0) {
+#pragma unroll
+                for (int l = 0; l < NLP; ++l) {
+                    const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
+                    if (l < nloc && k <= n) {
+                        const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            P[i] = dd_fma(wbp[l], f[i], P[i]);
+                            if (k >= 1) C[i] = dd_fma(wap[l], f[i], C[i]);   // k = 0: c_n
+                        }
+                    }
+                }
+                fetch(s + kCdLook);    // in flight while the step is synchronised
+            } else {
+                for (int l = 0; l < nloc; ++l) {
+                    const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
+                    if (k > n) break;               // later local chunks lie further out
+                    const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) {
+                        const int w = PC ? i : 0;
+                        P[i] = dd_fma(ld(A.b[w], s + kCdLook - 1 - k), f[i], P[i]);
+                        if (k >= 1) C[i] = dd_fma(ld(A.a[w], s + kCdLook - 1 - k), f[i], C[i]);   // k = 0: c_n
+                    }
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                const dd ps = wave_sum_dd(P[i]);
+                const dd cs = wave_sum_dd(C[i]);
+                if (lane == 0) {
+                    rw[wid * 2 * D + i] = ps;
+                    rw[wid * 2 * D + D + i] = cs;
+                }
+            }
         }
+        // f_s is stored and step s+4's work-wave partials are in LDS
         __syncthreads();
         if (s_abort) return;
+        // work wave 0 publishes the workgroup's slice sums of step s+4 and
+        // raises its flag to s+4 (slots by step mod kCdSlots)
+        if (G > 1 && t == 0 && s + kCdLook <= N) {
+            const dd* rw = red + (size_t)((s + kCdLook) % kCdSlots) * kCdWorkWaves * 2 * D;
+            double* slot = A.part + ((size_t)((s + kCdLook) % kCdSlots) * G + g) * kCdPartStride;
+#pragma unroll
+            for (int j = 0; j < 2 * D; ++j) {
+                const dd v = dd_add(dd_add(dd_add(rw[j], rw[2 * D + j]), rw[4 * D + j]), rw[6 * D + j]);
+                slot[2 * j] = v.hi;
+                slot[2 * j + 1] = v.lo;
+            }
+            st_release(&A.flags[g], (uint32_t)(s + kCdLook));
+        }
     }
 }
 
@@ -641,7 +752,7 @@ hipError_t launch_dd_t(const PlainArgs& A, bool single, hipStream_t st)
         }
         return hipErrorInvalidValue;
     }
-    const size_t shmem = ((size_t)A.nloc * kCdCh * D + 4 * 2 * D) * 2 * sizeof(double);
+    const size_t shmem = ((size_t)A.nloc * kCdCh * D + cd_extra_pairs(D, PC ? D : 1)) * 2 * sizeof(double);
     const void* fn = !PC && A.nloc <= 4 ? reinterpret_cast<const void*>(&k_plain_dd<R, D, false, 4>)
                                         : reinterpret_cast<const void*>(&k_plain_dd<R, D, PC, 0>);
     hipError_t e = allow_lds(fn, shmem);
@@ -664,10 +775,11 @@ bool plain_dd_single_fits(int64_t N, int d, int tables)
 
 int plain_dd_max_local_chunks(int d)
 {
-    return (int)((kCdLds - 4 * 2 * d * 2 * sizeof(double)) / ((size_t)kCdCh * d * 2 * sizeof(double)));
+    // the largest weight-table count a system of d components can have
+    return (int)((kCdLds - cd_extra_pairs(d, d) * 2 * sizeof(double)) / ((size_t)kCdCh * d * 2 * sizeof(double)));
 }
 
-int plain_dd_part_doubles(int G) { return 2 * G * kCdPartStride; }
+int plain_dd_part_doubles(int G) { return kCdSlots * G * kCdPartStride; }
 
 hipError_t launch_weights_dd(double alpha, int64_t n, double* gam, double* b, double* a, double* c,
                              hipStream_t st)

@@ -119,13 +119,40 @@ def test_dd_small_vs_quad_oracle(ctx, case, N):
         assert e <= TOL_DD, (rhs, N, stride, e)
 
 
-@pytest.mark.parametrize("G", [3, 50])
+@pytest.mark.parametrize("G", [2, 3, 50])
 def test_dd_cooperative_workgroup_counts(ctx, G, monkeypatch):
     """The cooperative double-double kernel at forced workgroup counts (the
-    history of 3000 steps would otherwise run in one workgroup)."""
+    history of 3000 steps would otherwise run in one workgroup): 6 local
+    chunks (weights loaded in the step), 4 (weights prefetched) and 1."""
     monkeypatch.setenv("ABM_PLAIN_G", str(G))
     p = inputs.duffing_single(N=3000, h=1e-2)
     assert err_pairs(run_dd(ctx, p, 1), quad_run(p, 1)) <= TOL_DD
+
+
+@pytest.mark.parametrize("G", [2, 65])
+@pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 9, 12])
+def test_dd_pipeline_start_and_end(ctx, G, N, monkeypatch):
+    """The cooperative kernel's all-reduce runs four steps ahead of the
+    update: runs shorter than twice that cover steps with no published
+    partials, the first published ones and the last; 65 workgroups put two
+    of them on some lanes of the synchronising wave."""
+    monkeypatch.setenv("ABM_PLAIN_G", str(G))
+    p = inputs.duffing_single(N=N, h=1e-2)
+    for stride in (1, 0):
+        assert err_pairs(run_dd(ctx, p, stride), quad_run(p, stride)) <= TOL_DD, (G, N, stride)
+
+
+COOP_CASES = [c for c in CASES if c[0] in ("LORENZ", "DIAG") or c[1] == (0.9, 0.8)]
+
+
+@pytest.mark.parametrize("case", COOP_CASES, ids=["%s-%s" % (c[0], c[1]) for c in COOP_CASES])
+def test_dd_cooperative_systems(ctx, case, monkeypatch):
+    """Three components and per-component orders (a weight table each) in the
+    cooperative kernel: 5 workgroups over 2000 steps."""
+    rhs, alpha, h, x0, pp, x1 = case
+    monkeypatch.setenv("ABM_PLAIN_G", "5")
+    p = inputs.Problem(rhs, alpha, h, 2000, x0, pp, x1=x1)
+    assert err_pairs(run_dd(ctx, p, 1), quad_run(p, 1)) <= TOL_DD, rhs
 
 
 def test_dd_scalar_linear_workload(ctx):
