@@ -61,6 +61,15 @@ __device__ __forceinline__ double dpp_f64(double v)
     return __builtin_bit_cast(double, ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo);
 }
 
+// lane l's value (l the same in every lane)
+__device__ __forceinline__ double readlane_f64(double v, int l)
+{
+    const uint64_t u = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
 // Sum over the 64 lanes of a full wave by DPP row operations in a fixed order
 // (pairs, quads, half rows, rows, then the two row broadcasts that carry the
 // row sums into the last row); every lane gets lane 63's total.
@@ -72,11 +81,27 @@ __device__ __forceinline__ double wave_sum_dpp(double v)
     v += dpp_f64<0x140, 0xF>(v);    // row_mirror
     v += dpp_f64<0x142, 0xA>(v);    // row_bcast:15 into rows 1 and 3
     v += dpp_f64<0x143, 0xC>(v);    // row_bcast:31 into rows 2 and 3
-    const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
-    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+    return readlane_f64(v, 63);
 }
+
+// The forcing depends on t only: the updating wave evaluates it for 64 steps
+// at a time, step s0 + l in lane l (s0 = 1, 65, 129, ..), and a step reads
+// its lane's value (the same expression as one evaluation per step).
+template <int R>
+struct ForceBlock {
+    double v = 0.0;
+    // call with every lane of the wave at each step s = 1, 2, ..
+    __device__ __forceinline__ double step(const double* __restrict__ p, double h, int64_t s, int lane)
+    {
+        if constexpr (R == ABM_RHS_DUFFING || R == ABM_RHS_LCR) {
+            const int j = (int)((s - 1) & 63);
+            if (j == 0) v = forcing<R>(p, (double)(s + lane) * h);
+            return readlane_f64(v, j);
+        } else {
+            return forcing<R>(p, (double)s * h);
+        }
+    }
+};
 
 // PC: the components have orders of their own (a weight table each);
 // otherwise every component uses component 0's table.  NL > 0: at most NL
@@ -155,6 +180,7 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
     double Fm[kLook][D];
     double pl[kMaxGLanes][2 * D];
     uint32_t fl[kMaxGLanes];
+    ForceBlock<R> fb{};
     if (!sync_wave) {
         if constexpr (NL > 0) fetch(kLook);
     } else {
@@ -194,6 +220,7 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
         // during step m-kLook, read during step m (a single workgroup) or
         // published right after step m-kLook (several)
         if (sync_wave) {
+            const double force = fb.step(A.p, A.h, s, lane);   // the forcing at t_s
             double tot[2 * D];
             bool ok = true;
             if (s <= kLook) {
@@ -290,11 +317,11 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
                 double yP[D], fP[D], y[D], fs[D];
 #pragma unroll
                 for (int i = 0; i < D; ++i) yP[i] = base[i] + ha[i] * tot[i];
-                rhs_eval<R, D>(A.p, td, yP, fP);
+                rhs_eval_forced<R, D>(A.p, yP, force, fP);
 #pragma unroll
                 for (int i = 0; i < D; ++i)
                     y[i] = base[i] + ha[i] * ((tot[D + i] + cn[PC ? i : 0] * F0[i]) + fP[i] / g2[i]);
-                rhs_eval<R, D>(A.p, td, y, fs);
+                rhs_eval_forced<R, D>(A.p, y, force, fs);
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
 #pragma unroll
@@ -458,6 +485,7 @@ __global__ __launch_bounds__(single_threads(D, PC)) void k_plain_single(PlainArg
 
     double wb[NJ][NW], wa[NJ][NW];                     // work waves: weights j = u + 960 q
     double ha[D], g2[D], x0[D], x1[D], F0[D], Fn[D], cn[NW], b0[NW], a0[NW];
+    ForceBlock<R> fb{};
     bool deriv[D];
     if (wid == 0) {
 #pragma unroll
@@ -554,11 +582,12 @@ __global__ __launch_bounds__(single_threads(D, PC)) void k_plain_single(PlainArg
             double yP[D], fP[D], y[D], fs[D];
 #pragma unroll
             for (int i = 0; i < D; ++i) yP[i] = base[i] + ha[i] * tot[i];
-            rhs_eval<R, D>(A.p, td, yP, fP);
+            const double force = fb.step(A.p, A.h, s, lane);
+            rhs_eval_forced<R, D>(A.p, yP, force, fP);
 #pragma unroll
             for (int i = 0; i < D; ++i)
                 y[i] = base[i] + ha[i] * ((tot[D + i] + cn[PC ? i : 0] * F0[i]) + fP[i] / g2[i]);
-            rhs_eval<R, D>(A.p, td, y, fs);
+            rhs_eval_forced<R, D>(A.p, y, force, fs);
             if (s < N) {
 #pragma unroll
                 for (int w = 0; w < NW; ++w) cn[w] = A.c[w][s];   // c_n of the next step

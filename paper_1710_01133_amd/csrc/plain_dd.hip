@@ -220,11 +220,12 @@ __device__ __forceinline__ dd dpp_dd(dd v)
     return dd{dpp_f64<CTRL, ROWS>(v.hi), dpp_f64<CTRL, ROWS>(v.lo)};
 }
 
-__device__ __forceinline__ double readlane63(double v)
+// lane l's value (l the same in every lane)
+__device__ __forceinline__ double readlane_d(double v, int l)
 {
     const uint64_t u = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, 63);
-    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), 63);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), l);
     return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
 }
 
@@ -238,10 +239,33 @@ __device__ __forceinline__ dd wave_sum_dd(dd v)
     v = dd_add(v, dpp_dd<0x140, 0xF>(v));
     v = dd_add(v, dpp_dd<0x142, 0xA>(v));
     v = dd_add(v, dpp_dd<0x143, 0xC>(v));
-    return dd{readlane63(v.hi), readlane63(v.lo)};
+    return dd{readlane_d(v.hi, 63), readlane_d(v.lo, 63)};
 }
 
 __device__ __forceinline__ dd ld(const double* t, int64_t k) { return dd{t[2 * k], t[2 * k + 1]}; }
+
+// The forcing depends on t only: the updating wave evaluates it for 64 steps
+// at a time, step s0 + l in lane l (s0 = 1, 65, 129, ..), and a step reads
+// its lane's values; the same operations as one evaluation per step.
+template <int R>
+constexpr bool forced_dd() { return R == ABM_RHS_DUFFING || R == ABM_RHS_LCR; }
+
+template <int R>
+struct ForcingBlock {
+    dd sn, cs;
+    // call with every lane of the wave at each step s = 1, 2, ..
+    __device__ __forceinline__ void step(const PlainArgs& A, int64_t s, int lane, dd* s_sn, dd* s_cs)
+    {
+        if constexpr (forced_dd<R>()) {
+            const int j = (int)((s - 1) & 63);
+            if (j == 0) forcing_dd<R>(A.p, two_prod((double)(s + lane), A.h), &sn, &cs);
+            *s_sn = dd{readlane_d(sn.hi, j), readlane_d(sn.lo, j)};
+            *s_cs = dd{readlane_d(cs.hi, j), readlane_d(cs.lo, j)};
+        } else {
+            *s_sn = *s_cs = dd_make(0.0);
+        }
+    }
+};
 
 // Index of the state written after step s (stride 0: the final state only), or -1.
 __device__ __forceinline__ int64_t out_index(int64_t s, int64_t N, int64_t stride)
@@ -252,11 +276,12 @@ __device__ __forceinline__ int64_t out_index(int64_t s, int64_t N, int64_t strid
 }
 
 // Step s's update (eq. abm and the corrector) from the totals P = tot[0..D),
-// C = tot[D..2D) (every history term but c_n f_0): writes y and f_s.
+// C = tot[D..2D) (every history term but c_n f_0) and the forcing's sin and
+// cos at t_s: writes y and f_s.
 template <int R, int D, bool PC>
 __device__ __forceinline__ void update_dd(const PlainArgs& A, int64_t s, const dd* tot, const dd* ha,
                                           const dd* g2, const bool* deriv, const dd* cn, const dd* F0,
-                                          dd* y, dd* fs)
+                                          dd sn, dd cs, dd* y, dd* fs)
 {
     const dd td = two_prod((double)s, A.h);                 // t_s = s h, exactly
     dd base[D];
@@ -266,8 +291,6 @@ __device__ __forceinline__ void update_dd(const PlainArgs& A, int64_t s, const d
     dd yP[D], fP[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) yP[i] = dd_add(base[i], dd_mul(ha[i], tot[i]));
-    dd sn, cs;
-    forcing_dd<R>(A.p, td, &sn, &cs);
     rhs_dd_sc<R, D>(A.p, td, sn, cs, yP, fP);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
@@ -331,6 +354,7 @@ __global__ __launch_bounds__(kSdThreads) void k_plain_single_dd(PlainArgs A)
     dd wb[NJ][NW], wa[NJ][NW];
     dd ha[D], g2[D], F0[D], Fn[D], cn[NW], b0[NW], a0[NW];
     bool deriv[D];
+    ForcingBlock<R> fb{};
     if (wid == 0) {
         factors_dd<D, PC>(A, ha, g2, deriv);
         dd x0[D];
@@ -409,8 +433,9 @@ __global__ __launch_bounds__(kSdThreads) void k_plain_single_dd(PlainArgs A)
                 tot[i] = dd_fma(b0[PC ? i : 0], Fn[i], tot[i]);
                 if (n >= 1) tot[D + i] = dd_fma(a0[PC ? i : 0], Fn[i], tot[D + i]);
             }
-            dd y[D], fs[D];
-            update_dd<R, D, PC>(A, s, tot, ha, g2, deriv, cn, F0, y, fs);
+            dd y[D], fs[D], sn, cs;
+            fb.step(A, s, lane, &sn, &cs);
+            update_dd<R, D, PC>(A, s, tot, ha, g2, deriv, cn, F0, sn, cs, y, fs);
             if (s < N) {
 #pragma unroll
                 for (int w = 0; w < NW; ++w) cn[w] = ld(A.c[w], s);
@@ -505,6 +530,7 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
     dd cn[NW], Fm[kCdLook][D];
     dd pl[kCdGLanes][2 * D];
     uint32_t fl[kCdGLanes];
+    ForcingBlock<R> fb{};
     if (!sync_wave) {
         if constexpr (NLP > 0) fetch(kCdLook);
     } else {
@@ -542,6 +568,8 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
         // during step m-kCdLook, read during step m (a single workgroup) or
         // published right after step m-kCdLook (several)
         if (sync_wave) {
+            dd sn, cs;                                         // the forcing at t_s
+            fb.step(A, s, lane, &sn, &cs);
             dd tot[2 * D];
             bool ok = true;
             if (s <= kCdLook) {
@@ -632,7 +660,7 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
                     }
                 }
                 dd y[D], fs[D];
-                update_dd<R, D, PC>(A, s, tot, ha, g2, deriv, cn, F0, y, fs);
+                update_dd<R, D, PC>(A, s, tot, ha, g2, deriv, cn, F0, sn, cs, y, fs);
 #pragma unroll
                 for (int i = 0; i < D; ++i) {
 #pragma unroll
