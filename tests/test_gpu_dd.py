@@ -119,17 +119,18 @@ def test_dd_small_vs_quad_oracle(ctx, case, N):
         assert e <= TOL_DD, (rhs, N, stride, e)
 
 
-@pytest.mark.parametrize("G", [2, 3, 50])
+@pytest.mark.parametrize("G", [1, 2, 3, 50])
 def test_dd_cooperative_workgroup_counts(ctx, G, monkeypatch):
     """The cooperative double-double kernel at forced workgroup counts (the
-    history of 3000 steps would otherwise run in one workgroup): 6 local
-    chunks (weights loaded in the step), 4 (weights prefetched) and 1."""
+    history of 3000 steps would otherwise run in one workgroup): 12 local
+    chunks in one workgroup (no flags: the sums come from its own LDS), 6
+    (weights loaded in the step), 4 (weights prefetched) and 1."""
     monkeypatch.setenv("ABM_PLAIN_G", str(G))
     p = inputs.duffing_single(N=3000, h=1e-2)
     assert err_pairs(run_dd(ctx, p, 1), quad_run(p, 1)) <= TOL_DD
 
 
-@pytest.mark.parametrize("G", [2, 65])
+@pytest.mark.parametrize("G", [1, 2, 65])
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 9, 12])
 def test_dd_pipeline_start_and_end(ctx, G, N, monkeypatch):
     """The cooperative kernel's all-reduce runs four steps ahead of the

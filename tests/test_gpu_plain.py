@@ -79,7 +79,7 @@ def test_plain_workgroup_counts(ctx, G, N, monkeypatch):
     assert normerr(y, oracle_run(p, 1)) <= TOL_FP64
 
 
-@pytest.mark.parametrize("G", [2, 65])
+@pytest.mark.parametrize("G", [1, 2, 65])
 @pytest.mark.parametrize("N", [1, 2, 3, 4, 5, 6, 7, 9, 12])
 def test_plain_pipeline_start_and_end(ctx, G, N, monkeypatch):
     """The cooperative kernel's all-reduce runs four steps ahead of the
