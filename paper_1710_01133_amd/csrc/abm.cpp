@@ -474,11 +474,11 @@ abm_status plain_setup_dd(abm_plan_s* pl)
     if (gmin > gcap)
         return fail(ABM_EINVAL, "N=%lld too long for the double-double plain path (history does not "
                     "fit the LDS of %d workgroups)", (long long)p.N, gcap);
-    // seven local chunks per workgroup: fewer workgroups make each step's
-    // sums longer, more give each lane of the synchronising wave more
-    // partials to add (measured: the 200000-step oscillator runs fastest at
-    // 6-8 chunks per workgroup, ~12% faster than at 4)
-    if (G <= 0) G = (int)((nchunks + 6) / 7);
+    // four local chunks per workgroup: the most whose weights the kernel
+    // prefetches into registers (measured on the 200000-step oscillator:
+    // 6.3 us per step at 4 chunks, 7.1-7.3 at 5 to 8 with the weights loaded
+    // in the step)
+    if (G <= 0) G = (int)((nchunks + 3) / 4);
     G = std::min(std::max(G, gmin), gcap);
     pl->plain_single = false;
     pl->plain_G = G;

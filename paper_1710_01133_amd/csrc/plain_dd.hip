@@ -468,16 +468,23 @@ constexpr int kCdGLanes = 4;               // workgroups per lane of the synchro
 constexpr size_t kCdLds = 160 * 1024 - 256;
 
 // pairs of LDS beside the history slice: the work-wave partials of kCdSlots
-// steps and b_0 .. b_3, a_0 .. a_3 of each weight table
-constexpr size_t cd_extra_pairs(int d, int tables) { return (size_t)kCdSlots * kCdWorkWaves * 2 * d + 2 * kCdLook * tables; }
+// steps, b_0 .. b_3, a_0 .. a_3 of each weight table and the gathered totals
+// of two steps
+constexpr size_t cd_extra_pairs(int d, int tables)
+{
+    return (size_t)kCdSlots * kCdWorkWaves * 2 * d + 2 * kCdLook * tables + 2 * 2 * d;
+}
+constexpr int kCdGather = kCdWorkWaves - 1;   // the work wave that also gathers the partials
 
 // As k_plain (plain.hip) with pairs, and the same pipelining of the
 // all-reduce: the slice sums of step s+4 over the indices k <= s-1 are taken
 // during step s and published right after it; the synchronising wave adds
 // the kCdLook newest terms, b_3 f_{s-4} + .. + b_0 f_{s-1} (a_j likewise),
-// from its own updates.  It checks the flags of step s+1 (loaded during step
-// s-1) and loads step s+1's partials during step s, so no global round trip
-// lies on a step's path while every workgroup keeps up.
+// from its own updates and takes the update.  The double-double sum over the
+// workgroups' partials is moved off its path: after its own slice sums, work
+// wave 3 adds up step s+1's partials (loaded during step s-1) into LDS for
+// the synchronising wave's next step, checks the flags of step s+2 (loaded
+// during step s-1), loads step s+2's partials and step s+3's flags.
 // NLP > 0 (one weight table, at most NLP local chunks): the weights of the
 // coming step are loaded into registers during the current one; NLP = 0:
 // loaded in the step.
@@ -490,6 +497,7 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
     dd* Fl = reinterpret_cast<dd*>(sm);                        // [nloc][256][D] history slice
     dd* red = Fl + (size_t)A.nloc * kCdCh * D;                 // [kCdSlots][4][2D] work-wave partials by step mod kCdSlots
     dd* wn = red + (size_t)kCdSlots * kCdWorkWaves * 2 * D;    // [kCdLook][NW] b_j, then [kCdLook][NW] a_j
+    dd* gtot = wn + 2 * kCdLook * NW;                          // [2][2D] gathered totals by step parity
     __shared__ int s_abort;
     const int g = blockIdx.x, t = threadIdx.x, lane = t & 63, wid = t >> 6;
     const bool sync_wave = wid == kCdWorkWaves;
@@ -524,13 +532,19 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
             wap[l] = ld(A.a[0], idx);
         }
     };
-    // synchronising wave: c_n of the coming step, the kCdLook newest history
-    // rows (Fm[j] = f_{s-1-j}), and per lane the loaded partials (pl, of step
-    // s+1) and flags (fl, of step s+2) of workgroups lane, lane + 64, ..
+    // synchronising wave: c_n of the coming step and the kCdLook newest
+    // history rows (Fm[j] = f_{s-1-j}); gathering wave: per lane the loaded
+    // partials (pl) and flags (fl) of workgroups lane, lane + 64, ..
     dd cn[NW], Fm[kCdLook][D];
     dd pl[kCdGLanes][2 * D];
     uint32_t fl[kCdGLanes];
     ForcingBlock<R> fb{};
+#pragma unroll
+    for (int r = 0; r < kCdGLanes; ++r) {
+        fl[r] = 0u;
+#pragma unroll
+        for (int j = 0; j < 2 * D; ++j) pl[r][j] = dd_make(0.0);
+    }
     if (!sync_wave) {
         if constexpr (NLP > 0) fetch(kCdLook);
     } else {
@@ -547,18 +561,6 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
 #pragma unroll
             for (int j = 1; j < kCdLook; ++j) Fm[j][i] = dd_make(0.0);
         }
-#pragma unroll
-        for (int r = 0; r < kCdGLanes; ++r) {
-            fl[r] = 0u;
-#pragma unroll
-            for (int j = 0; j < 2 * D; ++j) pl[r][j] = dd_make(0.0);
-        }
-        // flags of step kCdLook + 1, checked at step kCdLook
-        if (G > 1 && kCdLook + 1 <= N) {
-#pragma unroll
-            for (int r = 0; r < kCdGLanes; ++r)
-                if (lane + kWave * r < G) fl[r] = ld_relaxed(&A.flags[lane + kWave * r]);
-        }
     }
     __syncthreads();
 
@@ -571,7 +573,6 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
             dd sn, cs;                                         // the forcing at t_s
             fb.step(A, s, lane, &sn, &cs);
             dd tot[2 * D];
-            bool ok = true;
             if (s <= kCdLook) {
 #pragma unroll
                 for (int j = 0; j < 2 * D; ++j) tot[j] = dd_make(0.0);   // no history before f_{s-kCdLook}
@@ -581,159 +582,175 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
                 for (int j = 0; j < 2 * D; ++j)
                     tot[j] = dd_add(dd_add(dd_add(rr[j], rr[2 * D + j]), rr[4 * D + j]), rr[6 * D + j]);
             } else {
-                // step s's partials, loaded during step s-1, in a fixed order
+                const dd* gt = gtot + (s & 1) * 2 * D;        // gathered during step s-1
 #pragma unroll
-                for (int j = 0; j < 2 * D; ++j) {
-                    dd acc = dd_make(0.0);
+                for (int j = 0; j < 2 * D; ++j) tot[j] = gt[j];
+            }
+            // the kCdLook newest terms, oldest first: k = n-j with weights
+            // b_j (k >= 0) and a_j (k >= 1); the k = 0 corrector term is
+            // c_n f_0
 #pragma unroll
-                    for (int r = 0; r < kCdGLanes; ++r)
-                        if (lane + kWave * r < G) acc = dd_add(acc, pl[r][j]);
-                    tot[j] = wave_sum_dd(acc);
+            for (int j = kCdLook - 1; j >= 0; --j) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const int w = PC ? i : 0;
+                    if (n >= j) tot[i] = dd_fma(wn[j * NW + w], Fm[j][i], tot[i]);
+                    if (n >= j + 1) tot[D + i] = dd_fma(wn[(kCdLook + j) * NW + w], Fm[j][i], tot[D + i]);
                 }
             }
-            if (G > 1 && s + 1 > kCdLook && s + 1 <= N) {
-                // every workgroup has published step s+1 (after its step
-                // s+1-kCdLook): checked on the flags loaded during step s-1
-                const uint32_t m1 = (uint32_t)(s + 1);
+            dd y[D], fs[D];
+            update_dd<R, D, PC>(A, s, tot, ha, g2, deriv, cn, F0, sn, cs, y, fs);
 #pragma unroll
-                for (int r = 0; r < kCdGLanes; ++r) {
-                    const int q = lane + kWave * r;
-                    if (q < G) {
-                        uint32_t spins = 0;
-                        while (fl[r] < m1) {
-                            if (++spins > A.spin_limit) {
-                                ok = false;
-                                break;
+            for (int i = 0; i < D; ++i) {
+#pragma unroll
+                for (int j = kCdLook - 1; j >= 1; --j) Fm[j][i] = Fm[j - 1][i];
+                Fm[0][i] = fs[i];
+            }
+            if (s < N) {
+#pragma unroll
+                for (int w = 0; w < NW; ++w) cn[w] = ld(A.c[w], s);
+            }
+            if (lane == 0) {
+                if (s < N) {
+                    const int64_t cs = s / kCdCh;
+                    if ((int)(cs % G) == g) {
+                        dd* dst = Fl + ((size_t)(cs / G) * kCdCh + (s % kCdCh)) * D;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) dst[i] = fs[i];
+                    }
+                }
+                if (g == 0) {
+                    bool bad = false;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) bad |= !dd_isfinite(y[i]);
+                    if (bad) raise_status(A.status, kStatusNonFinite);
+                    write_out_dd<D>(A, s, y);
+                }
+            }
+        } else {
+            if (s + kCdLook <= N) {
+                // slice sums of step s+4 over this thread's indices k <= s-1:
+                // b_{s+3-k} f_k and, for k >= 1, a_{s+3-k} f_k
+                dd* rw = red + (size_t)((s + kCdLook) % kCdSlots) * kCdWorkWaves * 2 * D;
+                dd P[D], C[D];
+#pragma unroll
+                for (int i = 0; i < D; ++i) P[i] = C[i] = dd_make(0.0);
+                if constexpr (NLP > 0) {
+#pragma unroll
+                    for (int l = 0; l < NLP; ++l) {
+                        const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
+                        if (l < nloc && k <= n) {
+                            const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
+#pragma unroll
+                            for (int i = 0; i < D; ++i) {
+                                P[i] = dd_fma(wbp[l], f[i], P[i]);
+                                if (k >= 1) C[i] = dd_fma(wap[l], f[i], C[i]);   // k = 0: c_n
                             }
-                            spin_pause();
-                            fl[r] = ld_relaxed(&A.flags[q]);
+                        }
+                    }
+                    fetch(s + kCdLook);    // in flight while the step is synchronised
+                } else {
+                    for (int l = 0; l < nloc; ++l) {
+                        const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
+                        if (k > n) break;               // later local chunks lie further out
+                        const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
+#pragma unroll
+                        for (int i = 0; i < D; ++i) {
+                            const int w = PC ? i : 0;
+                            P[i] = dd_fma(ld(A.b[w], s + kCdLook - 1 - k), f[i], P[i]);
+                            if (k >= 1) C[i] = dd_fma(ld(A.a[w], s + kCdLook - 1 - k), f[i], C[i]);   // k = 0: c_n
                         }
                     }
                 }
-                // the partials of step s+1 (summed at step s+1), loaded with
-                // device-coherent loads issued after every flag load has
-                // returned s+1: each writer's release made its partials
-                // visible before its flag, so no acquire fence (which would
-                // invalidate this XCD's L2 every step) is needed
-                if (ok) {
-                    const double* slot_base = A.part + (size_t)((s + 1) % kCdSlots) * G * kCdPartStride;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    const dd ps = wave_sum_dd(P[i]);
+                    const dd cs = wave_sum_dd(C[i]);
+                    if (lane == 0) {
+                        rw[wid * 2 * D + i] = ps;
+                        rw[wid * 2 * D + D + i] = cs;
+                    }
+                }
+            }
+            if (wid == kCdGather && G > 1) {
+                // step s+1's partials (loaded during step s-1), in a fixed
+                // order, for the synchronising wave's next step
+                if (s + 1 > kCdLook && s + 1 <= N) {
+                    dd* gt = gtot + ((s + 1) & 1) * 2 * D;
+#pragma unroll
+                    for (int j = 0; j < 2 * D; ++j) {
+                        dd acc = dd_make(0.0);
+#pragma unroll
+                        for (int r = 0; r < kCdGLanes; ++r)
+                            if (lane + kWave * r < G) acc = dd_add(acc, pl[r][j]);
+                        acc = wave_sum_dd(acc);
+                        if (lane == 0) gt[j] = acc;
+                    }
+                }
+                bool ok = true;
+                if (s + 2 > kCdLook && s + 2 <= N) {
+                    // every workgroup has published step s+2 (after its step
+                    // s+2-kCdLook): checked on the flags loaded during step s-1
+                    const uint32_t m2 = (uint32_t)(s + 2);
 #pragma unroll
                     for (int r = 0; r < kCdGLanes; ++r) {
                         const int q = lane + kWave * r;
                         if (q < G) {
-                            const double* sl = slot_base + (size_t)q * kCdPartStride;
+                            uint32_t spins = 0;
+                            while (fl[r] < m2) {
+                                if (++spins > A.spin_limit) {
+                                    ok = false;
+                                    break;
+                                }
+                                spin_pause();
+                                fl[r] = ld_relaxed(&A.flags[q]);
+                            }
+                        }
+                    }
+                    // the partials of step s+2, loaded with device-coherent
+                    // loads issued after every flag load has returned s+2:
+                    // each writer's release made its partials visible before
+                    // its flag, so no acquire fence (which would invalidate
+                    // this XCD's L2 every step) is needed
+                    if (ok) {
+                        const double* slot_base = A.part + (size_t)((s + 2) % kCdSlots) * G * kCdPartStride;
 #pragma unroll
-                            for (int j = 0; j < 2 * D; ++j)
-                                pl[r][j] = dd{ld_relaxed(&sl[2 * j]), ld_relaxed(&sl[2 * j + 1])};
+                        for (int r = 0; r < kCdGLanes; ++r) {
+                            const int q = lane + kWave * r;
+                            if (q < G) {
+                                const double* sl = slot_base + (size_t)q * kCdPartStride;
+#pragma unroll
+                                for (int j = 0; j < 2 * D; ++j)
+                                    pl[r][j] = dd{ld_relaxed(&sl[2 * j]), ld_relaxed(&sl[2 * j + 1])};
+                            }
                         }
                     }
                 }
-                // the flags of step s+2, checked at step s+1
-                if (s + 2 <= N) {
+                // the flags of step s+3, checked at step s+1
+                if (s + 3 > kCdLook && s + 3 <= N) {
 #pragma unroll
                     for (int r = 0; r < kCdGLanes; ++r)
                         if (lane + kWave * r < G) fl[r] = ld_relaxed(&A.flags[lane + kWave * r]);
                 }
-            }
-            if (!ok) {
-                raise_status(A.status, kStatusTimeout);
-                s_abort = 1;
-                if (g == 0 && lane == 0) {
-                    const int64_t last = A.out_stride == 0 ? 0 : N / A.out_stride + (N % A.out_stride ? 1 : 0);
+                if (__ballot(!ok) != 0) {
+                    if (lane == 0) {
+                        raise_status(A.status, kStatusTimeout);
+                        s_abort = 1;
+                        // the run is incomplete: its final state reads NaN
+                        if (g == 0) {
+                            const int64_t last = A.out_stride == 0 ? 0 : N / A.out_stride + (N % A.out_stride ? 1 : 0);
 #pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        A.y_out[2 * (last * D + i)] = __builtin_nan("");
-                        A.y_out[2 * (last * D + i) + 1] = __builtin_nan("");
-                    }
-                }
-            } else {
-                // the kCdLook newest terms, oldest first: k = n-j with weights
-                // b_j (k >= 0) and a_j (k >= 1); the k = 0 corrector term is
-                // c_n f_0
-#pragma unroll
-                for (int j = kCdLook - 1; j >= 0; --j) {
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        const int w = PC ? i : 0;
-                        if (n >= j) tot[i] = dd_fma(wn[j * NW + w], Fm[j][i], tot[i]);
-                        if (n >= j + 1) tot[D + i] = dd_fma(wn[(kCdLook + j) * NW + w], Fm[j][i], tot[D + i]);
-                    }
-                }
-                dd y[D], fs[D];
-                update_dd<R, D, PC>(A, s, tot, ha, g2, deriv, cn, F0, sn, cs, y, fs);
-#pragma unroll
-                for (int i = 0; i < D; ++i) {
-#pragma unroll
-                    for (int j = kCdLook - 1; j >= 1; --j) Fm[j][i] = Fm[j - 1][i];
-                    Fm[0][i] = fs[i];
-                }
-                if (s < N) {
-#pragma unroll
-                    for (int w = 0; w < NW; ++w) cn[w] = ld(A.c[w], s);
-                }
-                if (lane == 0) {
-                    if (s < N) {
-                        const int64_t cs = s / kCdCh;
-                        if ((int)(cs % G) == g) {
-                            dd* dst = Fl + ((size_t)(cs / G) * kCdCh + (s % kCdCh)) * D;
-#pragma unroll
-                            for (int i = 0; i < D; ++i) dst[i] = fs[i];
+                            for (int i = 0; i < D; ++i) {
+                                A.y_out[2 * (last * D + i)] = __builtin_nan("");
+                                A.y_out[2 * (last * D + i) + 1] = __builtin_nan("");
+                            }
                         }
                     }
-                    if (g == 0) {
-                        bool bad = false;
-#pragma unroll
-                        for (int i = 0; i < D; ++i) bad |= !dd_isfinite(y[i]);
-                        if (bad) raise_status(A.status, kStatusNonFinite);
-                        write_out_dd<D>(A, s, y);
-                    }
-                }
-            }
-        } else if (s + kCdLook <= N) {
-            // slice sums of step s+4 over this thread's indices k <= s-1:
-            // b_{s+3-k} f_k and, for k >= 1, a_{s+3-k} f_k
-            dd* rw = red + (size_t)((s + kCdLook) % kCdSlots) * kCdWorkWaves * 2 * D;
-            dd P[D], C[D];
-#pragma unroll
-            for (int i = 0; i < D; ++i) P[i] = C[i] = dd_make(0.0);
-            if constexpr (NLP > 0) {
-#pragma unroll
-                for (int l = 0; l < NLP; ++l) {
-                    const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
-                    if (l < nloc && k <= n) {
-                        const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
-#pragma unroll
-                        for (int i = 0; i < D; ++i) {
-                            P[i] = dd_fma(wbp[l], f[i], P[i]);
-                            if (k >= 1) C[i] = dd_fma(wap[l], f[i], C[i]);   // k = 0: c_n
-                        }
-                    }
-                }
-                fetch(s + kCdLook);    // in flight while the step is synchronised
-            } else {
-                for (int l = 0; l < nloc; ++l) {
-                    const int64_t k = (int64_t)(g + l * G) * kCdCh + t;
-                    if (k > n) break;               // later local chunks lie further out
-                    const dd* f = Fl + ((size_t)l * kCdCh + t) * D;
-#pragma unroll
-                    for (int i = 0; i < D; ++i) {
-                        const int w = PC ? i : 0;
-                        P[i] = dd_fma(ld(A.b[w], s + kCdLook - 1 - k), f[i], P[i]);
-                        if (k >= 1) C[i] = dd_fma(ld(A.a[w], s + kCdLook - 1 - k), f[i], C[i]);   // k = 0: c_n
-                    }
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                const dd ps = wave_sum_dd(P[i]);
-                const dd cs = wave_sum_dd(C[i]);
-                if (lane == 0) {
-                    rw[wid * 2 * D + i] = ps;
-                    rw[wid * 2 * D + D + i] = cs;
                 }
             }
         }
-        // f_s is stored and step s+4's work-wave partials are in LDS
+        // f_s is stored, step s+4's work-wave partials and step s+1's
+        // gathered totals are in LDS
         __syncthreads();
         if (s_abort) return;
         // work wave 0 publishes the workgroup's slice sums of step s+4 and
