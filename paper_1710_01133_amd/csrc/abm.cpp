@@ -443,7 +443,11 @@ PlainArgs plain_args(const abm_problem& prob, const PlainTables& T, const PlainS
     A.y_out = y_out;
     A.out_stride = prob.out_stride;
     A.status = status;
-    A.spin_limit = kSpinLimit;
+    // test hooks for the device-side waits' failure path: a smaller bound
+    // and an offset that no flag reaches (every wait then gives up)
+    const int spin = env_int("ABM_SPIN_LIMIT", 0);
+    A.spin_limit = spin > 0 ? (uint32_t)spin : kSpinLimit;
+    A.wait_bias = (uint32_t)std::max(0, env_int("ABM_WAIT_BIAS", 0));
     return A;
 }
 

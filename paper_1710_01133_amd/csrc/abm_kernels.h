@@ -45,6 +45,8 @@ struct PlainArgs {
     int64_t out_stride;
     uint32_t* status;    // device status word (kStatus* bits)
     uint32_t spin_limit; // bound on each device-side wait
+    uint32_t wait_bias;  // added to every awaited step number: 0 (a test hook
+                         // sets it so that no wait can be met)
 };
 int plain_max_local_chunks(int d);
 int plain_chunk();

@@ -245,7 +245,7 @@ __global__ __launch_bounds__(kThreads) void k_plain(PlainArgs A)
             if (G > 1 && s + 1 > kLook && s + 1 <= N) {
                 // every workgroup has published step s+1 (after its step
                 // s+1-kLook): checked on the flags loaded during step s-1
-                const uint32_t m1 = (uint32_t)(s + 1);
+                const uint32_t m1 = (uint32_t)(s + 1) + A.wait_bias;
 #pragma unroll
                 for (int r = 0; r < kMaxGLanes; ++r) {
                     const int q = lane + kWave * r;

@@ -691,7 +691,7 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
                 if (s + 2 > kCdLook && s + 2 <= N) {
                     // every workgroup has published step s+2 (after its step
                     // s+2-kCdLook): checked on the flags loaded during step s-1
-                    const uint32_t m2 = (uint32_t)(s + 2);
+                    const uint32_t m2 = (uint32_t)(s + 2) + A.wait_bias;
 #pragma unroll
                     for (int r = 0; r < kCdGLanes; ++r) {
                         const int q = lane + kWave * r;

@@ -8,6 +8,8 @@
   every result equal to the oracle.
 * Destroying a context with queued and running requests, and a server whose
   arena cannot be allocated, end without touching freed requests.
+* A device-side wait of the cooperative plain kernels that cannot be met
+  (forced from the host) gives up within its bound in every workgroup.
 """
 import threading
 import time
@@ -102,6 +104,41 @@ def test_nonfinite_plain_path_reports_edevice(torch_ready):
         plan.check()
     assert e.value.code == abm.ABM_EDEVICE
     assert not np.isfinite(y.cpu().numpy()).all()
+    plan.close()
+    ctx.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "dd"])
+def test_cooperative_wait_that_cannot_be_met_gives_up(torch_ready, prec, monkeypatch):
+    """The cooperative plain kernels' bounded waits, forced from the host to
+    fail: the ABM_WAIT_BIAS test hook raises every awaited step number by 2^30
+    (no flag reaches it) and ABM_SPIN_LIMIT bounds each wait at 64 polls.
+    Every workgroup gives up and exits, abm_plan_check reports ABM_EDEVICE,
+    the final state reads NaN, and the next solve on the same context (hooks
+    cleared) matches the oracle."""
+    monkeypatch.setenv("ABM_PLAIN_G", "3")
+    monkeypatch.setenv("ABM_SPIN_LIMIT", "64")
+    monkeypatch.setenv("ABM_WAIT_BIAS", str(1 << 30))
+    base = inputs.duffing_single(N=3000, h=1e-2)
+    p = inputs.Problem(base.rhs, base.alpha, base.h, base.N, base.x0, base.p, prec)
+    ctx = abm.Context(0)
+    plan = abm.Plan(ctx, [p], out_stride=0)
+    y = abm.alloc_out(p, 0)
+    abm.solve(plan, p, y)
+    with pytest.raises(abm.AbmError) as e:
+        plan.check()
+    assert e.value.code == abm.ABM_EDEVICE
+    assert np.isnan(y.cpu().numpy()).all()
+    monkeypatch.delenv("ABM_WAIT_BIAS")
+    monkeypatch.delenv("ABM_SPIN_LIMIT")
+    plan.close()
+    plan = abm.Plan(ctx, [p], out_stride=0)
+    abm.solve(plan, p, y)
+    plan.check()
+    out = y.cpu().numpy()
+    if prec == "dd":
+        out = out[..., 0] + out[..., 1]
+    assert normerr(out, oracle_run(base, 0)) <= TOL_FP64
     plan.close()
     ctx.close()
 
