@@ -289,7 +289,7 @@ abm_status abm_poll(abm_ctx *ctx, uint64_t ticket, abm_result *res);
  * cooperative form's step flags and partial sums live in a library-wide
  * device array of 8 MiB that each GPU holds until the process ends.
  * Limit: (distinct orders among the components) * 3 * (N + 2048) * 8 bytes
- * plus 34 KiB must fit those 8 MiB (one order: N <= 346000), and the plain
+ * plus about 130 KiB must fit those 8 MiB (one order: N <= 341952), and the plain
  * path's own limit applies; larger problems return ABM_EINVAL.  Calls on one
  * GPU share the array and keep the last call's contents: calls that overlap
  * on one GPU (different streams or host threads) race and must be serialised

@@ -65,8 +65,16 @@ def test_noalloc_equals_abm_solve_on_calls_in_a_row(ctx, seq):
 
 
 def test_noalloc_refuses_a_problem_larger_than_its_workspace(ctx):
-    p = inputs.Problem("LINEAR", 0.8, 1e-3, 400000, (1.0,), (1.0,))
+    """The stated limit, exactly: with one order the 8 MiB workspace holds
+    N = 341952 steps ((N + 2048) 8-byte weights in three tables, 256-byte
+    aligned, after the status word, the flags and 8 partial slots of 256
+    workgroups); one step more is refused."""
+    p = inputs.Problem("LINEAR", 0.8, 1e-3, 341953, (1.0,), (1.0,))
     y = abm.alloc_out(p, 0)
     with pytest.raises(abm.AbmError) as e:
         abm.solve_noalloc(p, y, 0)
     assert e.value.code == abm.ABM_EINVAL
+    p = inputs.Problem("LINEAR", 0.8, 1e-3, 341952, (1.0,), (1.0,))
+    y = abm.alloc_out(p, 0)
+    abm.solve_noalloc(p, y, 0)
+    assert np.array_equal(y.cpu().numpy(), _plan_solve(ctx, p, 0))
