@@ -481,8 +481,9 @@ abm_status plain_setup_dd(abm_plan_s* pl)
     // four local chunks per workgroup: the most whose weights the kernel
     // prefetches into registers (measured on the 200000-step oscillator:
     // 6.3 us per step at 4 chunks, 7.1-7.3 at 5 to 8 with the weights loaded
-    // in the step)
-    if (G <= 0) G = (int)((nchunks + 3) / 4);
+    // in the step); short histories spread over at least 32 workgroups while
+    // there are chunks for them (8192 steps: 2.39 us per step at 32, 2.55 at 8)
+    if (G <= 0) G = (int)std::max<int64_t>((nchunks + 3) / 4, std::min<int64_t>(nchunks, 32));
     G = std::min(std::max(G, gmin), gcap);
     pl->plain_single = false;
     pl->plain_G = G;
