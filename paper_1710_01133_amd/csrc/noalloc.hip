@@ -97,6 +97,8 @@ extern "C" abm_status abm_solve_noalloc(const abm_problem* prob, double* y_out, 
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
     PlainShape sh{};
     if ((s = plain_shape(*prob, n_cu, &sh)) != ABM_OK) return s;
+    if ((size_t)plain_part_doubles(sh.G) * sizeof(double) > kTablesOff - kPartOff)
+        return fail(ABM_EINVAL, "%d workgroups' partial slots exceed the workspace layout", sh.G);
     unsigned char* base = nullptr;
     if ((s = scratch_of(dev, &base)) != ABM_OK) return s;
     const hipStream_t st = (hipStream_t)hip_stream;
