@@ -1,6 +1,7 @@
 """Host-side checks of the C ABI (no GPU work): the library loads, exports
-every entry point include/abm.h declares, and the binding's struct layouts
-match the header's."""
+every entry point include/abm.h declares, the binding's struct layouts match
+the header's, and invalid problems are refused with ABM_EINVAL before any
+device work."""
 import ctypes
 import os
 import re
@@ -87,3 +88,67 @@ def test_problem_marshalling():
     assert (c.rhs, c.d, c.N, c.out_stride, c.far_prec) == (1, 2, 1234, 7, 0)
     assert list(c.x0)[:2] == [0.1, 0.0] and list(c.p)[:3] == [0.1, 0.3, 1.2]
     assert abm.n_out(10, 0) == 1 and abm.n_out(10, 3) == 5 and abm.n_out(9, 3) == 4
+
+
+def _invalid_problems():
+    """(what, abm_problem) pairs that abm.h's contract refuses with
+    ABM_EINVAL before any device work."""
+    from paper_1710_01133_amd import inputs
+    nan, inf = float("nan"), float("inf")
+
+    def base(**kw):
+        p = inputs.duffing_single(N=kw.pop("N", 1000))
+        c = abm.c_problem(p)
+        for k, v in kw.items():
+            setattr(c, k, v)
+        return c
+
+    out = [("unknown rhs", base(rhs=99)),
+           ("dimension of the rhs", base(d=3)),
+           ("order 0", base(alpha=0.0)),
+           ("order above 2", base(alpha=2.5)),
+           ("order not a number", base(alpha=nan)),
+           ("h = 0", base(h=0.0)),
+           ("h not finite", base(h=inf)),
+           ("N = 0", base(N=0)),
+           ("N above 2^30 (32-bit step flags)", base(N=(1 << 30) + 1)),
+           ("negative output stride", base(out_stride=-1)),
+           ("unknown far_prec", base(far_prec=42))]
+    c = base()
+    c.x0[0] = nan
+    out.append(("x0 not finite", c))
+    c = base()
+    c.p[7] = inf
+    out.append(("p not finite", c))
+    c = base(alpha=1.5)
+    c.x1[1] = nan
+    out.append(("x1 not finite for an order above 1", c))
+    c = base()
+    c.alpha = 0.0
+    c.alphas[0], c.alphas[1] = 0.9, 2.01
+    out.append(("a per-component order above 2", c))
+    return out
+
+
+@pytest.mark.parametrize("what,c", _invalid_problems(), ids=[w for w, _ in _invalid_problems()])
+def test_invalid_problem_refused_before_any_device_work(lib, what, c):
+    """abm_solve_noalloc validates the problem before it touches a device
+    (the output pointer is a host dummy that is never written)."""
+    dummy = ctypes.create_string_buffer(64)
+    st = lib.abm_solve_noalloc(ctypes.byref(c), ctypes.cast(dummy, ctypes.c_void_p), None)
+    assert st == abm.ABM_EINVAL, (what, st)
+    assert lib.abm_last_error(), what
+
+
+def test_noalloc_workspace_bound_checked_on_the_host(lib):
+    """One order and N = 341953 steps need more than the 8 MiB no-allocation
+    workspace (its stated limit is N <= 341952): refused before any device
+    work; a double-double problem is refused there too."""
+    from paper_1710_01133_amd import inputs
+    dummy = ctypes.create_string_buffer(64)
+    c = abm.c_problem(inputs.Problem("LINEAR", 0.8, 1e-3, 341953, (1.0,), (1.0,)))
+    assert lib.abm_solve_noalloc(ctypes.byref(c), ctypes.cast(dummy, ctypes.c_void_p), None) == abm.ABM_EINVAL
+    assert b"workspace" in lib.abm_last_error()
+    c = abm.c_problem(inputs.Problem("LINEAR", 0.8, 1e-3, 1000, (1.0,), (1.0,), "dd"))
+    assert lib.abm_solve_noalloc(ctypes.byref(c), ctypes.cast(dummy, ctypes.c_void_p), None) == abm.ABM_EINVAL
+    assert b"double-double" in lib.abm_last_error()
