@@ -474,7 +474,7 @@ constexpr size_t cd_extra_pairs(int d, int tables)
 {
     return (size_t)kCdSlots * kCdWorkWaves * 2 * d + 2 * kCdLook * tables + 2 * 2 * d;
 }
-constexpr int kCdGather = kCdWorkWaves - 1;   // the work wave that also gathers the partials
+constexpr int kCdGather = kCdWorkWaves - 2;   // work waves 2 and 3 also gather the partials (G <= 64; above, wave 3 alone)
 
 // As k_plain (plain.hip) with pairs, and the same pipelining of the
 // all-reduce: the slice sums of step s+4 over the indices k <= s-1 are taken
@@ -672,13 +672,21 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
                     }
                 }
             }
-            if (wid == kCdGather && G > 1) {
+            // with one workgroup per lane (G <= 64) waves 2 and 3 share the
+            // gathering, the predictor sums (wave 2) and the corrector sums
+            // (wave 3); with more, the flag polls of a second wave cost more
+            // than the halved sums save, and wave 3 gathers both
+            const bool split = G <= kWave;
+            if (G > 1 && (wid == kCdWorkWaves - 1 || (split && wid == kCdGather))) {
+                const int v0 = split ? (wid - kCdGather) * D : 0;   // this wave's first value
+                const int nv = split ? D : 2 * D;                   // and its count
                 // step s+1's partials (loaded during step s-1), in a fixed
                 // order, for the synchronising wave's next step
                 if (s + 1 > kCdLook && s + 1 <= N) {
-                    dd* gt = gtot + ((s + 1) & 1) * 2 * D;
+                    dd* gt = gtot + ((s + 1) & 1) * 2 * D + v0;
 #pragma unroll
                     for (int j = 0; j < 2 * D; ++j) {
+                        if (j >= nv) break;
                         dd acc = dd_make(0.0);
 #pragma unroll
                         for (int r = 0; r < kCdGLanes; ++r)
@@ -718,10 +726,10 @@ __global__ __launch_bounds__(kCdThreads) void k_plain_dd(PlainArgs A)
                         for (int r = 0; r < kCdGLanes; ++r) {
                             const int q = lane + kWave * r;
                             if (q < G) {
-                                const double* sl = slot_base + (size_t)q * kCdPartStride;
+                                const double* sl = slot_base + (size_t)q * kCdPartStride + 2 * v0;
 #pragma unroll
                                 for (int j = 0; j < 2 * D; ++j)
-                                    pl[r][j] = dd{ld_relaxed(&sl[2 * j]), ld_relaxed(&sl[2 * j + 1])};
+                                    if (j < nv) pl[r][j] = dd{ld_relaxed(&sl[2 * j]), ld_relaxed(&sl[2 * j + 1])};
                             }
                         }
                     }
