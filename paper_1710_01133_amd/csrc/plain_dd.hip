@@ -484,7 +484,9 @@ constexpr int kCdGather = kCdWorkWaves - 2;   // work waves 2 and 3 also gather 
 // workgroups' partials is moved off its path: after its own slice sums, work
 // wave 3 adds up step s+1's partials (loaded during step s-1) into LDS for
 // the synchronising wave's next step, checks the flags of step s+2 (loaded
-// during step s-1), loads step s+2's partials and step s+3's flags.
+// during step s-1), loads step s+2's partials and step s+3's flags; with at
+// most 64 workgroups (one per lane) waves 2 and 3 share this, the predictor
+// and the corrector sums.
 // NLP > 0 (one weight table, at most NLP local chunks): the weights of the
 // coming step are loaded into registers during the current one; NLP = 0:
 // loaded in the step.
